@@ -1,0 +1,767 @@
+/*
+ * FP64 CPU oracle of the multi-component lattice Boltzmann model (MCLBM) for
+ * buoyancy-driven flow of a nanosuspension in a differentially heated cavity.
+ *
+ * TEST INFRASTRUCTURE ONLY: used by tests, the smoke check and the CPU
+ * baseline of the benchmark; never by the product path.  Plain two-array
+ * ("AB") layout, unshifted FP64 populations, one plain loop per algorithm
+ * step, OpenMP over rows (which does not change any arithmetic).
+ *
+ * Per time step (Section 2.d):
+ *   S1 moments (Eqs 29-31) -> S2 mixture velocity and mass fraction (Eqs 25,
+ *   32) -> S3 local properties and relaxation times (Eqs 7-11, 22-24) ->
+ *   S4 gradients of the previous step's (phi, theta) -> S5 slip forces
+ *   (Table 1, Eqs 6, 20) -> S6 BGK collision with forcing (Eqs 18, 19,
+ *   26-28) -> S7 streaming and walls (Eqs 34-36) -> S8 keep (phi, theta).
+ *
+ * Readings of passages that are garbled or silent in the paper are marked
+ * "Reading:" where they are used.
+ *
+ * Parity status per part: the equilibrium, forcing, streaming, walls,
+ * conduction limit, drag integrator and Nusselt definition are pinned by
+ * closed forms and invariants in the tests.  The magnitudes of the Brownian,
+ * thermophoretic, Saffman, Magnus/rotation and gravity forces follow the
+ * printed formulas under the stated readings; they are checked only by
+ * scaling laws and limits, their physical values are parity unpinned (the
+ * paper prints no value that could fix them).
+ */
+#include "mclbm_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ---- D2Q9 lattice, Eqs 21 and 28 -------------------------------------- */
+/* Order of Eq 21: rest; theta = 0, 90, 180, 270 deg; then the diagonals at
+ * 45, 135, 225, 315 deg. */
+static const int EX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+static const int EY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+static const int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+static const double WGT[9] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,
+                              1.0 / 9.0,  1.0 / 9.0,  1.0 / 36.0,
+                              1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+
+/* ---- physical constants ------------------------------------------------ */
+static const double KB = 1.380649e-23; /* Boltzmann constant, J/K */
+static const double GRAV = 9.81;       /* m/s^2 */
+static const double PI = 3.14159265358979323846;
+
+/* Table 1 constants. */
+static const double C_S = 1.17, C_T = 2.18, C_M = 1.14; /* thermophoresis */
+static const double K_S = 81.2;                         /* Saffman lift */
+
+/* Wall temperatures of the zero-mean theta = (T - T0)/dT. */
+static const double TH_HOT = 0.5, TH_COLD = -0.5;
+
+typedef struct {
+  double nu_f, alpha_f, R, nu_L, alpha_L, tau_f, H, dx, dt, G_L, grav_L, Ck;
+  double rhoc_ratio, beta_ratio, rho_f0, rho_p0;
+  double s[6]; /* force switches times scales: D, B, T, S, MR, G */
+} Setup;
+
+struct mo_state {
+  mo_config cfg;
+  Setup s;
+  int nx, ny;
+  size_t nn;
+  int64_t t;
+  double *f, *p, *g;    /* [9][nn], populations after streaming */
+  double *fs, *ps, *gs; /* [9][nn], populations after collision */
+  double *phi_prev, *th_prev, *phi_cur, *th_cur;
+  double *snap_ux, *snap_uy, *snap_th;
+};
+
+void mclbm_oracle_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
+int mclbm_oracle_max_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+void mclbm_oracle_config_defaults(mo_config* c) {
+  memset(c, 0, sizeof(*c));
+  c->nx = c->ny = 64;
+  c->Ra = 1e3;
+  c->Pr = 6.2;
+  c->phi0 = 0.01;
+  c->dp = 100e-9;
+  c->tau_f = 0.8;
+  c->dT = 10.0;
+  c->T0 = 300.0;
+  c->force_mask = MO_F_ALL;
+  for (int k = 0; k < 6; ++k) c->force_scale[k] = 1.0;
+  c->phi_perturb_amp = 1e-6;
+  /* Reading: the paper names water and alumina but gives no property
+   * values; a fixed textbook set at 300 K is used. */
+  c->fluid.rho = 997.1;
+  c->fluid.cp = 4179.0;
+  c->fluid.k = 0.613;
+  c->fluid.beta = 2.1e-4;
+  c->fluid.mu = 8.9e-4;
+  c->fluid.d_mol = 0.384e-9;
+  c->particle.rho = 3970.0;
+  c->particle.cp = 765.0;
+  c->particle.k = 40.0;
+  c->particle.beta = 8.5e-6;
+  c->particle.mu = 0.0;
+  c->particle.d_mol = 0.0;
+  c->boundary = MO_CAVITY;
+}
+
+/* ---- setup: lattice units from Ra, Pr, tau_f (Eqs 16, 22) -------------- */
+static int derive_setup(const mo_config* c, Setup* s) {
+  const double N = (double)c->nx; /* hot-to-cold wall distance in nodes */
+  s->nu_f = c->fluid.mu / c->fluid.rho;
+  s->alpha_f = s->nu_f / c->Pr;
+  s->R = c->particle.rho / c->fluid.rho;
+  if (c->tau_f > 0.0) {
+    /* Eq 22 with c = dx/dt = 1, c_s^2 = 1/3: nu = (2 tau - 1)/6 */
+    s->nu_L = (2.0 * c->tau_f - 1.0) / 6.0;
+  } else {
+    /* Reading: automatic viscosity keeps the free-fall velocity
+     * sqrt(Ra nu alpha)/N at or below 0.1 of the lattice sound speed. */
+    const double umax = 0.1 / sqrt(3.0);
+    double nu = 0.1;
+    const double ufree = nu * sqrt(c->Ra / c->Pr) / N;
+    if (ufree > umax) nu = umax * N / sqrt(c->Ra / c->Pr);
+    s->nu_L = nu;
+  }
+  s->tau_f = 3.0 * s->nu_L + 0.5;
+  s->alpha_L = s->nu_L / c->Pr;
+  /* Ra of the base fluid (Eq 16 with base-fluid properties) fixes the
+   * physical height; Ra = 0 (pure conduction) uses a 1 cm cavity. */
+  if (c->Ra > 0.0)
+    s->H = cbrt(c->Ra * s->nu_f * s->alpha_f / (GRAV * c->fluid.beta * c->dT));
+  else
+    s->H = 0.01;
+  s->dx = s->H / N;
+  s->dt = s->nu_L * s->dx * s->dx / s->nu_f;
+  /* g beta dT in lattice units follows from Eq 16 directly. */
+  s->G_L = c->Ra * s->nu_L * s->alpha_L / (N * N * N);
+  s->grav_L = GRAV * s->dt * s->dt / s->dx;
+  /* Eq 10a/10b evaluated at T0.  Reading: the conductivity ratio is taken as
+   * k_p/k_f (the printed k_f/k_p would make the enhancement vanish). */
+  {
+    const double Re = c->fluid.rho * KB * c->T0 /
+                      (3.0 * PI * c->fluid.mu * c->fluid.mu * c->fluid.d_mol);
+    s->Ck = 64.7 * pow(c->fluid.d_mol / c->dp, 0.369) *
+            pow(c->particle.k / c->fluid.k, 0.7476) * pow(c->Pr, 0.995) *
+            pow(Re, 1.2321);
+  }
+  s->rhoc_ratio = (c->particle.rho * c->particle.cp) /
+                  (c->fluid.rho * c->fluid.cp);
+  s->beta_ratio = c->particle.beta / c->fluid.beta;
+  s->rho_f0 = 1.0 - c->phi0;
+  s->rho_p0 = s->R * c->phi0;
+  for (int k = 0; k < 6; ++k)
+    s->s[k] = ((c->force_mask >> k) & 1u) ? c->force_scale[k] : 0.0;
+  return MO_OK;
+}
+
+/* ---- Eq 26/27: second-order equilibrium E_i(a, u) ---------------------- */
+static double equilibrium(int i, double a, double ux, double uy) {
+  const double eu = EX[i] * ux + EY[i] * uy;
+  const double uu = ux * ux + uy * uy;
+  /* c_s^2 = 1/3 */
+  return WGT[i] * a * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
+}
+
+void mclbm_oracle_equilibrium(double a, double ux, double uy, double out[9]) {
+  for (int i = 0; i < 9; ++i) out[i] = equilibrium(i, a, ux, uy);
+}
+
+/* Reading of the forcing term of Eq 18: S_i = W_i e_i.F / c_s^2 so that its
+ * first moment is F (the printed W_i F e_i gives F/3). */
+static double forcing(int i, double Fx, double Fy) {
+  return 3.0 * WGT[i] * (EX[i] * Fx + EY[i] * Fy);
+}
+
+void mclbm_oracle_forcing(double Fx, double Fy, double out[9]) {
+  for (int i = 0; i < 9; ++i) out[i] = forcing(i, Fx, Fy);
+}
+
+/* ---- S3 + S5: properties and forces at one node ------------------------ */
+typedef struct {
+  double rho_f, jx_f, jy_f, rho_p, jx_p, jy_p, theta;
+  double dphi_dx, dphi_dy, dth_dx, dth_dy;
+} NodeIn;
+
+typedef struct {
+  double ux_f, uy_f, ux_p, uy_p, ux_ns, uy_ns;
+  double tau_p, tau_th;
+  double Ffx, Ffy, Fpx, Fpy;
+  double aB[2], aT[2], aS[2], aMR[2], aG[2], D[2];
+  double beta_L, kappa, r_k, r_mu;
+} NodeOut;
+
+static void node_physics(const mo_state* o, const NodeIn* in, NodeOut* r) {
+  const Setup* s = &o->s;
+  const mo_config* c = &o->cfg;
+  memset(r, 0, sizeof(*r));
+
+  /* S1: Eqs 29-30 per component.  Reading: the lattices carry partial
+   * densities, rho_p~ = R phi. */
+  const double rho_f = in->rho_f, rho_p = in->rho_p;
+  const double uxf = in->jx_f / rho_f, uyf = in->jy_f / rho_f;
+  const int empty = !(rho_p > 1e-12);
+  const double uxp = empty ? uxf : in->jx_p / rho_p;
+  const double uyp = empty ? uyf : in->jy_p / rho_p;
+  const double phi = rho_p / s->R;
+
+  /* S2: Eq 32 read as the mass-averaged velocity; Eq 25 mass fraction. */
+  const double rho_m = rho_f + rho_p;
+  const double uxn = (in->jx_f + in->jx_p) / rho_m;
+  const double uyn = (in->jy_f + in->jy_p) / rho_m;
+  const double rbar_p = rho_p / rho_m;
+
+  /* S3: Eqs 7-11 as ratios to the base fluid. */
+  const double phic = phi > 0.0 ? phi : 0.0;
+  const double r_rho = 1.0 + phi * (s->R - 1.0);                /* Eq 7 */
+  const double r_rhoc = 1.0 + phi * (s->rhoc_ratio - 1.0);      /* Eq 8 */
+  const double r_beta = 1.0 + phi * (s->beta_ratio - 1.0);      /* Eq 9 */
+  const double r_k = 1.0 + s->Ck * pow(phic, 0.764);            /* Eq 10a */
+  const double r_mu = 1.0 + 4.93 * phi + 222.4 * phi * phi;     /* Eq 11 */
+  /* Eq 23 solved for the particle relaxation time, nu_ns from Eq 11/7. */
+  const double nu_ns = s->nu_L * r_mu / r_rho;
+  double tau_p;
+  if (rbar_p <= 1e-12) {
+    tau_p = s->tau_f;
+  } else {
+    tau_p = (3.0 * nu_ns + 0.5 - (1.0 - rbar_p) * s->tau_f) / rbar_p;
+    if (tau_p < 0.505) tau_p = 0.505;
+    if (tau_p > 5.0) tau_p = 5.0;
+  }
+  /* Eq 24 with one thermal lattice for the suspension: alpha_ns =
+   * alpha_f k_ns/k_f / ((rho cp)_ns/(rho cp)_f). */
+  const double tau_th = 3.0 * s->alpha_L * r_k / r_rhoc + 0.5;
+
+  /* S5: slip forces of Table 1, evaluated in SI units and converted.
+   * Reading: each force is the force on one particle; the force density on
+   * the particle lattice is n_p F = rho_p~ F/m_p (Eq 4 per mixture volume),
+   * so every term below is an acceleration per particle mass. */
+  const double vel = s->dx / s->dt;          /* lattice -> SI velocity */
+  const double acc = s->dt * s->dt / s->dx;  /* SI -> lattice acceleration */
+  const double d = c->dp;
+  const double Vp = PI * d * d * d / 6.0, Ap = PI * d * d;
+  const double mp = c->particle.rho * Vp;
+  const double mu_ns = c->fluid.mu * r_mu;
+  const double rho_ns = c->fluid.rho * r_rho;
+  const double T = c->T0 + c->dT * in->theta;
+
+  /* slip velocity w = v_f - v_p and its +90 degree rotation */
+  const double wx = uxf - uxp, wy = uyf - uyp;
+  const double wn = sqrt(wx * wx + wy * wy);
+  const double wpx = wn > 0.0 ? -wy / wn : 0.0;
+  const double wpy = wn > 0.0 ? wx / wn : 0.0;
+  const double up_si = sqrt(uxp * uxp + uyp * uyp) * vel;
+  /* shear rate of Table 1 (Saffman row): 8 v_p / H */
+  const double gdot = 8.0 * up_si / s->H;
+
+  double aB[2] = {0, 0}, aT[2] = {0, 0}, aS[2] = {0, 0};
+  double aMR[2] = {0, 0}, aG[2] = {0, 0}, D[2] = {0, 0};
+  double beta_L = 0.0, kappa = 0.0;
+  double Fpx = 0.0, Fpy = 0.0, Ffx, Ffy;
+
+  /* buoyancy on the fluid lattice (Eq 20), Boussinesq with beta_ns (Eq 9) */
+  Ffx = c->body_force[0];
+  Ffy = c->body_force[1] + rho_m * r_beta * s->G_L * in->theta;
+
+  if (s->s[5] != 0.0) {
+    /* Reading: the settling force of Table 1 (particles) is referenced to
+     * the uniform initial suspension; the fluid carries the opposite
+     * uniform weight so that the mixture feels only (phi - phi0). */
+    Ffy += s->s[5] * s->rho_p0 * (1.0 - 1.0 / s->R) * s->grav_L;
+  }
+
+  if (!empty) {
+    /* Brownian (Table 1).  Reading: directed down the concentration
+     * gradient. */
+    if (s->s[1] != 0.0) {
+      const double DB = 2.0 * KB * T / (3.0 * PI * mu_ns * d);
+      const double vB = 2.0 * KB * T / (PI * mu_ns * d * d);
+      const double coef = c->particle.rho * DB * Ap * vB / mp; /* per grad */
+      aB[0] = -s->s[1] * coef * (in->dphi_dx / s->dx) * acc;
+      aB[1] = -s->s[1] * coef * (in->dphi_dy / s->dx) * acc;
+    }
+    /* Thermophoresis (Table 1).  Reading: F_T = mu_ns d_p v_T (a force),
+     * with v_T as printed; directed down the temperature gradient. */
+    if (s->s[2] != 0.0) {
+      const double kstar = c->fluid.k * r_k / c->particle.k;
+      const double Kn = c->fluid.d_mol / d;
+      const double CT = 6.0 * PI * C_S * (kstar + C_T * Kn) /
+                        ((1.0 + 3.0 * C_M * Kn) *
+                         (1.0 + 2.0 * kstar + 2.0 * C_T * Kn));
+      const double gTx = c->dT * in->dth_dx / s->dx; /* K/m */
+      const double gTy = c->dT * in->dth_dy / s->dx;
+      const double vTx = CT * (mu_ns / rho_ns) * gTx / T;
+      const double vTy = CT * (mu_ns / rho_ns) * gTy / T;
+      aT[0] = -s->s[2] * mu_ns * d * vTx / mp * acc;
+      aT[1] = -s->s[2] * mu_ns * d * vTy / mp * acc;
+    }
+    /* Saffman lift (Table 1).  Reading: square root on (rho gdot / mu),
+     * directed along the rotated slip. */
+    if (s->s[3] != 0.0) {
+      const double FS = (K_S / 4.0) * mu_ns * (wn * vel) * d * d *
+                        sqrt(rho_ns * gdot / mu_ns);
+      aS[0] = s->s[3] * FS / mp * wpx * acc;
+      aS[1] = s->s[3] * FS / mp * wpy * acc;
+    }
+    /* Magnus + particle rotation (Table 1).  Reading: v_M = (v_f + v_p)/2,
+     * mass rate m_p |v_M| / d_p from tau_M = d_p / v_M of Table 2; the
+     * rotation term times the particle area, along the rotated slip. */
+    if (s->s[4] != 0.0) {
+      const double vMx = 0.5 * (uxf + uxp) * vel, vMy = 0.5 * (uyf + uyp) * vel;
+      const double vMn = sqrt(vMx * vMx + vMy * vMy);
+      const double mdot = mp * vMn / d;
+      const double FMx = mdot * (uxp * vel - vMx);
+      const double FMy = mdot * (uyp * vel - vMy);
+      const double FR = mu_ns * c->particle.rho * gdot / rho_ns * Ap;
+      aMR[0] = s->s[4] * (FMx + FR * wpx) / mp * acc;
+      aMR[1] = s->s[4] * (FMy + FR * wpy) / mp * acc;
+    }
+    /* Gravity (Table 1): F_G = -V_p (rho_p - rho_f) g */
+    if (s->s[5] != 0.0) {
+      aG[1] = -s->s[5] * Vp * (c->particle.rho - c->fluid.rho) * GRAV / mp *
+              acc;
+    }
+    const double aIx = aB[0] + aT[0] + aS[0] + aMR[0];
+    const double aIy = aB[1] + aT[1] + aS[1] + aMR[1];
+    /* Reading: the interaction forces act on the fluid as reactions
+     * (Eq 20 extended from drag and Brownian to every particle-fluid
+     * interaction); gravity is external. */
+    Ffx -= rho_p * aIx;
+    Ffy -= rho_p * aIy;
+    Fpx = rho_p * (aIx + aG[0]);
+    Fpy = rho_p * (aIy + aG[1]);
+    /* Drag (Table 1): F_D = beta m_p (v_f - v_p) on the particles,
+     * beta = 18 mu C_d Re_d / (24 rho_p d^2) with Schiller-Naumann C_d.
+     * Reading: beta dt ~ 1e4 makes explicit forcing unstable, so the
+     * coupled two-phase relative-velocity equation dw/dt = a_rel - kappa w
+     * is integrated exactly over the step and the mean drag is applied. */
+    if (s->s[0] != 0.0) {
+      const double Red = c->particle.rho * d * (wn * vel) / mu_ns;
+      const double beta = 18.0 * mu_ns * (1.0 + 0.15 * pow(Red, 0.687)) /
+                          (c->particle.rho * d * d);
+      beta_L = s->s[0] * beta * s->dt;
+      kappa = beta_L * (1.0 + rho_p / rho_f);
+      const double arx = Ffx / rho_f - Fpx / rho_p;
+      const double ary = Ffy / rho_f - Fpy / rho_p;
+      /* mean of w over the step: w_inf + (w - w_inf)(1 - e^-k)/k with
+       * w_inf = a_rel / kappa */
+      const double ph1 = -expm1(-kappa) / kappa;
+      double ph2; /* (1 - ph1)/kappa, series for small kappa */
+      if (kappa < 1e-4)
+        ph2 = 0.5 - kappa / 6.0 + kappa * kappa / 24.0;
+      else
+        ph2 = (1.0 - ph1) / kappa;
+      const double wmx = wx * ph1 + arx * ph2;
+      const double wmy = wy * ph1 + ary * ph2;
+      D[0] = rho_p * beta_L * wmx;
+      D[1] = rho_p * beta_L * wmy;
+      Fpx += D[0];
+      Fpy += D[1];
+      Ffx -= D[0];
+      Ffy -= D[1];
+    }
+  }
+
+  r->ux_f = uxf; r->uy_f = uyf; r->ux_p = uxp; r->uy_p = uyp;
+  r->ux_ns = uxn; r->uy_ns = uyn;
+  r->tau_p = tau_p; r->tau_th = tau_th;
+  r->Ffx = Ffx; r->Ffy = Ffy; r->Fpx = Fpx; r->Fpy = Fpy;
+  memcpy(r->aB, aB, sizeof aB); memcpy(r->aT, aT, sizeof aT);
+  memcpy(r->aS, aS, sizeof aS); memcpy(r->aMR, aMR, sizeof aMR);
+  memcpy(r->aG, aG, sizeof aG); memcpy(r->D, D, sizeof D);
+  r->beta_L = beta_L; r->kappa = kappa; r->r_k = r_k; r->r_mu = r_mu;
+}
+
+/* ---- S4 helpers: previous-step fields with wall ghosts ----------------- */
+static int wrap(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
+
+static double phi_at(const mo_state* o, int x, int y) {
+  const int nx = o->nx, ny = o->ny, b = o->cfg.boundary;
+  if (b != MO_CAVITY) x = wrap(x, nx);
+  if (b == MO_PERIODIC) y = wrap(y, ny);
+  /* zero-flux walls: mirror ghost */
+  if (x < 0) x = 0;
+  if (x >= nx) x = nx - 1;
+  if (y < 0) y = 0;
+  if (y >= ny) y = ny - 1;
+  return o->phi_prev[(size_t)y * nx + x];
+}
+
+static double theta_at(const mo_state* o, int x, int y) {
+  const int nx = o->nx, ny = o->ny, b = o->cfg.boundary;
+  if (b != MO_CAVITY) x = wrap(x, nx);
+  if (b == MO_PERIODIC) y = wrap(y, ny);
+  if (y < 0) y = 0;          /* adiabatic: mirror */
+  if (y >= ny) y = ny - 1;
+  /* isothermal: linear ghost through the wall value at half a spacing */
+  if (x < 0) return 2.0 * TH_HOT - o->th_prev[(size_t)y * nx + 0];
+  if (x >= nx) return 2.0 * TH_COLD - o->th_prev[(size_t)y * nx + nx - 1];
+  return o->th_prev[(size_t)y * nx + x];
+}
+
+/* ---- create / destroy -------------------------------------------------- */
+static void free_state(mo_state* o) {
+  if (!o) return;
+  free(o->f); free(o->p); free(o->g);
+  free(o->fs); free(o->ps); free(o->gs);
+  free(o->phi_prev); free(o->th_prev); free(o->phi_cur); free(o->th_cur);
+  free(o->snap_ux); free(o->snap_uy); free(o->snap_th);
+  free(o);
+}
+
+void mclbm_oracle_destroy(mo_state* o) { free_state(o); }
+
+static void node_moments(const mo_state* o, size_t n, double* rho_f,
+                         double* jxf, double* jyf, double* rho_p, double* jxp,
+                         double* jyp, double* th) {
+  const size_t nn = o->nn;
+  double a = 0, bx = 0, by = 0, c = 0, cx = 0, cy = 0, t = 0;
+  for (int i = 0; i < 9; ++i) {
+    const double fi = o->f[i * nn + n], pi = o->p[i * nn + n];
+    a += fi; bx += fi * EX[i]; by += fi * EY[i];
+    c += pi; cx += pi * EX[i]; cy += pi * EY[i];
+    t += o->g[i * nn + n];
+  }
+  *rho_f = a; *jxf = bx; *jyf = by; *rho_p = c; *jxp = cx; *jyp = cy; *th = t;
+}
+
+int mclbm_oracle_create(const mo_config* cfg, const double* xi,
+                        mo_state** out) {
+  if (!cfg || !out) return MO_EINVAL;
+  *out = NULL;
+  if (cfg->nx < 4 || cfg->ny < 4) return MO_EINVAL;
+  if (!(cfg->Ra >= 0.0) || !(cfg->Pr > 0.0) || !(cfg->phi0 >= 0.0) ||
+      !(cfg->phi0 <= 0.1) || !(cfg->dp > 0.0))
+    return MO_EINVAL;
+  if (cfg->tau_f > 0.0 && !(cfg->tau_f > 0.5)) return MO_EINVAL;
+  mo_state* o = (mo_state*)calloc(1, sizeof(mo_state));
+  if (!o) return MO_ENOMEM;
+  o->cfg = *cfg;
+  o->nx = cfg->nx;
+  o->ny = cfg->ny;
+  o->nn = (size_t)cfg->nx * (size_t)cfg->ny;
+  derive_setup(cfg, &o->s);
+  const size_t nn = o->nn;
+  o->f = malloc(9 * nn * sizeof(double));
+  o->p = malloc(9 * nn * sizeof(double));
+  o->g = malloc(9 * nn * sizeof(double));
+  o->fs = malloc(9 * nn * sizeof(double));
+  o->ps = malloc(9 * nn * sizeof(double));
+  o->gs = malloc(9 * nn * sizeof(double));
+  o->phi_prev = malloc(nn * sizeof(double));
+  o->th_prev = malloc(nn * sizeof(double));
+  o->phi_cur = malloc(nn * sizeof(double));
+  o->th_cur = malloc(nn * sizeof(double));
+  o->snap_ux = malloc(nn * sizeof(double));
+  o->snap_uy = malloc(nn * sizeof(double));
+  o->snap_th = malloc(nn * sizeof(double));
+  if (!o->f || !o->p || !o->g || !o->fs || !o->ps || !o->gs || !o->phi_prev ||
+      !o->th_prev || !o->phi_cur || !o->th_cur || !o->snap_ux ||
+      !o->snap_uy || !o->snap_th) {
+    free_state(o);
+    return MO_ENOMEM;
+  }
+  /* Initial state: equilibrium at the initial velocities (zero in the
+   * cavity), rho_f~ = 1 - phi0, rho_p~ = R phi(x), theta = 0. */
+  for (size_t n = 0; n < nn; ++n) {
+    double phi = cfg->phi0;
+    if (xi) phi += cfg->phi_perturb_amp * xi[n];
+    if (phi < 0.0) phi = 0.0;
+    const double rf = o->s.rho_f0, rp = o->s.R * phi;
+    for (int i = 0; i < 9; ++i) {
+      o->f[i * nn + n] = equilibrium(i, rf, cfg->u_f_init[0], cfg->u_f_init[1]);
+      o->p[i * nn + n] = equilibrium(i, rp, cfg->u_p_init[0], cfg->u_p_init[1]);
+      o->g[i * nn + n] = 0.0;
+    }
+  }
+  for (size_t n = 0; n < nn; ++n) {
+    double rf, jxf, jyf, rp, jxp, jyp, th;
+    node_moments(o, n, &rf, &jxf, &jyf, &rp, &jxp, &jyp, &th);
+    o->phi_prev[n] = rp / o->s.R;
+    o->th_prev[n] = th;
+    o->snap_ux[n] = (jxf + jxp) / (rf + rp);
+    o->snap_uy[n] = (jyf + jyp) / (rf + rp);
+    o->snap_th[n] = th;
+  }
+  o->t = 0;
+  *out = o;
+  return MO_OK;
+}
+
+int64_t mclbm_oracle_time(const mo_state* o) { return o ? o->t : -1; }
+
+/* ---- one time step ----------------------------------------------------- */
+static void collide_all(mo_state* o) {
+  const int nx = o->nx, ny = o->ny;
+  const size_t nn = o->nn;
+  const double tau_f = o->s.tau_f;
+#pragma omp parallel for schedule(static)
+  for (int y = 0; y < ny; ++y) {
+    for (int x = 0; x < nx; ++x) {
+      const size_t n = (size_t)y * nx + x;
+      NodeIn in;
+      /* S1 */
+      node_moments(o, n, &in.rho_f, &in.jx_f, &in.jy_f, &in.rho_p, &in.jx_p,
+                   &in.jy_p, &in.theta);
+      /* S4: central differences of the previous step's fields.  Reading:
+       * the paper gives no stencil; the lag keeps the gradient independent
+       * of the order in which nodes are updated. */
+      in.dphi_dx = 0.5 * (phi_at(o, x + 1, y) - phi_at(o, x - 1, y));
+      in.dphi_dy = 0.5 * (phi_at(o, x, y + 1) - phi_at(o, x, y - 1));
+      in.dth_dx = 0.5 * (theta_at(o, x + 1, y) - theta_at(o, x - 1, y));
+      in.dth_dy = 0.5 * (theta_at(o, x, y + 1) - theta_at(o, x, y - 1));
+      NodeOut r;
+      node_physics(o, &in, &r); /* S2, S3, S5 */
+      /* S6: BGK collisions, Eqs 18-19 with equilibria of Eqs 26-27.
+       * Reading: f and p relax to their own velocities; g to the mixture
+       * velocity of Eq 32. */
+      for (int i = 0; i < 9; ++i) {
+        const size_t k = i * nn + n;
+        const double fi = o->f[k], pi = o->p[k], gi = o->g[k];
+        o->fs[k] = fi - (fi - equilibrium(i, in.rho_f, r.ux_f, r.uy_f)) / tau_f +
+                   forcing(i, r.Ffx, r.Ffy);
+        o->ps[k] = pi - (pi - equilibrium(i, in.rho_p, r.ux_p, r.uy_p)) / r.tau_p +
+                   forcing(i, r.Fpx, r.Fpy);
+        o->gs[k] = gi - (gi - equilibrium(i, in.theta, r.ux_ns, r.uy_ns)) / r.tau_th;
+      }
+      /* keep (phi, theta) of this step for the next step's gradients */
+      o->phi_cur[n] = in.rho_p / o->s.R;
+      o->th_cur[n] = in.theta;
+    }
+  }
+}
+
+/* S7: pull streaming with the walls of Eqs 34-36.
+ * Reading: walls sit half-way between the last node and its ghost, so the
+ * no-slip condition of Eq 34 becomes link-wise bounce-back and conserves the
+ * mass of each component exactly; the isothermal condition of Eq 35 solved
+ * for the unknown gives anti-bounce-back g_i = -g*_opp + 2 W_i theta_w; the
+ * adiabatic condition of Eq 36 copies the unknown populations from the
+ * adjacent row in the same direction, after the isothermal rule. */
+static void stream_all(mo_state* o) {
+  const int nx = o->nx, ny = o->ny, b = o->cfg.boundary;
+  const size_t nn = o->nn;
+#pragma omp parallel for schedule(static)
+  for (int y = 0; y < ny; ++y) {
+    for (int x = 0; x < nx; ++x) {
+      const size_t n = (size_t)y * nx + x;
+      for (int i = 0; i < 9; ++i) {
+        int sx = x - EX[i], sy = y - EY[i];
+        if (b != MO_CAVITY) sx = wrap(sx, nx);
+        if (b == MO_PERIODIC) sy = wrap(sy, ny);
+        const int in_x = sx >= 0 && sx < nx, in_y = sy >= 0 && sy < ny;
+        const size_t k = i * nn + n;
+        if (in_x && in_y) {
+          const size_t src = i * nn + (size_t)sy * nx + sx;
+          o->f[k] = o->fs[src];
+          o->p[k] = o->ps[src];
+          o->g[k] = o->gs[src];
+        } else {
+          const size_t own = OPP[i] * nn + n;
+          o->f[k] = o->fs[own];
+          o->p[k] = o->ps[own];
+          if (!in_x) {
+            const double thw = sx < 0 ? TH_HOT : TH_COLD;
+            o->g[k] = -o->gs[own] + 2.0 * WGT[i] * thw;
+          } else {
+            o->g[k] = NAN; /* crossing a y-wall only: set by the copy below */
+          }
+        }
+      }
+    }
+  }
+  if (b == MO_PERIODIC) return;
+  /* adiabatic walls: unknowns of row 0 (e_y = +1) and of row ny-1
+   * (e_y = -1) copied from rows 1 and ny-2 */
+  for (int x = 0; x < nx; ++x) {
+    for (int i = 0; i < 9; ++i) {
+      if (EY[i] == 1)
+        o->g[i * nn + x] = o->g[i * nn + (size_t)nx + x];
+      else if (EY[i] == -1)
+        o->g[i * nn + (size_t)(ny - 1) * nx + x] =
+            o->g[i * nn + (size_t)(ny - 2) * nx + x];
+    }
+  }
+}
+
+int mclbm_oracle_step(mo_state* o, int64_t nsteps) {
+  if (!o || nsteps < 0) return MO_EINVAL;
+  for (int64_t s = 0; s < nsteps; ++s) {
+    collide_all(o);
+    stream_all(o);
+    /* S8 */
+    double* t1 = o->phi_prev; o->phi_prev = o->phi_cur; o->phi_cur = t1;
+    double* t2 = o->th_prev; o->th_prev = o->th_cur; o->th_cur = t2;
+    o->t += 1;
+  }
+  return MO_OK;
+}
+
+/* ---- outputs ----------------------------------------------------------- */
+int mclbm_oracle_read_moments(const mo_state* o, uint32_t mask, double* out,
+                              size_t n_doubles) {
+  if (!o || !out) return MO_EINVAL;
+  int nf = 0;
+  for (int b = 0; b < 9; ++b) nf += (mask >> b) & 1u;
+  if (mask >> 9) return MO_EINVAL;
+  const size_t nn = o->nn;
+  if (n_doubles < (size_t)nf * nn) return MO_EINVAL;
+  for (size_t n = 0; n < nn; ++n) {
+    double rf, jxf, jyf, rp, jxp, jyp, th;
+    node_moments(o, n, &rf, &jxf, &jyf, &rp, &jxp, &jyp, &th);
+    const double uxf = jxf / rf, uyf = jyf / rf;
+    const int empty = !(rp > 1e-12);
+    const double v[9] = {rf,
+                         uxf,
+                         uyf,
+                         rp / o->s.R,
+                         empty ? uxf : jxp / rp,
+                         empty ? uyf : jyp / rp,
+                         th,
+                         (jxf + jxp) / (rf + rp),
+                         (jyf + jyp) / (rf + rp)};
+    int slot = 0;
+    for (int b = 0; b < 9; ++b) {
+      if ((mask >> b) & 1u) {
+        out[(size_t)slot * nn + n] = v[b];
+        ++slot;
+      }
+    }
+  }
+  return MO_OK;
+}
+
+int mclbm_oracle_read_populations(const mo_state* o, double* out,
+                                  size_t n_doubles) {
+  if (!o || !out || n_doubles < 27 * o->nn) return MO_EINVAL;
+  memcpy(out, o->f, 9 * o->nn * sizeof(double));
+  memcpy(out + 9 * o->nn, o->p, 9 * o->nn * sizeof(double));
+  memcpy(out + 18 * o->nn, o->g, 9 * o->nn * sizeof(double));
+  return MO_OK;
+}
+
+/* Average Nusselt number at the walls.  Reading: the paper plots the average
+ * hot-wall Nu without printing its formula; the wall gradient is the
+ * second-order one-sided difference through theta_w at half a spacing and
+ * the two first nodes, (9 theta_0 - theta_1 - 8 theta_w)/3, which is exact
+ * for linear profiles.  nu_hot_k weights it with k_ns/k_f at the first node. */
+int mclbm_oracle_nusselt(const mo_state* o, double* nu_hot, double* nu_cold,
+                         double* nu_hot_k) {
+  if (!o) return MO_EINVAL;
+  const int nx = o->nx, ny = o->ny;
+  const size_t nn = o->nn;
+  double sh = 0.0, sc = 0.0, sk = 0.0;
+  int bad = 0;
+  for (int y = 0; y < ny; ++y) {
+    double th[4] = {0, 0, 0, 0};
+    const int xs[4] = {0, 1, nx - 2, nx - 1};
+    for (int q = 0; q < 4; ++q) {
+      const size_t n = (size_t)y * nx + xs[q];
+      for (int i = 0; i < 9; ++i) th[q] += o->g[i * nn + n];
+    }
+    double rp = 0.0;
+    for (int i = 0; i < 9; ++i) rp += o->p[i * nn + (size_t)y * nx];
+    double phi = rp / o->s.R;
+    if (phi < 0.0) phi = 0.0;
+    const double r_k = 1.0 + o->s.Ck * pow(phi, 0.764);
+    const double gh = -(double)nx * (9.0 * th[0] - th[1] - 8.0 * TH_HOT) / 3.0;
+    const double gc = (double)nx * (9.0 * th[3] - th[2] - 8.0 * TH_COLD) / 3.0;
+    sh += gh;
+    sc += gc;
+    sk += r_k * gh;
+    if (!isfinite(gh) || !isfinite(gc)) bad = 1;
+  }
+  if (nu_hot) *nu_hot = sh / ny;
+  if (nu_cold) *nu_cold = sc / ny;
+  if (nu_hot_k) *nu_hot_k = sk / ny;
+  return bad ? MO_EDIVERGED : MO_OK;
+}
+
+/* Relative L2 change of the mixture velocity and of theta since the last
+ * call (or since the initial state), then the snapshot is replaced. */
+int mclbm_oracle_residual(mo_state* o, double* res_u, double* res_theta) {
+  if (!o) return MO_EINVAL;
+  const size_t nn = o->nn;
+  double du = 0.0, nu = 0.0, dth = 0.0, nth = 0.0;
+  int bad = 0;
+  for (size_t n = 0; n < nn; ++n) {
+    double rf, jxf, jyf, rp, jxp, jyp, th;
+    node_moments(o, n, &rf, &jxf, &jyf, &rp, &jxp, &jyp, &th);
+    const double ux = (jxf + jxp) / (rf + rp), uy = (jyf + jyp) / (rf + rp);
+    if (!isfinite(ux) || !isfinite(uy) || !isfinite(th)) bad = 1;
+    du += (ux - o->snap_ux[n]) * (ux - o->snap_ux[n]) +
+          (uy - o->snap_uy[n]) * (uy - o->snap_uy[n]);
+    nu += ux * ux + uy * uy;
+    dth += (th - o->snap_th[n]) * (th - o->snap_th[n]);
+    nth += th * th;
+    o->snap_ux[n] = ux;
+    o->snap_uy[n] = uy;
+    o->snap_th[n] = th;
+  }
+  if (res_u) *res_u = nu > 0.0 ? sqrt(du / nu) : (du > 0.0 ? INFINITY : 0.0);
+  if (res_theta)
+    *res_theta = nth > 0.0 ? sqrt(dth / nth) : (dth > 0.0 ? INFINITY : 0.0);
+  return bad ? MO_EDIVERGED : MO_OK;
+}
+
+int mclbm_oracle_derived(const mo_state* o, double* out, int n) {
+  if (!o || !out || n < MO_D_COUNT) return MO_EINVAL;
+  const Setup* s = &o->s;
+  out[MO_D_NU_L] = s->nu_L;
+  out[MO_D_ALPHA_L] = s->alpha_L;
+  out[MO_D_H] = s->H;
+  out[MO_D_DX] = s->dx;
+  out[MO_D_DT] = s->dt;
+  out[MO_D_G_L] = s->G_L;
+  out[MO_D_GRAV_L] = s->grav_L;
+  out[MO_D_CK] = s->Ck;
+  out[MO_D_R] = s->R;
+  out[MO_D_TAU_F] = s->tau_f;
+  out[MO_D_RHOC_RATIO] = s->rhoc_ratio;
+  out[MO_D_BETA_RATIO] = s->beta_ratio;
+  out[MO_D_RHO_F0] = s->rho_f0;
+  out[MO_D_RHO_P0] = s->rho_p0;
+  out[MO_D_NU_F] = s->nu_f;
+  out[MO_D_ALPHA_F] = s->alpha_f;
+  return MO_OK;
+}
+
+int mclbm_oracle_node_forces(const mo_state* o, const double* in,
+                             double* out) {
+  if (!o || !in || !out) return MO_EINVAL;
+  NodeIn a;
+  a.rho_f = in[MO_IN_RHO_F]; a.jx_f = in[MO_IN_JX_F]; a.jy_f = in[MO_IN_JY_F];
+  a.rho_p = in[MO_IN_RHO_P]; a.jx_p = in[MO_IN_JX_P]; a.jy_p = in[MO_IN_JY_P];
+  a.theta = in[MO_IN_THETA];
+  a.dphi_dx = in[MO_IN_DPHI_DX]; a.dphi_dy = in[MO_IN_DPHI_DY];
+  a.dth_dx = in[MO_IN_DTH_DX]; a.dth_dy = in[MO_IN_DTH_DY];
+  NodeOut r;
+  node_physics(o, &a, &r);
+  out[MO_OUT_FFX] = r.Ffx; out[MO_OUT_FFY] = r.Ffy;
+  out[MO_OUT_FPX] = r.Fpx; out[MO_OUT_FPY] = r.Fpy;
+  out[MO_OUT_TAU_P] = r.tau_p; out[MO_OUT_TAU_TH] = r.tau_th;
+  out[MO_OUT_ABX] = r.aB[0]; out[MO_OUT_ABY] = r.aB[1];
+  out[MO_OUT_ATX] = r.aT[0]; out[MO_OUT_ATY] = r.aT[1];
+  out[MO_OUT_ASX] = r.aS[0]; out[MO_OUT_ASY] = r.aS[1];
+  out[MO_OUT_AMRX] = r.aMR[0]; out[MO_OUT_AMRY] = r.aMR[1];
+  out[MO_OUT_AGX] = r.aG[0]; out[MO_OUT_AGY] = r.aG[1];
+  out[MO_OUT_DX] = r.D[0]; out[MO_OUT_DY] = r.D[1];
+  out[MO_OUT_BETA_L] = r.beta_L; out[MO_OUT_KAPPA] = r.kappa;
+  out[MO_OUT_R_K] = r.r_k; out[MO_OUT_R_MU] = r.r_mu;
+  return MO_OK;
+}

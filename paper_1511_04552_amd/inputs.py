@@ -1,0 +1,70 @@
+"""Seeded synthetic inputs for the MCLBM cavity workloads.
+
+This module holds no arithmetic of the method.  It only draws random numbers
+and names workload parameter sets, so that the HIP path and the FP64 oracle
+(used by the tests) receive identical inputs without sharing any code.
+
+* ``phi_perturbation`` draws the +-1 field xi that scales the initial
+  particle-volume-fraction perturbation (the cavity starts at rest with a
+  uniform suspension, Section 2.d; the tiny seeded perturbation only breaks
+  exact symmetry).  SplitMix64 (Steele, Lea and Flood, 2014), one draw per
+  node in row-major order (x fastest).
+* ``sweep_parameters`` draws a batch of uneven cavities for parameter sweeps.
+* ``WORKLOADS`` names the cavity configurations used by tests and the bench.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+_GOLDEN = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+
+
+def splitmix64(seed: int, n: int) -> np.ndarray:
+    """First ``n`` outputs of SplitMix64 started at ``seed`` (uint64)."""
+    with np.errstate(over="ignore"):
+        k = np.arange(1, n + 1, dtype=np.uint64)
+        z = np.uint64(seed & 0xFFFFFFFFFFFFFFFF) + k * _GOLDEN
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+        z = z ^ (z >> np.uint64(31))
+    return z
+
+
+def uniform(seed: int, n: int) -> np.ndarray:
+    """``n`` doubles in [0, 1) from the top 53 bits of SplitMix64."""
+    return (splitmix64(seed, n) >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+
+
+def phi_perturbation(seed: int, nx: int, ny: int) -> np.ndarray:
+    """xi in [-1, 1), shape (ny, nx), row-major draw order."""
+    return (2.0 * uniform(seed, nx * ny) - 1.0).reshape(ny, nx)
+
+
+# Cavity workloads: 64^2 FP64 reference run; 512^2 run to steady state;
+# 2048^2 reduced-precision storage case (properties of water / alumina).
+WORKLOADS = {
+    "cavity64_ra1e3": dict(nx=64, ny=64, Ra=1e3, Pr=6.2, phi0=0.01, dp_nm=100.0,
+                           tau_f=0.8, seed=1),
+    "cavity512_ra1e5": dict(nx=512, ny=512, Ra=1e5, Pr=6.2, phi0=0.03, dp_nm=50.0,
+                            tau_f=0.8, seed=2),
+    "cavity2048_ra1e6": dict(nx=2048, ny=2048, Ra=1e6, Pr=6.2, phi0=0.04, dp_nm=30.0,
+                             tau_f=0.8, seed=4),
+    "cavity160_paper": dict(nx=160, ny=160, Ra=1e6, Pr=8.923, phi0=0.04, dp_nm=33.0,
+                            tau_f=0.8, seed=6),
+}
+
+
+def sweep_parameters(seed: int, count: int,
+                     sides=(64, 128, 256, 384, 512)) -> list:
+    """Uneven cavity batch: side uniform over ``sides``, Ra log-uniform in
+    [1e3, 1e6], phi uniform in [0, 0.05], d_p uniform in [10, 100] nm."""
+    u = uniform(seed, 4 * count).reshape(count, 4)
+    out = []
+    for k in range(count):
+        side = int(sides[min(int(u[k, 0] * len(sides)), len(sides) - 1)])
+        out.append(dict(nx=side, ny=side, Ra=float(10.0 ** (3.0 + 3.0 * u[k, 1])),
+                        phi0=float(0.05 * u[k, 2]), dp_nm=float(10.0 + 90.0 * u[k, 3]),
+                        seed=seed * 1000003 + k))
+    return out
