@@ -1,0 +1,212 @@
+/*
+ * mclbm.h -- C ABI of the MI355X (gfx950) multi-component lattice Boltzmann
+ * library: three coupled D2Q9 lattices (base fluid f, nanoparticle phase p,
+ * temperature g) in a differentially heated cavity, after Savithiri, Dhar,
+ * Pattamatta and Das, "Particle-fluid interactivity deteriorates buoyancy
+ * driven thermal transport in nanosuspensions: a multi component lattice
+ * Boltzmann approach" (arXiv:1511.04552).
+ *
+ * Conventions for every entry point:
+ *   - All functions return an int status (MCLBM_OK = 0, negative = error)
+ *     unless stated otherwise; mclbm_last_error() gives a thread-local
+ *     message for the last failure on the calling thread.
+ *   - No C++ exception crosses this boundary.
+ *   - Device pointers are HIP device addresses on the current device; host
+ *     pointers are plain host memory.  The library never allocates device
+ *     memory: the caller passes one device buffer of mclbm_device_bytes()
+ *     bytes, which the library borrows until mclbm_destroy().
+ *   - All device work is enqueued on the stream given at creation
+ *     (a hipStream_t, NULL = the legacy default stream).  Calls marked
+ *     "async" return before the work completes; calls marked "sync" wait for
+ *     the stream before returning.
+ *   - A cavity handle is not thread-safe; distinct handles on distinct
+ *     streams may be used concurrently.
+ *
+ * Lattice conventions (Section 2.d, Eqs 21 and 28): direction order rest,
+ * E, N, W, S, NE, NW, SW, SE; lattice units dx = dt = 1, c_s^2 = 1/3;
+ * nodes x = 0..nx-1 (hot wall at x = -1/2, cold wall at x = nx - 1/2),
+ * y = 0..ny-1 (adiabatic walls at y = -1/2 and ny - 1/2); theta =
+ * (T - T0)/dT with theta_hot = +1/2, theta_cold = -1/2.
+ */
+#ifndef MCLBM_H
+#define MCLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MCLBM_ABI_VERSION 1
+
+enum mclbm_status {
+  MCLBM_OK = 0,
+  MCLBM_EINVAL = -1,      /* invalid argument or configuration */
+  MCLBM_ENOMEM = -2,      /* device buffer smaller than mclbm_device_bytes */
+  MCLBM_EHIP = -3,        /* a HIP runtime call failed (message kept) */
+  MCLBM_EDIVERGED = -4,   /* a non-finite value was found at a sync point */
+  MCLBM_ESTATE = -5,      /* call not allowed in the current state */
+  MCLBM_EUNSUPPORTED = -6 /* valid request this build does not implement */
+};
+
+/* Storage type of the populations.  Populations are always stored as
+ * deviations from the uniform reference state (f_i - W_i rho_ref); the
+ * collision always computes in FP32 and reductions in FP64. */
+enum mclbm_storage { MCLBM_FP32S = 0, MCLBM_FP16S = 1, MCLBM_BF16S = 2 };
+
+/* Slip-force switches (Table 1 of the paper).  Buoyancy (Eq 20) is always
+ * on and scales with Ra. */
+enum mclbm_force {
+  MCLBM_F_DRAG = 1, MCLBM_F_BROWN = 2, MCLBM_F_THERMO = 4, MCLBM_F_SAFF = 8,
+  MCLBM_F_MAGROT = 16, MCLBM_F_GRAV = 32, MCLBM_F_ALL = 63
+};
+
+/* Moment fields (Eqs 29-32) for mclbm_read_moments / mclbm_export_moments.
+ * Fields are written in increasing bit order, each nx*ny doubles, row-major
+ * with x fastest. RHO_F is the fluid partial density, PHI the particle
+ * volume fraction, *_NS the mass-averaged mixture velocity of Eq 32. */
+enum mclbm_field {
+  MCLBM_RHO_F = 1, MCLBM_UX_F = 2, MCLBM_UY_F = 4, MCLBM_PHI = 8,
+  MCLBM_UX_P = 16, MCLBM_UY_P = 32, MCLBM_THETA = 64, MCLBM_UX_NS = 128,
+  MCLBM_UY_NS = 256, MCLBM_ALL_FIELDS = 511
+};
+
+/* Derived lattice constants (slots of mclbm_derived). */
+enum mclbm_derived_slot {
+  MCLBM_D_NU_L = 0, MCLBM_D_ALPHA_L, MCLBM_D_H, MCLBM_D_DX, MCLBM_D_DT,
+  MCLBM_D_G_L, MCLBM_D_GRAV_L, MCLBM_D_CK, MCLBM_D_R, MCLBM_D_TAU_F,
+  MCLBM_D_RHOC_RATIO, MCLBM_D_BETA_RATIO, MCLBM_D_RHO_F0, MCLBM_D_RHO_P0,
+  MCLBM_D_NU_F, MCLBM_D_ALPHA_F, MCLBM_D_COUNT
+};
+
+typedef struct {
+  double rho;   /* density, kg/m^3 */
+  double cp;    /* specific heat, J/(kg K) */
+  double k;     /* thermal conductivity, W/(m K) */
+  double beta;  /* thermal expansion coefficient, 1/K */
+  double mu;    /* dynamic viscosity, Pa s (fluid only) */
+  double d_mol; /* molecular diameter, m (fluid only; also the mean free
+                   path of the thermophoretic Knudsen number) */
+} mclbm_material;
+
+typedef struct {
+  int32_t nx, ny;          /* nodes, each >= 4; Ra is based on nx */
+  double Ra;               /* base-fluid Rayleigh number (Eq 16), >= 0 */
+  double Pr;               /* base-fluid Prandtl number, > 0 */
+  double phi0;             /* mean particle volume fraction, [0, 0.1] */
+  double dp_m;             /* particle diameter, m, > 0 */
+  double tau_f;            /* fluid relaxation time (Eq 22), > 0.5; <= 0:
+                              automatic, free-fall velocity <= 0.1 c_s */
+  double dT_K, T0_K;       /* wall temperature difference and mean, K */
+  uint32_t force_mask;     /* MCLBM_F_* bits */
+  double force_scale[6];   /* per-force multipliers in bit order (test knob) */
+  double phi_perturb_amp;  /* initial phi = max(phi0 + amp * xi, 0) */
+  mclbm_material fluid, particle;
+  int32_t storage;         /* enum mclbm_storage */
+  int32_t block_x, block_y;/* step-kernel block shape; 0 = default (64x4).
+                              block_x in {32, 64, 128, 256},
+                              block_x * block_y in {64, 128, 256, 512, 1024} */
+} mclbm_config;
+
+typedef struct mclbm_cavity mclbm_cavity; /* opaque host-side handle */
+
+/* Fill *cfg with the defaults: 64x64, Ra 1e3, Pr 6.2, phi0 0.01, dp 100 nm,
+ * tau_f 0.8, dT 10 K, T0 300 K, all forces at scale 1, amplitude 1e-6,
+ * water and alumina properties, FP32 storage, default block shape. */
+void mclbm_config_defaults(mclbm_config* cfg);
+
+/* Bytes of device memory a cavity with this configuration needs; 0 if the
+ * configuration is invalid (see mclbm_last_error). */
+size_t mclbm_device_bytes(const mclbm_config* cfg);
+
+/* Derived lattice constants of a configuration (host only, no device work):
+ * MCLBM_D_COUNT doubles in enum mclbm_derived_slot order -- lattice
+ * viscosity and diffusivity (Eq 22), cavity width H from Ra (Eq 16), dx,
+ * dt, g beta dT and g in lattice units, the Eq 10a constant, density ratio,
+ * relaxation time, heat-capacity and expansion ratios (Eqs 8-9), reference
+ * partial densities, physical viscosity and diffusivity. */
+int mclbm_derive_constants(const mclbm_config* cfg, double* out, int n);
+
+/* Create a cavity on the device buffer dev_buf (>= mclbm_device_bytes,
+ * 256-byte aligned) and enqueue its initial state on `stream`: fluid at rest,
+ * uniform temperature theta = 0, populations at equilibrium (Eqs 26-27).
+ * xi_host: NULL or nx*ny host doubles in [-1, 1] (row-major) scaling the
+ * initial phi perturbation; it is copied.  Async.  The library keeps a
+ * pointer to neither cfg nor xi_host. */
+int mclbm_create(const mclbm_config* cfg, const double* xi_host,
+                 void* dev_buf, size_t bytes, void* stream,
+                 mclbm_cavity** out);
+
+/* Change Ra, phi0 and dp (the parameters the paper sweeps, Section 3) and
+ * restart from the initial state.  Allowed at any time; re-derives the
+ * lattice constants.  Async.  MCLBM_EINVAL leaves the cavity unchanged. */
+int mclbm_set_properties(mclbm_cavity* c, double Ra, double phi0,
+                         double dp_m);
+
+/* Restart from the initial state (time 0).  Async. */
+int mclbm_reset(mclbm_cavity* c);
+
+/* Advance nsteps >= 0 time steps (Eqs 18-36: collision with the slip
+ * forces, streaming, walls).  Each step is one fused kernel launch.  Async. */
+int mclbm_step(mclbm_cavity* c, int64_t nsteps);
+
+/* Number of steps taken since the initial state. */
+int64_t mclbm_time(const mclbm_cavity* c);
+
+/* Moments (Eqs 29-32) of the current state as doubles into device memory
+ * dev_out (n_doubles >= popcount(mask) * nx * ny).  Async. */
+int mclbm_export_moments(mclbm_cavity* c, uint32_t mask, double* dev_out,
+                         size_t n_doubles);
+
+/* As mclbm_export_moments, into host memory.  Sync. */
+int mclbm_read_moments(mclbm_cavity* c, uint32_t mask, double* host_out,
+                       size_t n_doubles);
+
+/* Populations of the current state after streaming, as doubles in host
+ * memory: [lattice f,p,g][direction][y][x], 27*nx*ny values, the shift of
+ * the storage added back.  Sync.  For tests and checkpoints. */
+int mclbm_read_populations(mclbm_cavity* c, double* host_out,
+                           size_t n_doubles);
+
+/* As mclbm_read_populations, into device memory dev_out
+ * (n_doubles >= 27*nx*ny).  Async. */
+int mclbm_export_populations(mclbm_cavity* c, double* dev_out,
+                             size_t n_doubles);
+
+/* Average Nusselt numbers of the current state, accumulated in FP64:
+ * nu_hot = mean over y of -nx (9 theta(0,y) - theta(1,y) - 8 theta_hot)/3,
+ * nu_cold the mirror image at the cold wall, nu_hot_k the hot-wall value
+ * weighted with k_ns/k_f of Eq 10a at the first node.  Any pointer may be
+ * NULL.  Sync.  Returns MCLBM_EDIVERGED if a wall value is not finite. */
+int mclbm_nusselt(mclbm_cavity* c, double* nu_hot, double* nu_cold,
+                  double* nu_hot_k);
+
+/* Relative L2 change of the mixture velocity and of theta since the
+ * previous call (or since the initial state), accumulated in FP64; the
+ * current state becomes the new reference.  Sync.  Returns
+ * MCLBM_EDIVERGED if any node is not finite. */
+int mclbm_residual(mclbm_cavity* c, double* res_u, double* res_theta);
+
+/* Derived lattice constants, MCLBM_D_COUNT doubles (enum slots). */
+int mclbm_derived(const mclbm_cavity* c, double* out, int n);
+
+/* Release the handle.  Does not free dev_buf.  Waits for the stream. */
+int mclbm_destroy(mclbm_cavity* c);
+
+/* Thread-local message describing the last failure ("" if none). */
+const char* mclbm_last_error(void);
+
+/* Measurement helper: copy `bytes` (multiple of 16) from src to dst, both
+ * device buffers, with a plain streaming kernel on `stream`.  Async.
+ * Used to calibrate the achievable HBM bandwidth and the byte counters. */
+int mclbm_copy_kernel(void* dst, const void* src, size_t bytes, void* stream);
+
+/* Library version string and the ABI version. */
+const char* mclbm_version(void);
+int mclbm_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MCLBM_H */

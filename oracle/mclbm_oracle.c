@@ -713,9 +713,9 @@ int mclbm_oracle_residual(mo_state* o, double* res_u, double* res_theta) {
     o->snap_uy[n] = uy;
     o->snap_th[n] = th;
   }
-  if (res_u) *res_u = nu > 0.0 ? sqrt(du / nu) : (du > 0.0 ? INFINITY : 0.0);
+  if (res_u) *res_u = bad ? NAN : (nu > 0.0 ? sqrt(du / nu) : (du > 0.0 ? INFINITY : 0.0));
   if (res_theta)
-    *res_theta = nth > 0.0 ? sqrt(dth / nth) : (dth > 0.0 ? INFINITY : 0.0);
+    *res_theta = bad ? NAN : (nth > 0.0 ? sqrt(dth / nth) : (dth > 0.0 ? INFINITY : 0.0));
   return bad ? MO_EDIVERGED : MO_OK;
 }
 

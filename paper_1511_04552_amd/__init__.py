@@ -1,0 +1,269 @@
+"""MI355X-native multi-component lattice Boltzmann (MCLBM) cavity solver.
+
+Thin ctypes binding of ``libmclbm.so`` (C ABI in ``include/mclbm.h``): three
+coupled D2Q9 lattices (base fluid, nanoparticle phase, temperature) for
+buoyancy-driven flow of a nanosuspension in a differentially heated cavity
+(Section 2.d of arXiv:1511.04552).  Every step of the method runs in the HIP
+kernels of the library; this module only marshals arguments.  PyTorch provides
+the device memory and the stream.  There is no CPU fallback: without the
+built library (``python -m paper_1511_04552_amd.build``) every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmclbm.so")
+
+# Interface constants of include/mclbm.h.
+OK, EINVAL, ENOMEM, EHIP, EDIVERGED, ESTATE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+FP32S, FP16S, BF16S = 0, 1, 2
+F_DRAG, F_BROWN, F_THERMO, F_SAFF, F_MAGROT, F_GRAV = 1, 2, 4, 8, 16, 32
+F_ALL = 63
+FIELDS = ("rho_f", "ux_f", "uy_f", "phi", "ux_p", "uy_p", "theta", "ux_ns", "uy_ns")
+FIELD_BIT = {name: 1 << i for i, name in enumerate(FIELDS)}
+DERIVED = ("nu_L", "alpha_L", "H", "dx", "dt", "G_L", "grav_L", "Ck", "R", "tau_f",
+           "rhoc_ratio", "beta_ratio", "rho_f0", "rho_p0", "nu_f", "alpha_f")
+EXPORTED = ("mclbm_config_defaults", "mclbm_device_bytes", "mclbm_derive_constants", "mclbm_create",
+            "mclbm_set_properties", "mclbm_reset", "mclbm_step", "mclbm_time",
+            "mclbm_export_moments", "mclbm_read_moments", "mclbm_read_populations",
+            "mclbm_export_populations", "mclbm_nusselt", "mclbm_residual",
+            "mclbm_derived", "mclbm_destroy", "mclbm_last_error", "mclbm_copy_kernel",
+            "mclbm_version", "mclbm_abi_version")
+
+
+class MclbmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"mclbm error {code}: {msg}")
+        self.code = code
+
+
+class Material(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in ("rho", "cp", "k", "beta", "mu", "d_mol")]
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("Ra", ctypes.c_double), ("Pr", ctypes.c_double),
+        ("phi0", ctypes.c_double), ("dp_m", ctypes.c_double),
+        ("tau_f", ctypes.c_double),
+        ("dT_K", ctypes.c_double), ("T0_K", ctypes.c_double),
+        ("force_mask", ctypes.c_uint32),
+        ("force_scale", ctypes.c_double * 6),
+        ("phi_perturb_amp", ctypes.c_double),
+        ("fluid", Material), ("particle", Material),
+        ("storage", ctypes.c_int32),
+        ("block_x", ctypes.c_int32), ("block_y", ctypes.c_int32),
+    ]
+
+
+_lib = None
+
+
+def lib(load_torch: bool = True):
+    """Load ``libmclbm.so`` (after torch, so that both share one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if load_torch:
+        import torch  # noqa: F401  (shares libamdhip64 with the library)
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built: run `python -m paper_1511_04552_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    P, D, I = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int
+    CP = ctypes.POINTER(Config)
+    L.mclbm_config_defaults.argtypes = [CP]
+    L.mclbm_config_defaults.restype = None
+    L.mclbm_device_bytes.argtypes = [CP]
+    L.mclbm_device_bytes.restype = ctypes.c_size_t
+    L.mclbm_derive_constants.argtypes = [CP, D, I]
+    L.mclbm_create.argtypes = [CP, D, P, ctypes.c_size_t, P, ctypes.POINTER(P)]
+    L.mclbm_set_properties.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_double]
+    L.mclbm_reset.argtypes = [P]
+    L.mclbm_step.argtypes = [P, ctypes.c_int64]
+    L.mclbm_time.argtypes = [P]
+    L.mclbm_time.restype = ctypes.c_int64
+    L.mclbm_export_moments.argtypes = [P, ctypes.c_uint32, P, ctypes.c_size_t]
+    L.mclbm_read_moments.argtypes = [P, ctypes.c_uint32, D, ctypes.c_size_t]
+    L.mclbm_read_populations.argtypes = [P, D, ctypes.c_size_t]
+    L.mclbm_export_populations.argtypes = [P, P, ctypes.c_size_t]
+    L.mclbm_nusselt.argtypes = [P, D, D, D]
+    L.mclbm_residual.argtypes = [P, D, D]
+    L.mclbm_derived.argtypes = [P, D, I]
+    L.mclbm_destroy.argtypes = [P]
+    L.mclbm_last_error.restype = ctypes.c_char_p
+    L.mclbm_copy_kernel.argtypes = [P, P, ctypes.c_size_t, P]
+    L.mclbm_version.restype = ctypes.c_char_p
+    L.mclbm_abi_version.restype = I
+    _lib = L
+    return L
+
+
+def _check(rc: int) -> int:
+    if rc != 0:
+        raise MclbmError(rc, lib().mclbm_last_error().decode())
+    return rc
+
+
+def make_config(**kw) -> Config:
+    """Config with the library defaults, overridden by keyword arguments
+    (``dp_nm`` is accepted for the particle diameter in nanometres)."""
+    c = Config()
+    lib().mclbm_config_defaults(ctypes.byref(c))
+    for key, val in kw.items():
+        if key == "force_scale":
+            for i, v in enumerate(val):
+                c.force_scale[i] = float(v)
+        elif key in ("fluid", "particle"):
+            m = getattr(c, key)
+            for mk, mv in val.items():
+                setattr(m, mk, float(mv))
+        elif key == "dp_nm":
+            c.dp_m = float(val) * 1e-9
+        elif key == "seed":
+            continue
+        else:
+            if not hasattr(c, key):
+                raise KeyError(key)
+            setattr(c, key, val)
+    return c
+
+
+def device_bytes(**kw) -> int:
+    n = lib().mclbm_device_bytes(ctypes.byref(make_config(**kw)))
+    if n == 0:
+        raise MclbmError(EINVAL, lib().mclbm_last_error().decode())
+    return int(n)
+
+
+def derive_constants(**kw) -> dict:
+    """Derived lattice constants of a configuration (host-side, no GPU)."""
+    out = np.zeros(len(DERIVED))
+    _check(lib().mclbm_derive_constants(ctypes.byref(make_config(**kw)),
+                                        out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), out.size))
+    return dict(zip(DERIVED, out.tolist()))
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+class Cavity:
+    """One cavity resident on the current GPU.
+
+    ``xi``: optional (ny, nx) field in [-1, 1] scaling the initial phi
+    perturbation (see ``paper_1511_04552_amd.inputs.phi_perturbation``).
+    Work is enqueued on ``stream`` (default: torch's current stream).
+    """
+
+    def __init__(self, xi=None, stream=None, device=None, **cfg):
+        import torch
+        L = lib()
+        self.cfg = make_config(**cfg)
+        self.nx, self.ny = int(self.cfg.nx), int(self.cfg.ny)
+        nbytes = L.mclbm_device_bytes(ctypes.byref(self.cfg))
+        if nbytes == 0:
+            raise MclbmError(EINVAL, L.mclbm_last_error().decode())
+        dev = torch.device("cuda" if device is None else device)
+        self._buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        base = self._buf.data_ptr()
+        self._base = (base + 255) // 256 * 256
+        self.nbytes = int(nbytes)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        self._h = ctypes.c_void_p()
+        xp = None
+        if xi is not None:
+            self._xi = np.ascontiguousarray(xi, dtype=np.float64).reshape(-1)
+            if self._xi.size != self.nx * self.ny:
+                raise ValueError("xi must hold nx*ny values")
+            xp = _dptr(self._xi)
+        _check(L.mclbm_create(ctypes.byref(self.cfg), xp, ctypes.c_void_p(self._base),
+                              ctypes.c_size_t(self.nbytes),
+                              ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(self._h)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().mclbm_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- stepping -----------------------------------------------------------
+    def step(self, n: int) -> None:
+        _check(lib().mclbm_step(self._h, int(n)))
+
+    @property
+    def time(self) -> int:
+        return int(lib().mclbm_time(self._h))
+
+    def reset(self) -> None:
+        _check(lib().mclbm_reset(self._h))
+
+    def set_properties(self, Ra: float, phi0: float, dp_m: float) -> None:
+        _check(lib().mclbm_set_properties(self._h, float(Ra), float(phi0), float(dp_m)))
+
+    # ---- outputs ------------------------------------------------------------
+    @staticmethod
+    def _mask(names):
+        if isinstance(names, str):
+            names = (names,)
+        mask = 0
+        for n in names:
+            mask |= FIELD_BIT[n]
+        return mask, [n for n in FIELDS if mask & FIELD_BIT[n]]
+
+    def moments(self, names=FIELDS) -> dict:
+        mask, order = self._mask(names)
+        out = np.zeros(len(order) * self.nx * self.ny)
+        _check(lib().mclbm_read_moments(self._h, mask, _dptr(out), out.size))
+        out = out.reshape(len(order), self.ny, self.nx)
+        return {n: out[k] for k, n in enumerate(order)}
+
+    def moments_device(self, names=FIELDS):
+        """Moments as a float64 torch tensor on the device, (nf, ny, nx)."""
+        import torch
+        mask, order = self._mask(names)
+        out = torch.empty((len(order), self.ny, self.nx), dtype=torch.float64, device=self._buf.device)
+        _check(lib().mclbm_export_moments(self._h, mask, ctypes.c_void_p(out.data_ptr()), out.numel()))
+        return order, out
+
+    def populations(self) -> np.ndarray:
+        out = np.zeros(27 * self.nx * self.ny)
+        _check(lib().mclbm_read_populations(self._h, _dptr(out), out.size))
+        return out.reshape(3, 9, self.ny, self.nx)
+
+    def nusselt(self, check: bool = True) -> tuple:
+        a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        rc = lib().mclbm_nusselt(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
+        if check:
+            _check(rc)
+        return a.value, b.value, c.value
+
+    def residual(self, check: bool = True) -> tuple:
+        a, b = ctypes.c_double(), ctypes.c_double()
+        rc = lib().mclbm_residual(self._h, ctypes.byref(a), ctypes.byref(b))
+        if check:
+            _check(rc)
+        return a.value, b.value
+
+    def derived(self) -> dict:
+        out = np.zeros(len(DERIVED))
+        _check(lib().mclbm_derived(self._h, _dptr(out), out.size))
+        return dict(zip(DERIVED, out.tolist()))
+
+
+def copy_kernel(dst, src, stream=None) -> None:
+    """Plain device-to-device streaming copy (bandwidth calibration)."""
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    nbytes = src.numel() * src.element_size()
+    _check(lib().mclbm_copy_kernel(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()),
+                                   ctypes.c_size_t(nbytes), ctypes.c_void_p(s.cuda_stream)))

@@ -1,0 +1,368 @@
+// Device-side building blocks of the fused three-lattice MCLBM step for
+// gfx950 (CDNA4, wave64): lattice constants, population storage, the A-A
+// in-place access pattern with the cavity walls, and the per-node physics.
+//
+// Lattice (Section 2.d, Eqs 21 and 28): directions rest, E, N, W, S, NE, NW,
+// SW, SE; lattice units dx = dt = 1, c_s^2 = 1/3.
+//
+// Memory layout in HBM (one copy, updated in place):
+//   pop[(l*9 + i)*plane + y*px + x]  l = 0 fluid f, 1 particles p, 2 theta g
+//   populations stored as deviations h = f - W_i rho_ref (rho_ref = 0 for g)
+//   d2[k][y*px + x] = (phi - phi_ref, theta) of the step before, k = t & 1
+//   d5[(wall*3 + slot)*px + x]  adiabatic-wall side buffer (see below)
+//
+// A-A pattern.  Even steps read the nine populations of a node from its own
+// slots i and write the post-collision value of direction i into its own slot
+// opp(i).  Odd steps read direction i from slot opp(i) of the upstream node
+// x - e_i and write direction i into slot i of the downstream node x + e_i.
+// Either way every thread reads exactly the slots it later writes, so one
+// array suffices and no two threads touch the same slot.
+//
+// Walls (half-way, Eqs 34-36).  No-slip (Eq 34) is link bounce-back; the
+// isothermal walls (Eq 35) use anti-bounce-back g_i = -g*_opp(i) + 2 W_i
+// theta_w; in the A-A pattern both reduce to an access of the node's own
+// slot.  The adiabatic walls (Eq 36) copy the unknown populations of the wall
+// row from the row next to it in the same direction (after the isothermal
+// rule at corners).  That copy reads slots that a neighbouring thread
+// rewrites in the odd step, so even steps also store the three values the
+// copy needs into the side buffer d5, which odd steps read; in odd steps the
+// thread that produces a copied value also stores it into the wall row.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_bf16.h>
+#include <stdint.h>
+
+namespace mclbm {
+
+__host__ __device__ constexpr int ex(int i) {
+  return (i == 1 || i == 5 || i == 8) ? 1 : ((i == 3 || i == 6 || i == 7) ? -1 : 0);
+}
+__host__ __device__ constexpr int ey(int i) {
+  return (i == 2 || i == 5 || i == 6) ? 1 : ((i == 4 || i == 7 || i == 8) ? -1 : 0);
+}
+__host__ __device__ constexpr int opp(int i) {
+  return i == 0 ? 0 : (i < 5 ? ((i + 1) % 4) + 1 : ((i - 3) % 4) + 5);
+}
+__host__ __device__ constexpr float wgt(int i) {
+  return i == 0 ? 4.0f / 9.0f : (i < 5 ? 1.0f / 9.0f : 1.0f / 36.0f);
+}
+// side-buffer slot of a wall-row unknown: bottom row N, NE, NW; top S, SE, SW
+__host__ __device__ constexpr int d5slot(int i) {
+  return (i == 2 || i == 4) ? 0 : ((i == 5 || i == 8) ? 1 : 2);
+}
+
+static_assert(opp(1) == 3 && opp(2) == 4 && opp(5) == 7 && opp(6) == 8 &&
+                  opp(7) == 5 && opp(8) == 6,
+              "opposite directions");
+
+// ---- population storage -------------------------------------------------
+// FP32 deviations; 16-bit deviations scaled by a power of two per lattice
+// (scale[l] on store, 1/scale[l] on load) so that typical deviations sit in
+// the normal range of the 16-bit format.
+struct StorF32 {
+  using T = float;
+  static __device__ __forceinline__ float ld(const T* p, float) { return *p; }
+  static __device__ __forceinline__ void st(T* p, float v, float) { *p = v; }
+};
+struct StorF16 {
+  using T = __half;
+  static __device__ __forceinline__ float ld(const T* p, float inv) {
+    return __half2float(*p) * inv;
+  }
+  static __device__ __forceinline__ void st(T* p, float v, float sc) {
+    *p = __float2half_rn(v * sc);
+  }
+};
+struct StorBF16 {
+  using T = __hip_bfloat16;
+  static __device__ __forceinline__ float ld(const T* p, float inv) {
+    return __bfloat162float(*p) * inv;
+  }
+  static __device__ __forceinline__ void st(T* p, float v, float sc) {
+    *p = __float2bfloat16(v * sc);
+  }
+};
+
+// ---- kernel parameters (kernarg, by value) -------------------------------
+struct StepParams {
+  int nx, ny, px, pad0;
+  long long plane;       // elements per population plane
+  float scale[3];        // storage scale per lattice (1 for FP32)
+  float inv_scale[3];
+  // reference state and relaxation
+  float rho_f_ref, rho_p_ref, dref_p;  // dref_p = rho_p_ref - R phi0
+  float tau_f, omega_f;
+  // properties (Eqs 7-11, 22-24)
+  float invR, Rm1, crc, crb, Ck, alpha3;
+  float tp_a, tp_b;      // tau_p = tau_f + tp_a rho_m (tp_b + 222.4 phi)/r_rho
+  float G_L;             // g beta dT in lattice units
+  // slip forces (Table 1) in lattice units, switches and scales folded in
+  float cB;              // Brownian
+  float cT, kfp, A1, A2; // thermophoresis
+  float dT_T0;
+  float cS;              // Saffman
+  float cM, cR;          // Magnus, particle rotation
+  float cG, cGref;       // settling per particle mass; fluid reference
+  float cRe, cD;         // drag: Re_d and Stokes rate coefficients
+  unsigned force_on;     // bit k set when force k has a non-zero coefficient
+};
+
+// ---- A-A access: read the nine populations of each lattice --------------
+template <bool ODD, class S>
+__device__ __forceinline__ void load_node(const StepParams& P,
+                                          const typename S::T* __restrict__ pop,
+                                          const float* __restrict__ d5, int x,
+                                          int y, float f[9], float p[9],
+                                          float g[9]) {
+  const long long n = (long long)y * P.px + x;
+  const long long pl = P.plane;
+  const bool xl = x == 0, xr = x == P.nx - 1, yb = y == 0, yt = y == P.ny - 1;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    if (!ODD) {
+      f[i] = S::ld(pop + pl * i + n, P.inv_scale[0]);
+      p[i] = S::ld(pop + pl * (9 + i) + n, P.inv_scale[1]);
+      g[i] = S::ld(pop + pl * (18 + i) + n, P.inv_scale[2]);
+    } else {
+      const bool outx = (ex(i) == 1 && xl) || (ex(i) == -1 && xr);
+      const bool outy = (ey(i) == 1 && yb) || (ey(i) == -1 && yt);
+      const bool out = outx || outy;
+      // inside: upstream node's slot opp(i); wall link: own slot i
+      const long long a = out ? (pl * i + n)
+                              : (pl * opp(i) + n - ex(i) - (long long)ey(i) * P.px);
+      f[i] = S::ld(pop + a, P.inv_scale[0]);
+      p[i] = S::ld(pop + pl * 9 + a, P.inv_scale[1]);
+      if (i == 0) {
+        g[i] = S::ld(pop + pl * 18 + a, P.inv_scale[2]);
+      } else if (outy) {
+        g[i] = d5[(long long)((ey(i) == 1 ? 0 : 3) + d5slot(i)) * P.px + x];
+      } else {
+        const float v = S::ld(pop + pl * 18 + a, P.inv_scale[2]);
+        g[i] = outx ? (xl ? wgt(i) : -wgt(i)) - v : v;
+      }
+    }
+  }
+}
+
+// ---- A-A access: write the post-collision populations --------------------
+template <bool ODD, class S>
+__device__ __forceinline__ void store_node(const StepParams& P,
+                                           typename S::T* __restrict__ pop,
+                                           float* __restrict__ d5, int x, int y,
+                                           const float f[9], const float p[9],
+                                           const float g[9]) {
+  const long long n = (long long)y * P.px + x;
+  const long long pl = P.plane;
+  const int nx = P.nx, ny = P.ny;
+  const bool xl = x == 0, xr = x == nx - 1, yb = y == 0, yt = y == ny - 1;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    if (!ODD) {
+      S::st(pop + pl * opp(i) + n, f[i], P.scale[0]);
+      S::st(pop + pl * (9 + opp(i)) + n, p[i], P.scale[1]);
+      S::st(pop + pl * (18 + opp(i)) + n, g[i], P.scale[2]);
+    } else {
+      const bool outx = (ex(i) == 1 && xr) || (ex(i) == -1 && xl);
+      const bool outy = (ey(i) == 1 && yt) || (ey(i) == -1 && yb);
+      const bool out = outx || outy;
+      const long long a = out ? (pl * opp(i) + n)
+                              : (pl * i + n + ex(i) + (long long)ey(i) * P.px);
+      S::st(pop + a, f[i], P.scale[0]);
+      S::st(pop + pl * 9 + a, p[i], P.scale[1]);
+      if (i == 0) {
+        S::st(pop + pl * 18 + a, g[i], P.scale[2]);
+      } else if (!out) {
+        S::st(pop + pl * 18 + a, g[i], P.scale[2]);
+        // the wall row takes the same value (copy of the adiabatic wall)
+        if ((ey(i) == 1 && yb) || (ey(i) == -1 && yt))
+          S::st(pop + pl * (18 + i) + n + ex(i), g[i], P.scale[2]);
+      } else if (!outy) {
+        // isothermal wall: anti-bounce-back into the own slot opp(i)
+        const float v = (ex(i) == -1 ? wgt(i) : -wgt(i)) - g[i];
+        S::st(pop + pl * 18 + a, v, P.scale[2]);
+        // corner: the wall row next to this one copies it
+        if (ey(opp(i)) == 1 && y == 1)
+          S::st(pop + pl * 18 + a - P.px, v, P.scale[2]);
+        if (ey(opp(i)) == -1 && y == ny - 2)
+          S::st(pop + pl * 18 + a + P.px, v, P.scale[2]);
+      }
+      // out through an adiabatic wall: the value leaves the domain
+    }
+  }
+  if (!ODD) {
+    // side buffer for the adiabatic copy of the next (odd) step
+    const long long px = P.px;
+    if (yb) {
+      d5[0 * px + x] = g[2];
+      if (!xr) d5[1 * px + x + 1] = g[5];
+      if (!xl) d5[2 * px + x - 1] = g[6];
+    }
+    if (y == 1) {
+      if (xl) d5[1 * px + 0] = wgt(5) - g[7];
+      if (xr) d5[2 * px + nx - 1] = -wgt(6) - g[8];
+    }
+    if (yt) {
+      d5[3 * px + x] = g[4];
+      if (!xr) d5[4 * px + x + 1] = g[8];
+      if (!xl) d5[5 * px + x - 1] = g[7];
+    }
+    if (y == ny - 2) {
+      if (xl) d5[4 * px + 0] = wgt(8) - g[6];
+      if (xr) d5[5 * px + nx - 1] = -wgt(7) - g[5];
+    }
+  }
+}
+
+// ---- BGK collision with forcing in deviation form (Eqs 18-19, 26-27) ------
+// h* = h + omega (h_eq - h) + 3 W_i e_i.F,
+// h_eq = W_i [d + a (3 e.u + 4.5 (e.u)^2 - 1.5 u^2)], with d = sum h the
+// deviation of the density and a the full density (for g: d = a = theta).
+__device__ __forceinline__ void collide(float h[9], float d, float a, float ux,
+                                        float uy, float omega, float Fx,
+                                        float Fy) {
+  const float base = d - 1.5f * a * (ux * ux + uy * uy);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const float eu = (float)ex(i) * ux + (float)ey(i) * uy;
+    const float heq = wgt(i) * (base + a * eu * (3.0f + 4.5f * eu));
+    const float s = 3.0f * wgt(i) * ((float)ex(i) * Fx + (float)ey(i) * Fy);
+    h[i] = fmaf(omega, heq - h[i], h[i]) + s;
+  }
+}
+
+struct NodeMoments {
+  float drf, jxf, jyf, drp, jxp, jyp, th;
+};
+
+__device__ __forceinline__ NodeMoments moments(const float f[9], const float p[9],
+                                               const float g[9]) {
+  NodeMoments m;
+  m.drf = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + (f[7] + f[8])));
+  m.jxf = (f[1] - f[3]) + ((f[5] - f[6]) + (f[8] - f[7]));
+  m.jyf = (f[2] - f[4]) + ((f[5] - f[8]) + (f[6] - f[7]));
+  m.drp = ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + (p[7] + p[8])));
+  m.jxp = (p[1] - p[3]) + ((p[5] - p[6]) + (p[8] - p[7]));
+  m.jyp = (p[2] - p[4]) + ((p[5] - p[8]) + (p[6] - p[7]));
+  m.th = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + (g[7] + g[8])));
+  return m;
+}
+
+// ---- one node: moments, properties, slip forces, collision ---------------
+// gphi, gth: central-difference gradients of the previous step's fields.
+// Returns the fields this step stores for the next step's gradients.
+__device__ __forceinline__ float2 node_update(const StepParams& P, float f[9],
+                                              float p[9], float g[9],
+                                              float gphix, float gphiy,
+                                              float gthx, float gthy) {
+  const NodeMoments m = moments(f, p, g);
+  // S1/S2: Eqs 29-32 (partial densities; mass-averaged mixture velocity)
+  const float rho_f = P.rho_f_ref + m.drf;
+  const float rho_p = P.rho_p_ref + m.drp;
+  const float irf = 1.0f / rho_f;
+  const float uxf = m.jxf * irf, uyf = m.jyf * irf;
+  const bool empty = !(rho_p > 1e-12f);
+  const float irp = empty ? 0.0f : 1.0f / rho_p;
+  const float uxp = empty ? uxf : m.jxp * irp;
+  const float uyp = empty ? uyf : m.jyp * irp;
+  const float rho_m = rho_f + rho_p;
+  const float irm = 1.0f / rho_m;
+  const float uxn = (m.jxf + m.jxp) * irm, uyn = (m.jyf + m.jyp) * irm;
+  const float th = m.th;
+
+  // S3: Eqs 7-11 as ratios to the base fluid; Eq 23 for tau_p; Eq 24
+  const float phi = rho_p * P.invR;
+  const float phic = fmaxf(phi, 0.0f);
+  const float r_rho = fmaf(phi, P.Rm1, 1.0f);
+  const float r_rhoc = fmaf(phi, P.crc, 1.0f);
+  const float r_beta = fmaf(phi, P.crb, 1.0f);
+  const float r_mu = fmaf(phi, fmaf(222.4f, phi, 4.93f), 1.0f);
+  const float r_k = fmaf(P.Ck, __powf(phic, 0.764f), 1.0f);
+  const float ir_rho = 1.0f / r_rho;
+  float tau_p = P.tau_f + P.tp_a * rho_m * fmaf(222.4f, phi, P.tp_b) * ir_rho;
+  tau_p = fminf(fmaxf(tau_p, 0.505f), 5.0f);
+  if (empty) tau_p = P.tau_f;
+  const float tau_th = fmaf(P.alpha3 * r_k, 1.0f / r_rhoc, 0.5f);
+
+  // S5: forces.  The fluid carries buoyancy (Eq 20) and the net weight of
+  // the particles relative to the uniform suspension; every interaction
+  // force acts on both lattices with opposite signs.
+  const float dp_true = m.drp + P.dref_p;          // rho_p - R phi0
+  const float Fbuoy = rho_m * r_beta * P.G_L * th;  // Eq 20, beta_ns of Eq 9
+  float Fpx = 0.0f, Fpy = 0.0f;
+  if (!empty) {
+    const unsigned on = P.force_on;
+    const float wx = uxf - uxp, wy = uyf - uyp;
+    const float wn = sqrtf(fmaf(wx, wx, wy * wy));
+    const float upn = sqrtf(fmaf(uxp, uxp, uyp * uyp));
+    const float r_mu2 = r_mu * r_mu;
+    float aix = 0.0f, aiy = 0.0f;  // interaction forces per particle mass
+    if (on & 2u) {  // Brownian, down the phi gradient
+      const float Tr = fmaf(P.dT_T0, th, 1.0f);
+      const float c = -P.cB * Tr * Tr / r_mu2;
+      aix = fmaf(c, gphix, aix);
+      aiy = fmaf(c, gphiy, aiy);
+    }
+    if (on & 4u) {  // thermophoresis, down the temperature gradient
+      const float Tr = fmaf(P.dT_T0, th, 1.0f);
+      const float ks = P.kfp * r_k;
+      const float CT = P.A2 * (ks + P.A1) / fmaf(2.0f, ks + P.A1, 1.0f);
+      const float c = -P.cT * CT * r_mu2 * ir_rho / Tr;
+      aix = fmaf(c, gthx, aix);
+      aiy = fmaf(c, gthy, aiy);
+    }
+    if (on & 8u) {  // Saffman lift, along the rotated slip
+      const float c = P.cS * sqrtf(r_mu * r_rho * upn);
+      aix = fmaf(-c, wy, aix);
+      aiy = fmaf(c, wx, aiy);
+    }
+    if (on & 16u) {  // Magnus (opposes the slip) + particle rotation
+      const float vmx = 0.5f * (uxf + uxp), vmy = 0.5f * (uyf + uyp);
+      const float cm = -0.5f * P.cM * sqrtf(fmaf(vmx, vmx, vmy * vmy));
+      const float iwn = wn > 0.0f ? 1.0f / wn : 0.0f;
+      const float cr = P.cR * r_mu * ir_rho * upn * iwn;
+      aix = fmaf(cm, wx, fmaf(-cr, wy, aix));
+      aiy = fmaf(cm, wy, fmaf(cr, wx, aiy));
+    }
+    const float aGy = -P.cG;  // settling per particle mass (0 when off)
+    if (on & 1u) {
+      // Drag integrated exactly over the step (stiff: kappa ~ 1e4).  Its
+      // mean combined with the other particle forces gives, without forming
+      // the large cancelling terms,
+      //   F^p = rho_p [phi1 (a_int + beta w) + beta phi2 Fext_f / rho_f
+      //               + a_G (r + phi1) / (1 + r)],
+      // r = rho_p/rho_f, kappa = beta (1 + r), phi1 = (1 - e^-kappa)/kappa,
+      // phi2 = (1 - phi1)/kappa, Fext_f the non-reacting fluid force.
+      const float r = rho_p * irf;
+      const float Red = P.cRe * wn / r_mu;
+      const float beta = P.cD * r_mu * fmaf(0.15f, __powf(Red, 0.687f), 1.0f);
+      const float kap = beta * (1.0f + r);
+      float ph1, ph2;
+      if (kap < 0.05f) {  // Taylor series, truncation < 1e-8
+        ph1 = fmaf(kap, fmaf(kap, fmaf(kap, -1.0f / 24.0f, 1.0f / 6.0f), -0.5f), 1.0f);
+        ph2 = fmaf(kap, fmaf(kap, fmaf(kap, -1.0f / 120.0f, 1.0f / 24.0f), -1.0f / 6.0f), 0.5f);
+      } else {
+        ph1 = -expm1f(-kap) / kap;
+        ph2 = (1.0f - ph1) / kap;
+      }
+      const float fext = Fbuoy + P.cGref;
+      Fpx = rho_p * ph1 * fmaf(beta, wx, aix);
+      Fpy = rho_p * fmaf(ph1, fmaf(beta, wy, aiy),
+                         fmaf(beta * ph2 * irf, fext, aGy * (r + ph1) / (1.0f + r)));
+    } else {
+      Fpx = rho_p * aix;
+      Fpy = rho_p * (aiy + aGy);
+    }
+  }
+  const float Ffx = -Fpx;
+  const float Ffy = fmaf(-P.cG, dp_true, Fbuoy) - Fpy;
+
+  // S6: collisions; f and p relax to their own velocities, g to u_ns
+  collide(f, m.drf, rho_f, uxf, uyf, P.omega_f, Ffx, Ffy);
+  collide(p, m.drp, rho_p, uxp, uyp, 1.0f / tau_p, Fpx, Fpy);
+  collide(g, th, th, uxn, uyn, 1.0f / tau_th, 0.0f, 0.0f);
+  return make_float2(m.drp * P.invR, th);
+}
+
+}  // namespace mclbm

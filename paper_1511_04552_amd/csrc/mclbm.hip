@@ -1,0 +1,859 @@
+// libmclbm: the fused three-lattice MCLBM time step for MI355X (gfx950) and
+// its C ABI (include/mclbm.h).
+//
+// Kernels
+//   k_init      initial equilibrium state (Eqs 26-27) and the lag field
+//   k_step      the fused hot path, one launch per time step: A-A load with
+//               streaming and walls (Eqs 34-36), moments (Eqs 29-32),
+//               properties (Eqs 7-11, 22-24), lagged gradients, slip forces
+//               (Table 1, Eqs 6, 20), BGK collision of three lattices
+//               (Eqs 18-19), A-A store
+//   k_nusselt   FP64 wall-Nusselt reduction
+//   k_residual  FP64 relative change of u_ns and theta (steady-state test)
+//   k_export    FP64 moments / populations of the current state
+//   k_copy      plain streaming copy, bandwidth and counter calibration
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/mclbm.h"
+#include "lbm_device.h"
+
+using namespace mclbm;
+
+// ===========================================================================
+// Kernels
+// ===========================================================================
+
+template <class S>
+__global__ __launch_bounds__(256) void k_init(StepParams P,
+                                              typename S::T* __restrict__ pop,
+                                              const double* __restrict__ dev_p,
+                                              double dev_f,
+                                              float2* __restrict__ d2prev) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  if (x >= P.nx || y >= P.ny) return;
+  const long long n = (long long)y * P.px + x;
+  const double dp = dev_p[(long long)y * P.nx + x];
+  float f[9], p[9], g[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const double w = (double)wgt(i);
+    f[i] = (float)(w * dev_f);
+    p[i] = (float)(w * dp);
+    g[i] = 0.0f;
+    S::st(pop + P.plane * i + n, f[i], P.scale[0]);
+    S::st(pop + P.plane * (9 + i) + n, p[i], P.scale[1]);
+    S::st(pop + P.plane * (18 + i) + n, g[i], P.scale[2]);
+  }
+  // the lag field holds what the first step would have stored
+  float fl[9], pl[9], gl[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    fl[i] = S::ld(pop + P.plane * i + n, P.inv_scale[0]);
+    pl[i] = S::ld(pop + P.plane * (9 + i) + n, P.inv_scale[1]);
+    gl[i] = S::ld(pop + P.plane * (18 + i) + n, P.inv_scale[2]);
+  }
+  const NodeMoments m = moments(fl, pl, gl);
+  d2prev[n] = make_float2(m.drp * P.invR, m.th);
+}
+
+template <bool ODD, class S>
+__global__ __launch_bounds__(256) void k_step(StepParams P,
+                                              typename S::T* __restrict__ pop,
+                                              const float2* __restrict__ d2p,
+                                              float2* __restrict__ d2c,
+                                              float* __restrict__ d5) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  if (x >= P.nx || y >= P.ny) return;
+  float f[9], p[9], g[9];
+  load_node<ODD, S>(P, pop, d5, x, y, f, p, g);
+
+  // S4: central differences of the previous step's (phi, theta); zero-flux
+  // mirror ghosts for phi on all walls and for theta on the adiabatic walls,
+  // linear ghosts 2 theta_w - theta through the isothermal walls.
+  const long long n = (long long)y * P.px + x;
+  const bool xl = x == 0, xr = x == P.nx - 1, yb = y == 0, yt = y == P.ny - 1;
+  float2 c = make_float2(0.0f, 0.0f);
+  if (xl || xr || yb || yt) c = d2p[n];
+  const float2 vE = xr ? c : d2p[n + 1];
+  const float2 vW = xl ? c : d2p[n - 1];
+  const float2 vN = yt ? c : d2p[n + P.px];
+  const float2 vS = yb ? c : d2p[n - P.px];
+  const float thE = xr ? (-1.0f - c.y) : vE.y;
+  const float thW = xl ? (1.0f - c.y) : vW.y;
+  const float gphix = 0.5f * (vE.x - vW.x), gphiy = 0.5f * (vN.x - vS.x);
+  const float gthx = 0.5f * (thE - thW), gthy = 0.5f * (vN.y - vS.y);
+
+  const float2 keep = node_update(P, f, p, g, gphix, gphiy, gthx, gthy);
+  store_node<ODD, S>(P, pop, d5, x, y, f, p, g);
+  d2c[n] = keep;
+}
+
+// Block-wide FP64 sum; wave64 shuffles then one LDS slot per wave.
+__device__ double block_sum(double v, double* lds) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) lds[wid] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int w = 0; w < nw; ++w) r += lds[w];
+  }
+  return r;
+}
+
+template <bool ODD, class S>
+__global__ __launch_bounds__(256) void k_nusselt(StepParams P,
+                                                 const typename S::T* __restrict__ pop,
+                                                 const float* __restrict__ d5,
+                                                 double rho_p_ref, double R,
+                                                 double Ck,
+                                                 double* __restrict__ out) {
+  __shared__ double lds[4];
+  const int nx = P.nx, ny = P.ny;
+  double sh = 0.0, sc = 0.0, sk = 0.0, bad = 0.0;
+  for (int y = threadIdx.x; y < ny; y += blockDim.x) {
+    const int xs[4] = {0, 1, nx - 2, nx - 1};
+    double th[4];
+    double rp = rho_p_ref;
+    for (int q = 0; q < 4; ++q) {
+      float f[9], p[9], g[9];
+      load_node<ODD, S>(P, const_cast<typename S::T*>(pop), d5, xs[q], y, f, p, g);
+      double t = 0.0;
+      for (int i = 0; i < 9; ++i) t += (double)g[i];
+      th[q] = t;
+      if (q == 0)
+        for (int i = 0; i < 9; ++i) rp += (double)p[i];
+    }
+    double phi = rp / R;
+    if (phi < 0.0) phi = 0.0;
+    const double rk = 1.0 + Ck * pow(phi, 0.764);
+    const double gh = -(double)nx * (9.0 * th[0] - th[1] - 4.0) / 3.0;
+    const double gc = (double)nx * (9.0 * th[3] - th[2] + 4.0) / 3.0;
+    sh += gh;
+    sc += gc;
+    sk += rk * gh;
+    if (!isfinite(gh) || !isfinite(gc)) bad = 1.0;
+  }
+  sh = block_sum(sh, lds);
+  sc = block_sum(sc, lds);
+  sk = block_sum(sk, lds);
+  bad = block_sum(bad, lds);
+  if (threadIdx.x == 0) {
+    out[0] = sh / ny;
+    out[1] = sc / ny;
+    out[2] = sk / ny;
+    out[3] = bad;
+  }
+}
+
+// Per-block partial sums of |u - u_ref|^2, |u|^2, (theta - theta_ref)^2,
+// theta^2 and a non-finite count; the snapshot is replaced by the state.
+template <bool ODD, class S>
+__global__ __launch_bounds__(256) void k_residual(StepParams P,
+                                                  const typename S::T* __restrict__ pop,
+                                                  const float* __restrict__ d5,
+                                                  double rho_f_ref, double rho_p_ref,
+                                                  double* __restrict__ snap,
+                                                  double* __restrict__ partial) {
+  __shared__ double lds[4];
+  const long long nn = (long long)P.nx * P.ny;
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  double du = 0.0, un = 0.0, dt = 0.0, tn = 0.0, bad = 0.0;
+  if (k < nn) {
+    const int x = (int)(k % P.nx), y = (int)(k / P.nx);
+    float f[9], p[9], g[9];
+    load_node<ODD, S>(P, const_cast<typename S::T*>(pop), d5, x, y, f, p, g);
+    double rf = rho_f_ref, rp = rho_p_ref, jx = 0.0, jy = 0.0, th = 0.0;
+    for (int i = 0; i < 9; ++i) {
+      rf += (double)f[i];
+      rp += (double)p[i];
+      jx += (double)ex(i) * ((double)f[i] + (double)p[i]);
+      jy += (double)ey(i) * ((double)f[i] + (double)p[i]);
+      th += (double)g[i];
+    }
+    const double ux = jx / (rf + rp), uy = jy / (rf + rp);
+    const double ox = snap[k], oy = snap[nn + k], ot = snap[2 * nn + k];
+    du = (ux - ox) * (ux - ox) + (uy - oy) * (uy - oy);
+    un = ux * ux + uy * uy;
+    dt = (th - ot) * (th - ot);
+    tn = th * th;
+    if (!isfinite(ux) || !isfinite(uy) || !isfinite(th)) bad = 1.0;
+    snap[k] = ux;
+    snap[nn + k] = uy;
+    snap[2 * nn + k] = th;
+  }
+  du = block_sum(du, lds);
+  un = block_sum(un, lds);
+  dt = block_sum(dt, lds);
+  tn = block_sum(tn, lds);
+  bad = block_sum(bad, lds);
+  if (threadIdx.x == 0) {
+    double* o = partial + 5 * (long long)blockIdx.x;
+    o[0] = du; o[1] = un; o[2] = dt; o[3] = tn; o[4] = bad;
+  }
+}
+
+// Fixed-order sum of the per-block partials (deterministic).
+__global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__ partial,
+                                                      int nblocks,
+                                                      double* __restrict__ out) {
+  __shared__ double lds[4];
+  for (int q = 0; q < 5; ++q) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) s += partial[5 * (long long)b + q];
+    s = block_sum(s, lds);
+    if (threadIdx.x == 0) out[q] = s;
+  }
+}
+
+// Snapshot of the initial state for the first residual call.
+template <bool ODD, class S>
+__global__ __launch_bounds__(256) void k_export(StepParams P,
+                                                const typename S::T* __restrict__ pop,
+                                                const float* __restrict__ d5,
+                                                double rho_f_ref, double rho_p_ref,
+                                                double invR, unsigned mask,
+                                                double* __restrict__ out) {
+  const long long nn = (long long)P.nx * P.ny;
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nn) return;
+  const int x = (int)(k % P.nx), y = (int)(k / P.nx);
+  float f[9], p[9], g[9];
+  load_node<ODD, S>(P, const_cast<typename S::T*>(pop), d5, x, y, f, p, g);
+  double rf = rho_f_ref, rp = rho_p_ref, jxf = 0, jyf = 0, jxp = 0, jyp = 0, th = 0;
+  for (int i = 0; i < 9; ++i) {
+    rf += (double)f[i];
+    rp += (double)p[i];
+    jxf += (double)ex(i) * (double)f[i];
+    jyf += (double)ey(i) * (double)f[i];
+    jxp += (double)ex(i) * (double)p[i];
+    jyp += (double)ey(i) * (double)p[i];
+    th += (double)g[i];
+  }
+  const double uxf = jxf / rf, uyf = jyf / rf;
+  const bool empty = !(rp > 1e-12);
+  const double v[9] = {rf, uxf, uyf, rp * invR,
+                       empty ? uxf : jxp / rp, empty ? uyf : jyp / rp, th,
+                       (jxf + jxp) / (rf + rp), (jyf + jyp) / (rf + rp)};
+  int slot = 0;
+  for (int b = 0; b < 9; ++b) {
+    if ((mask >> b) & 1u) {
+      out[(long long)slot * nn + k] = v[b];
+      ++slot;
+    }
+  }
+}
+
+// Populations after streaming with the storage shift added back; q < 0
+// writes all 27 planes, otherwise only plane q (lattice q / 9, direction
+// q % 9) into out[0 .. nx*ny).
+template <bool ODD, class S>
+__global__ __launch_bounds__(256) void k_export_pops(StepParams P,
+                                                     const typename S::T* __restrict__ pop,
+                                                     const float* __restrict__ d5,
+                                                     double rho_f_ref, double rho_p_ref,
+                                                     int q, double* __restrict__ out) {
+  const long long nn = (long long)P.nx * P.ny;
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nn) return;
+  const int x = (int)(k % P.nx), y = (int)(k / P.nx);
+  float f[9], p[9], g[9];
+  load_node<ODD, S>(P, const_cast<typename S::T*>(pop), d5, x, y, f, p, g);
+  for (int i = 0; i < 9; ++i) {
+    const double w = (double)wgt(i);
+    const double vf = (double)f[i] + w * rho_f_ref;
+    const double vp = (double)p[i] + w * rho_p_ref;
+    const double vg = (double)g[i];
+    if (q < 0) {
+      out[(long long)i * nn + k] = vf;
+      out[(long long)(9 + i) * nn + k] = vp;
+      out[(long long)(18 + i) * nn + k] = vg;
+    } else if (q == i) {
+      out[k] = vf;
+    } else if (q == 9 + i) {
+      out[k] = vp;
+    } else if (q == 18 + i) {
+      out[k] = vg;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_copy(float4* __restrict__ dst,
+                                              const float4* __restrict__ src,
+                                              long long n) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride)
+    dst[k] = src[k];
+}
+
+// ===========================================================================
+// Host side
+// ===========================================================================
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(MCLBM_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr)                                  \
+  do {                                                 \
+    hipError_t e_ = (expr);                            \
+    if (e_ != hipSuccess) return hip_fail(e_, #expr);  \
+  } while (0)
+
+// Physical constants (SI).
+constexpr double kBoltzmann = 1.380649e-23;
+constexpr double kGravity = 9.81;
+constexpr double kPi = 3.14159265358979323846;
+// Table 1: thermophoresis C_S, C_t, C_m; Saffman K_S.
+constexpr double kCs = 1.17, kCt = 2.18, kCm = 1.14, kKs = 81.2;
+
+struct Derived {
+  double v[MCLBM_D_COUNT];
+};
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+  int px;
+  long long plane;
+  size_t off_pop, off_d2, off_d5, off_snap, off_part, off_res, off_stage, total;
+  int red_blocks;
+};
+
+int storage_bytes(int storage) { return storage == MCLBM_FP32S ? 4 : 2; }
+
+Layout make_layout(const mclbm_config& c) {
+  Layout L{};
+  L.px = (c.nx + 63) / 64 * 64;
+  L.plane = (long long)L.px * c.ny;
+  const long long nn = (long long)c.nx * c.ny;
+  size_t off = 0;
+  L.off_pop = off;
+  off = align_up(off + (size_t)27 * L.plane * storage_bytes(c.storage));
+  L.off_d2 = off;
+  off = align_up(off + (size_t)2 * L.plane * sizeof(float2));
+  L.off_d5 = off;
+  off = align_up(off + (size_t)6 * L.px * sizeof(float));
+  L.off_snap = off;
+  off = align_up(off + (size_t)3 * nn * sizeof(double));
+  L.red_blocks = (int)((nn + 255) / 256);
+  L.off_part = off;
+  off = align_up(off + (size_t)5 * L.red_blocks * sizeof(double));
+  L.off_res = off;
+  off = align_up(off + 16 * sizeof(double));
+  L.off_stage = off;
+  off = align_up(off + (size_t)nn * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+int validate(const mclbm_config* c) {
+  if (!c) return fail(MCLBM_EINVAL, "config is NULL");
+  if (c->nx < 4 || c->ny < 4 || c->nx > 65536 || c->ny > 65536)
+    return fail(MCLBM_EINVAL, "nx and ny must lie in [4, 65536]");
+  if (!std::isfinite(c->Ra) || c->Ra < 0.0) return fail(MCLBM_EINVAL, "Ra must be finite and >= 0");
+  if (!finite_pos(c->Pr)) return fail(MCLBM_EINVAL, "Pr must be > 0");
+  if (!std::isfinite(c->phi0) || c->phi0 < 0.0 || c->phi0 > 0.1)
+    return fail(MCLBM_EINVAL, "phi0 must lie in [0, 0.1]");
+  if (!finite_pos(c->dp_m)) return fail(MCLBM_EINVAL, "dp_m must be > 0");
+  if (!std::isfinite(c->tau_f) || (c->tau_f > 0.0 && c->tau_f <= 0.5))
+    return fail(MCLBM_EINVAL, "tau_f must be > 0.5 (or <= 0 for automatic)");
+  if (!finite_pos(c->dT_K) || !finite_pos(c->T0_K)) return fail(MCLBM_EINVAL, "dT_K and T0_K must be > 0");
+  if (!(c->dT_K < 2.0 * c->T0_K)) return fail(MCLBM_EINVAL, "dT_K must be below 2 T0_K");
+  const mclbm_material& f = c->fluid;
+  const mclbm_material& p = c->particle;
+  if (!finite_pos(f.rho) || !finite_pos(f.cp) || !finite_pos(f.k) || !finite_pos(f.beta) ||
+      !finite_pos(f.mu) || !finite_pos(f.d_mol))
+    return fail(MCLBM_EINVAL, "fluid properties must be > 0");
+  if (!finite_pos(p.rho) || !finite_pos(p.cp) || !finite_pos(p.k) || !std::isfinite(p.beta) || p.beta < 0.0)
+    return fail(MCLBM_EINVAL, "particle rho, cp, k must be > 0 and beta >= 0");
+  if (c->force_mask > MCLBM_F_ALL) return fail(MCLBM_EINVAL, "unknown force bits");
+  for (int k = 0; k < 6; ++k)
+    if (!std::isfinite(c->force_scale[k])) return fail(MCLBM_EINVAL, "force_scale must be finite");
+  if (!std::isfinite(c->phi_perturb_amp) || c->phi_perturb_amp < 0.0)
+    return fail(MCLBM_EINVAL, "phi_perturb_amp must be >= 0");
+  if (c->storage != MCLBM_FP32S && c->storage != MCLBM_FP16S && c->storage != MCLBM_BF16S)
+    return fail(MCLBM_EINVAL, "unknown storage type");
+  if (c->storage != MCLBM_FP32S)
+    return fail(MCLBM_EUNSUPPORTED, "16-bit population storage is not available in this build");
+  const int bx = c->block_x == 0 ? 64 : c->block_x;
+  const int by = c->block_y == 0 ? 4 : c->block_y;
+  if (!(bx == 32 || bx == 64 || bx == 128 || bx == 256) || by < 1 ||
+      !(bx * by == 64 || bx * by == 128 || bx * by == 256))
+    return fail(MCLBM_EINVAL, "block shape must have block_x in {32,64,128,256} and 64..256 threads");
+  return MCLBM_OK;
+}
+
+// Lattice units from Ra, Pr and tau_f: Eq 22 gives the lattice viscosity,
+// Eq 16 (with base-fluid properties) the physical cavity width.
+void derive(const mclbm_config& c, Derived& d) {
+  double* v = d.v;
+  const double nu_f = c.fluid.mu / c.fluid.rho;
+  const double alpha_f = nu_f / c.Pr;
+  const double N = (double)c.nx;
+  double nu_L;
+  if (c.tau_f > 0.0) {
+    nu_L = (c.tau_f - 0.5) / 3.0;
+  } else {
+    // automatic: free-fall velocity sqrt(Ra nu alpha)/N at most 0.1 c_s
+    const double cap = 0.1 / std::sqrt(3.0);
+    const double s = std::sqrt(c.Ra / c.Pr) / N;  // free fall per unit nu
+    nu_L = (0.1 * s > cap) ? cap / s : 0.1;
+  }
+  const double alpha_L = nu_L / c.Pr;
+  const double H = c.Ra > 0.0
+                       ? std::cbrt(c.Ra * nu_f * alpha_f / (kGravity * c.fluid.beta * c.dT_K))
+                       : 0.01;
+  const double dx = H / N;
+  const double dt = nu_L * dx * dx / nu_f;
+  const double R = c.particle.rho / c.fluid.rho;
+  // Eq 10b at T0, Eq 10a constant with the ratio k_p/k_f
+  const double Re = c.fluid.rho * kBoltzmann * c.T0_K /
+                    (3.0 * kPi * c.fluid.mu * c.fluid.mu * c.fluid.d_mol);
+  const double Ck = 64.7 * std::pow(c.fluid.d_mol / c.dp_m, 0.369) *
+                    std::pow(c.particle.k / c.fluid.k, 0.7476) * std::pow(c.Pr, 0.995) *
+                    std::pow(Re, 1.2321);
+  v[MCLBM_D_NU_L] = nu_L;
+  v[MCLBM_D_ALPHA_L] = alpha_L;
+  v[MCLBM_D_H] = H;
+  v[MCLBM_D_DX] = dx;
+  v[MCLBM_D_DT] = dt;
+  v[MCLBM_D_G_L] = c.Ra * nu_L * alpha_L / (N * N * N);
+  v[MCLBM_D_GRAV_L] = kGravity * dt * dt / dx;
+  v[MCLBM_D_CK] = Ck;
+  v[MCLBM_D_R] = R;
+  v[MCLBM_D_TAU_F] = 3.0 * nu_L + 0.5;
+  v[MCLBM_D_RHOC_RATIO] = (c.particle.rho * c.particle.cp) / (c.fluid.rho * c.fluid.cp);
+  v[MCLBM_D_BETA_RATIO] = c.particle.beta / c.fluid.beta;
+  v[MCLBM_D_RHO_F0] = 1.0 - c.phi0;
+  v[MCLBM_D_RHO_P0] = R * c.phi0;
+  v[MCLBM_D_NU_F] = nu_f;
+  v[MCLBM_D_ALPHA_F] = alpha_f;
+}
+
+// Per-node coefficients of the fused step in lattice units (FP32 kernarg).
+StepParams make_params(const mclbm_config& c, const Derived& D, const Layout& L) {
+  const double* v = D.v;
+  StepParams P{};
+  P.nx = c.nx;
+  P.ny = c.ny;
+  P.px = L.px;
+  P.plane = L.plane;
+  for (int l = 0; l < 3; ++l) {
+    P.scale[l] = 1.0f;
+    P.inv_scale[l] = 1.0f;
+  }
+  const double R = v[MCLBM_D_R], dx = v[MCLBM_D_DX], dt = v[MCLBM_D_DT], H = v[MCLBM_D_H];
+  const double tau_f = v[MCLBM_D_TAU_F];
+  const float rf_ref = (float)v[MCLBM_D_RHO_F0];
+  const float rp_ref = (float)v[MCLBM_D_RHO_P0];
+  P.rho_f_ref = rf_ref;
+  P.rho_p_ref = rp_ref;
+  P.dref_p = (float)((double)rp_ref - v[MCLBM_D_RHO_P0]);
+  P.tau_f = (float)tau_f;
+  P.omega_f = (float)(1.0 / tau_f);
+  P.invR = (float)(1.0 / R);
+  P.Rm1 = (float)(R - 1.0);
+  P.crc = (float)(v[MCLBM_D_RHOC_RATIO] - 1.0);
+  P.crb = (float)(v[MCLBM_D_BETA_RATIO] - 1.0);
+  P.Ck = (float)v[MCLBM_D_CK];
+  P.alpha3 = (float)(3.0 * v[MCLBM_D_ALPHA_L]);
+  // Eq 23 solved for tau_p without cancellation:
+  // tau_p - tau_f = (tau_f - 1/2) (r_mu - r_rho) / (r_rho rbar_p), with
+  // (r_mu - r_rho)/rbar_p = (rho_m/R) (4.93 - (R - 1) + 222.4 phi).
+  P.tp_a = (float)((tau_f - 0.5) / R);
+  P.tp_b = (float)(4.93 - (R - 1.0));
+  P.G_L = (float)v[MCLBM_D_G_L];
+
+  double s[6];
+  for (int k = 0; k < 6; ++k) s[k] = ((c.force_mask >> k) & 1u) ? c.force_scale[k] : 0.0;
+  const double d = c.dp_m;
+  const double Vp = kPi * d * d * d / 6.0, Ap = kPi * d * d, mp = c.particle.rho * Vp;
+  const double mu = c.fluid.mu, rho = c.fluid.rho;
+  const double dtdx2 = dt * dt / (dx * dx);
+  // Brownian: rho_p D_B A_p v_B / m_p = 8 kB^2 T^2 / (pi^2 mu^2 d^4) per grad phi
+  P.cB = (float)(s[1] * 8.0 * kBoltzmann * kBoltzmann * c.T0_K * c.T0_K /
+                 (kPi * kPi * mu * mu * d * d * d * d) * dtdx2);
+  // thermophoresis: mu_ns d v_T / m_p with v_T = C_T (mu/rho)_ns grad T / T
+  P.cT = (float)(s[2] * mu * mu * d * c.dT_K / (mp * rho * c.T0_K) * dtdx2);
+  const double Kn = c.fluid.d_mol / d;
+  P.kfp = (float)(c.fluid.k / c.particle.k);
+  P.A1 = (float)(kCt * Kn);
+  P.A2 = (float)(6.0 * kPi * kCs / (1.0 + 3.0 * kCm * Kn));
+  P.dT_T0 = (float)(c.dT_K / c.T0_K);
+  // Saffman: (K_S/4) mu |w| d^2 sqrt(rho gdot / mu) / m_p, gdot = 8 |v_p| / H
+  P.cS = (float)(s[3] * (kKs / 4.0) * d * d * dt * std::sqrt(8.0 * mu * rho * dx / (dt * H)) / mp);
+  // Magnus: (|v_M|/d)(v_p - v_M); rotation: mu rho_p gdot A_p / (rho m_p)
+  P.cM = (float)(s[4] * dx / d);
+  P.cR = (float)(s[4] * 8.0 * R * mu * Ap * dt / (H * mp));
+  // settling -(1 - rho_f/rho_p) g; fluid reference R phi0 (1 - 1/R) g
+  P.cG = (float)(s[5] * (1.0 - 1.0 / R) * v[MCLBM_D_GRAV_L]);
+  P.cGref = (float)(s[5] * (1.0 - 1.0 / R) * v[MCLBM_D_GRAV_L] * v[MCLBM_D_RHO_P0]);
+  // drag: Re_d = rho_p d |w| / mu_ns, beta = 18 mu_ns (1 + 0.15 Re^0.687)/(rho_p d^2)
+  P.cRe = (float)(c.particle.rho * d * (dx / dt) / mu);
+  P.cD = (float)(s[0] * 18.0 * mu * dt / (c.particle.rho * d * d));
+  unsigned on = 0;
+  if (P.cD != 0.0f) on |= 1u;
+  if (P.cB != 0.0f) on |= 2u;
+  if (P.cT != 0.0f) on |= 4u;
+  if (P.cS != 0.0f) on |= 8u;
+  if (P.cM != 0.0f || P.cR != 0.0f) on |= 16u;
+  if (P.cG != 0.0f) on |= 32u;
+  P.force_on = on;
+  return P;
+}
+
+}  // namespace
+
+struct mclbm_cavity {
+  mclbm_config cfg;
+  std::vector<double> xi;
+  hipStream_t stream;
+  char* base;
+  size_t bytes;
+  Layout L;
+  Derived D;
+  StepParams P;
+  int64_t t;
+  dim3 block, grid;
+  std::vector<double> host_dev_p;  // initial phi deviations (kept for async copy)
+
+  typename StorF32::T* pop() { return reinterpret_cast<float*>(base + L.off_pop); }
+  float2* d2(int k) { return reinterpret_cast<float2*>(base + L.off_d2) + (size_t)k * L.plane; }
+  float* d5() { return reinterpret_cast<float*>(base + L.off_d5); }
+  double* snap() { return reinterpret_cast<double*>(base + L.off_snap); }
+  double* part() { return reinterpret_cast<double*>(base + L.off_part); }
+  double* res() { return reinterpret_cast<double*>(base + L.off_res); }
+  double* stage() { return reinterpret_cast<double*>(base + L.off_stage); }
+};
+
+namespace {
+
+int launch_check(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, what);
+  return MCLBM_OK;
+}
+
+int enqueue_init(mclbm_cavity* c) {
+  const mclbm_config& cfg = c->cfg;
+  const long long nn = (long long)cfg.nx * cfg.ny;
+  const double R = c->D.v[MCLBM_D_R];
+  const double rp_ref = (double)c->P.rho_p_ref;
+  c->host_dev_p.assign((size_t)nn, 0.0);
+  for (long long k = 0; k < nn; ++k) {
+    double phi = cfg.phi0;
+    if (!c->xi.empty()) phi += cfg.phi_perturb_amp * c->xi[(size_t)k];
+    if (phi < 0.0) phi = 0.0;
+    c->host_dev_p[(size_t)k] = R * phi - rp_ref;
+  }
+  const double dev_f = c->D.v[MCLBM_D_RHO_F0] - (double)c->P.rho_f_ref;
+  HIP_TRY(hipMemcpyAsync(c->stage(), c->host_dev_p.data(), (size_t)nn * sizeof(double),
+                         hipMemcpyHostToDevice, c->stream));
+  k_init<StorF32><<<c->grid, c->block, 0, c->stream>>>(c->P, c->pop(), c->stage(), dev_f, c->d2(1));
+  int rc = launch_check("k_init");
+  if (rc) return rc;
+  HIP_TRY(hipMemsetAsync(c->d5(), 0, (size_t)6 * c->L.px * sizeof(float), c->stream));
+  c->t = 0;
+  // snapshot of the initial state for the first residual call
+  const unsigned rb = (unsigned)c->L.red_blocks;
+  k_residual<false, StorF32><<<rb, 256, 0, c->stream>>>(
+      c->P, c->pop(), c->d5(), (double)c->P.rho_f_ref, (double)c->P.rho_p_ref, c->snap(), c->part());
+  rc = launch_check("k_residual");
+  if (rc) return rc;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return MCLBM_OK;
+}
+
+int setup_cavity(mclbm_cavity* c) {
+  derive(c->cfg, c->D);
+  c->L = make_layout(c->cfg);
+  c->P = make_params(c->cfg, c->D, c->L);
+  const int bx = c->cfg.block_x == 0 ? 64 : c->cfg.block_x;
+  const int by = c->cfg.block_y == 0 ? 4 : c->cfg.block_y;
+  c->block = dim3(bx, by, 1);
+  c->grid = dim3((c->cfg.nx + bx - 1) / bx, (c->cfg.ny + by - 1) / by, 1);
+  return MCLBM_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+
+extern "C" {
+
+void mclbm_config_defaults(mclbm_config* c) {
+  if (!c) return;
+  std::memset(c, 0, sizeof(*c));
+  c->nx = c->ny = 64;
+  c->Ra = 1e3;
+  c->Pr = 6.2;
+  c->phi0 = 0.01;
+  c->dp_m = 100e-9;
+  c->tau_f = 0.8;
+  c->dT_K = 10.0;
+  c->T0_K = 300.0;
+  c->force_mask = MCLBM_F_ALL;
+  for (int k = 0; k < 6; ++k) c->force_scale[k] = 1.0;
+  c->phi_perturb_amp = 1e-6;
+  // water and alumina near 300 K
+  c->fluid = mclbm_material{997.1, 4179.0, 0.613, 2.1e-4, 8.9e-4, 0.384e-9};
+  c->particle = mclbm_material{3970.0, 765.0, 40.0, 8.5e-6, 0.0, 0.0};
+  c->storage = MCLBM_FP32S;
+  c->block_x = 0;
+  c->block_y = 0;
+}
+
+size_t mclbm_device_bytes(const mclbm_config* cfg) {
+  if (validate(cfg) != MCLBM_OK) return 0;
+  return make_layout(*cfg).total;
+}
+
+int mclbm_derive_constants(const mclbm_config* cfg, double* out, int n) {
+  int rc = validate(cfg);
+  if (rc) return rc;
+  if (!out || n < MCLBM_D_COUNT) return fail(MCLBM_EINVAL, "output too small");
+  Derived d;
+  derive(*cfg, d);
+  std::memcpy(out, d.v, sizeof(d.v));
+  return MCLBM_OK;
+}
+
+int mclbm_create(const mclbm_config* cfg, const double* xi_host, void* dev_buf, size_t bytes,
+                 void* stream, mclbm_cavity** out) {
+  if (!out) return fail(MCLBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = validate(cfg);
+  if (rc) return rc;
+  if (!dev_buf) return fail(MCLBM_EINVAL, "dev_buf is NULL");
+  if (reinterpret_cast<uintptr_t>(dev_buf) % kAlign != 0)
+    return fail(MCLBM_EINVAL, "dev_buf must be 256-byte aligned");
+  const size_t need = make_layout(*cfg).total;
+  if (bytes < need)
+    return fail(MCLBM_ENOMEM, "device buffer too small: need " + std::to_string(need) + " bytes");
+  mclbm_cavity* c = new (std::nothrow) mclbm_cavity();
+  if (!c) return fail(MCLBM_ENOMEM, "host allocation failed");
+  c->cfg = *cfg;
+  if (xi_host) c->xi.assign(xi_host, xi_host + (size_t)cfg->nx * cfg->ny);
+  c->stream = reinterpret_cast<hipStream_t>(stream);
+  c->base = reinterpret_cast<char*>(dev_buf);
+  c->bytes = bytes;
+  setup_cavity(c);
+  rc = enqueue_init(c);
+  if (rc) {
+    delete c;
+    return rc;
+  }
+  *out = c;
+  return MCLBM_OK;
+}
+
+int mclbm_set_properties(mclbm_cavity* c, double Ra, double phi0, double dp_m) {
+  if (!c) return fail(MCLBM_EINVAL, "cavity is NULL");
+  mclbm_config nc = c->cfg;
+  nc.Ra = Ra;
+  nc.phi0 = phi0;
+  nc.dp_m = dp_m;
+  int rc = validate(&nc);
+  if (rc) return rc;
+  c->cfg = nc;
+  setup_cavity(c);
+  return enqueue_init(c);
+}
+
+int mclbm_reset(mclbm_cavity* c) {
+  if (!c) return fail(MCLBM_EINVAL, "cavity is NULL");
+  return enqueue_init(c);
+}
+
+int mclbm_step(mclbm_cavity* c, int64_t nsteps) {
+  if (!c) return fail(MCLBM_EINVAL, "cavity is NULL");
+  if (nsteps < 0) return fail(MCLBM_EINVAL, "nsteps must be >= 0");
+  for (int64_t s = 0; s < nsteps; ++s) {
+    const int k = (int)(c->t & 1);
+    if (k == 0)
+      k_step<false, StorF32><<<c->grid, c->block, 0, c->stream>>>(c->P, c->pop(), c->d2(1), c->d2(0), c->d5());
+    else
+      k_step<true, StorF32><<<c->grid, c->block, 0, c->stream>>>(c->P, c->pop(), c->d2(0), c->d2(1), c->d5());
+    int rc = launch_check("k_step");
+    if (rc) return rc;
+    c->t += 1;
+  }
+  return MCLBM_OK;
+}
+
+int64_t mclbm_time(const mclbm_cavity* c) { return c ? c->t : -1; }
+
+int mclbm_export_moments(mclbm_cavity* c, uint32_t mask, double* dev_out, size_t n_doubles) {
+  if (!c || !dev_out) return fail(MCLBM_EINVAL, "NULL argument");
+  if (mask == 0 || mask > MCLBM_ALL_FIELDS) return fail(MCLBM_EINVAL, "bad field mask");
+  const long long nn = (long long)c->cfg.nx * c->cfg.ny;
+  const int nf = __builtin_popcount(mask);
+  if (n_doubles < (size_t)nf * nn) return fail(MCLBM_EINVAL, "output too small");
+  const unsigned nb = (unsigned)((nn + 255) / 256);
+  const double rf = (double)c->P.rho_f_ref, rp = (double)c->P.rho_p_ref;
+  const double invR = 1.0 / c->D.v[MCLBM_D_R];
+  if (c->t & 1)
+    k_export<true, StorF32><<<nb, 256, 0, c->stream>>>(c->P, c->pop(), c->d5(), rf, rp, invR, mask, dev_out);
+  else
+    k_export<false, StorF32><<<nb, 256, 0, c->stream>>>(c->P, c->pop(), c->d5(), rf, rp, invR, mask, dev_out);
+  return launch_check("k_export");
+}
+
+int mclbm_read_moments(mclbm_cavity* c, uint32_t mask, double* host_out, size_t n_doubles) {
+  if (!c || !host_out) return fail(MCLBM_EINVAL, "NULL argument");
+  if (mask == 0 || mask > MCLBM_ALL_FIELDS) return fail(MCLBM_EINVAL, "bad field mask");
+  const long long nn = (long long)c->cfg.nx * c->cfg.ny;
+  if (n_doubles < (size_t)__builtin_popcount(mask) * nn) return fail(MCLBM_EINVAL, "output too small");
+  int slot = 0;
+  for (int b = 0; b < 9; ++b) {
+    if (!((mask >> b) & 1u)) continue;
+    int rc = mclbm_export_moments(c, 1u << b, c->stage(), (size_t)nn);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(host_out + (size_t)slot * nn, c->stage(), (size_t)nn * sizeof(double),
+                           hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    ++slot;
+  }
+  return MCLBM_OK;
+}
+
+namespace {
+int export_pops(mclbm_cavity* c, int q, double* dev_out) {
+  const long long nn = (long long)c->cfg.nx * c->cfg.ny;
+  const unsigned nb = (unsigned)((nn + 255) / 256);
+  const double rf = (double)c->P.rho_f_ref, rp = (double)c->P.rho_p_ref;
+  if (c->t & 1)
+    k_export_pops<true, StorF32><<<nb, 256, 0, c->stream>>>(c->P, c->pop(), c->d5(), rf, rp, q, dev_out);
+  else
+    k_export_pops<false, StorF32><<<nb, 256, 0, c->stream>>>(c->P, c->pop(), c->d5(), rf, rp, q, dev_out);
+  return launch_check("k_export_pops");
+}
+}  // namespace
+
+int mclbm_export_populations(mclbm_cavity* c, double* dev_out, size_t n_doubles) {
+  if (!c || !dev_out) return fail(MCLBM_EINVAL, "NULL argument");
+  const long long nn = (long long)c->cfg.nx * c->cfg.ny;
+  if (n_doubles < (size_t)27 * nn) return fail(MCLBM_EINVAL, "output too small");
+  return export_pops(c, -1, dev_out);
+}
+
+int mclbm_read_populations(mclbm_cavity* c, double* host_out, size_t n_doubles) {
+  if (!c || !host_out) return fail(MCLBM_EINVAL, "NULL argument");
+  const long long nn = (long long)c->cfg.nx * c->cfg.ny;
+  if (n_doubles < (size_t)27 * nn) return fail(MCLBM_EINVAL, "output too small");
+  for (int q = 0; q < 27; ++q) {  // one plane at a time through the stage
+    int rc = export_pops(c, q, c->stage());
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(host_out + (size_t)q * nn, c->stage(), (size_t)nn * sizeof(double),
+                           hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+  }
+  return MCLBM_OK;
+}
+
+int mclbm_nusselt(mclbm_cavity* c, double* nu_hot, double* nu_cold, double* nu_hot_k) {
+  if (!c) return fail(MCLBM_EINVAL, "cavity is NULL");
+  const double rp = (double)c->P.rho_p_ref, R = c->D.v[MCLBM_D_R], Ck = c->D.v[MCLBM_D_CK];
+  if (c->t & 1)
+    k_nusselt<true, StorF32><<<1, 256, 0, c->stream>>>(c->P, c->pop(), c->d5(), rp, R, Ck, c->res());
+  else
+    k_nusselt<false, StorF32><<<1, 256, 0, c->stream>>>(c->P, c->pop(), c->d5(), rp, R, Ck, c->res());
+  int rc = launch_check("k_nusselt");
+  if (rc) return rc;
+  double h[4];
+  HIP_TRY(hipMemcpyAsync(h, c->res(), sizeof(h), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (nu_hot) *nu_hot = h[0];
+  if (nu_cold) *nu_cold = h[1];
+  if (nu_hot_k) *nu_hot_k = h[2];
+  if (h[3] != 0.0) return fail(MCLBM_EDIVERGED, "non-finite temperature at a wall");
+  return MCLBM_OK;
+}
+
+int mclbm_residual(mclbm_cavity* c, double* res_u, double* res_theta) {
+  if (!c) return fail(MCLBM_EINVAL, "cavity is NULL");
+  const unsigned rb = (unsigned)c->L.red_blocks;
+  const double rf = (double)c->P.rho_f_ref, rp = (double)c->P.rho_p_ref;
+  if (c->t & 1)
+    k_residual<true, StorF32><<<rb, 256, 0, c->stream>>>(c->P, c->pop(), c->d5(), rf, rp, c->snap(), c->part());
+  else
+    k_residual<false, StorF32><<<rb, 256, 0, c->stream>>>(c->P, c->pop(), c->d5(), rf, rp, c->snap(), c->part());
+  int rc = launch_check("k_residual");
+  if (rc) return rc;
+  k_sum_partials<<<1, 256, 0, c->stream>>>(c->part(), (int)rb, c->res() + 4);
+  rc = launch_check("k_sum_partials");
+  if (rc) return rc;
+  double h[5];
+  HIP_TRY(hipMemcpyAsync(h, c->res() + 4, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  const double ru = h[1] > 0.0 ? std::sqrt(h[0] / h[1]) : (h[0] > 0.0 ? INFINITY : 0.0);
+  const double rt = h[3] > 0.0 ? std::sqrt(h[2] / h[3]) : (h[2] > 0.0 ? INFINITY : 0.0);
+  if (res_u) *res_u = ru;
+  if (res_theta) *res_theta = rt;
+  if (h[4] != 0.0) return fail(MCLBM_EDIVERGED, "non-finite velocity or temperature");
+  return MCLBM_OK;
+}
+
+int mclbm_derived(const mclbm_cavity* c, double* out, int n) {
+  if (!c || !out || n < MCLBM_D_COUNT) return fail(MCLBM_EINVAL, "bad arguments");
+  std::memcpy(out, c->D.v, sizeof(c->D.v));
+  return MCLBM_OK;
+}
+
+int mclbm_destroy(mclbm_cavity* c) {
+  if (!c) return MCLBM_OK;
+  hipError_t e = hipStreamSynchronize(c->stream);
+  delete c;
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  return MCLBM_OK;
+}
+
+const char* mclbm_last_error(void) { return g_err.c_str(); }
+
+int mclbm_copy_kernel(void* dst, const void* src, size_t bytes, void* stream) {
+  if (!dst || !src || bytes % 16 != 0) return fail(MCLBM_EINVAL, "copy: bad arguments");
+  const long long n = (long long)(bytes / 16);
+  int dev = 0, ncu = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) ncu = v;
+  }
+  const long long want = (n + 255) / 256;
+  const unsigned blocks = (unsigned)std::max<long long>(1, std::min<long long>(want, (long long)ncu * 16));
+  k_copy<<<blocks, 256, 0, reinterpret_cast<hipStream_t>(stream)>>>(
+      reinterpret_cast<float4*>(dst), reinterpret_cast<const float4*>(src), n);
+  return launch_check("k_copy");
+}
+
+const char* mclbm_version(void) { return "mclbm 0.1.0 (gfx950)"; }
+int mclbm_abi_version(void) { return MCLBM_ABI_VERSION; }
+
+}  // extern "C"

@@ -1,0 +1,100 @@
+"""The C-ABI library loads and exports every symbol include/mclbm.h declares;
+host-side logic (defaults, validation, sizes, derived constants) on the CPU.
+No device work is launched here."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import paper_1511_04552_amd as mc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mclbm.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mclbm_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = mc.lib()
+    declared = _declared_functions()
+    assert len(declared) >= 15
+    for name in declared:
+        assert hasattr(L, name), name
+    assert set(declared) == set(mc.EXPORTED)
+    out = subprocess.run(["nm", "-D", "--defined-only", mc.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (mclbm_[a-z_0-9]+)", out))
+    assert set(declared) <= exported
+    assert L.mclbm_abi_version() == 1
+    assert b"gfx950" in L.mclbm_version()
+
+
+def test_library_is_built_for_gfx950_only(tmp_path):
+    """The device code object bundled in the library targets gfx950 only."""
+    fatbin = tmp_path / "fatbin.bin"
+    r = subprocess.run(["/opt/rocm/llvm/bin/llvm-objcopy", f"--dump-section=.hip_fatbin={fatbin}",
+                        mc.LIB_PATH, str(tmp_path / "copy.so")], capture_output=True, text=True)
+    if r.returncode != 0:
+        pytest.skip("llvm-objcopy unavailable")
+    out = subprocess.run(["/opt/rocm/llvm/bin/clang-offload-bundler", "--list", "--type=o",
+                          f"--input={fatbin}"], capture_output=True, text=True)
+    targets = [t for t in out.stdout.split() if "amdgcn" in t]
+    assert targets and all(t.endswith("gfx950") for t in targets), out.stdout
+
+
+def test_defaults_and_sizes():
+    c = mc.make_config()
+    assert (c.nx, c.ny) == (64, 64) and c.force_mask == mc.F_ALL and c.storage == mc.FP32S
+    n64 = mc.device_bytes(nx=64, ny=64)
+    n128 = mc.device_bytes(nx=128, ny=128)
+    # 27 FP32 populations + two lag planes (8 B) per node dominate; x padded to 64
+    assert 27 * 4 * 64 * 64 < n64 < 200 * 64 * 64
+    assert 3.9 < n128 / n64 < 4.1
+    n67 = mc.device_bytes(nx=67, ny=53)
+    assert n67 >= 27 * 4 * 128 * 53
+
+
+@pytest.mark.parametrize("bad", [dict(nx=3), dict(ny=2), dict(Ra=-1.0), dict(Pr=0.0), dict(phi0=0.2),
+                                 dict(phi0=-0.01), dict(dp_m=0.0), dict(tau_f=0.5), dict(tau_f=0.3),
+                                 dict(force_mask=64), dict(block_x=48), dict(block_x=64, block_y=8),
+                                 dict(storage=7), dict(phi_perturb_amp=-1.0), dict(dT_K=0.0)])
+def test_invalid_configs_rejected(bad):
+    with pytest.raises(mc.MclbmError) as e:
+        mc.device_bytes(**bad)
+    assert e.value.code == mc.EINVAL
+    assert mc.lib().mclbm_last_error()
+
+
+def test_create_rejects_small_or_misaligned_buffers_without_touching_them():
+    L = mc.lib()
+    c = mc.make_config(nx=16, ny=16)
+    h = ctypes.c_void_p()
+    need = L.mclbm_device_bytes(ctypes.byref(c))
+    rc = L.mclbm_create(ctypes.byref(c), None, ctypes.c_void_p(256), ctypes.c_size_t(need - 1), None, ctypes.byref(h))
+    assert rc == mc.ENOMEM and not h.value
+    rc = L.mclbm_create(ctypes.byref(c), None, ctypes.c_void_p(4096 + 8), ctypes.c_size_t(need), None, ctypes.byref(h))
+    assert rc == mc.EINVAL and not h.value
+    rc = L.mclbm_create(ctypes.byref(c), None, None, ctypes.c_size_t(need), None, ctypes.byref(h))
+    assert rc == mc.EINVAL
+
+
+def test_derived_constants_agree_with_independent_oracle_derivation():
+    """Two independent host derivations of the lattice constants (library in
+    C++, oracle in C): they agree to round-off for several configurations."""
+    import oracle
+    cases = [dict(nx=64, ny=64, Ra=1e3, Pr=6.2, phi0=0.01, dp_nm=100, tau_f=0.8),
+             dict(nx=512, ny=512, Ra=1e5, Pr=6.2, phi0=0.03, dp_nm=50, tau_f=0.8),
+             dict(nx=2048, ny=2048, Ra=1e6, Pr=6.2, phi0=0.04, dp_nm=30, tau_f=0.8),
+             dict(nx=64, ny=64, Ra=1e6, Pr=6.2, phi0=0.02, dp_nm=20, tau_f=-1.0),
+             dict(nx=160, ny=80, Ra=0.0, Pr=8.923, phi0=0.0, dp_nm=33, tau_f=1.1)]
+    for cfg in cases:
+        a = mc.derive_constants(**cfg)
+        b = oracle.Oracle(**cfg).derived()
+        for k in mc.DERIVED:
+            assert abs(a[k] - b[k]) <= 1e-14 * max(abs(b[k]), 1e-300), (cfg, k, a[k], b[k])

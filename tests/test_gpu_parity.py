@@ -1,0 +1,241 @@
+"""HIP path (FP32 shifted storage, A-A in place) against the FP64 oracle.
+
+Tolerances: moments within 1e-5 of the field maximum (max |gpu - oracle| /
+max |oracle| per field) after 1000 steps, Nusselt numbers within 1e-4
+relative.  Every case calls the library through its C ABI (ctypes binding)
+with the same seeded inputs as the oracle.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import oracle  # noqa: E402
+import paper_1511_04552_amd as mc  # noqa: E402
+from paper_1511_04552_amd import inputs  # noqa: E402
+
+MOMENT_TOL = 1e-5
+NU_TOL = 1e-4
+VELOCITY_FIELDS = ("ux_f", "uy_f", "ux_p", "uy_p", "ux_ns", "uy_ns")
+
+
+def _pair(seed=None, **cfg):
+    xi = None
+    if seed is not None:
+        xi = inputs.phi_perturbation(seed, cfg["nx"], cfg["ny"])
+    gpu = mc.Cavity(xi=xi, **cfg)
+    ocfg = {k: v for k, v in cfg.items() if k not in ("block_x", "block_y", "storage")}
+    ora = oracle.Oracle(xi=xi, **ocfg)
+    return gpu, ora
+
+
+def _field_errors(g, o):
+    err = {}
+    for k in o:
+        scale = np.abs(o[k]).max()
+        if k == "phi":  # phi varies around phi0: compare its deviation too
+            err[k] = np.abs(g[k] - o[k]).max() / max(scale, 1e-300)
+        else:
+            err[k] = np.abs(g[k] - o[k]).max() / max(scale, 1e-300)
+    return err
+
+
+def _assert_moments(gpu, ora, tol=MOMENT_TOL, fields=oracle.FIELDS):
+    g, o = gpu.moments(fields), ora.moments(fields)
+    err = _field_errors(g, o)
+    print({k: f"{v:.2e}" for k, v in err.items()}, flush=True)
+    for k, v in err.items():
+        if np.abs(o[k]).max() == 0.0:
+            assert np.abs(g[k]).max() == 0.0, k
+        else:
+            assert v <= tol, (k, v)
+    return g, o
+
+
+def _assert_nusselt(gpu, ora, tol=NU_TOL):
+    a, b = gpu.nusselt(), ora.nusselt()
+    print("Nu gpu", a, "oracle", b, flush=True)
+    for x, y in zip(a, b):
+        assert abs(x - y) <= tol * abs(y), (a, b)
+
+
+def test_reference_cavity_64_after_1000_steps():
+    """64^2, Ra 1e3, phi 1 %, 100 nm, all six slip forces, seeded
+    perturbation: moments and Nu after 1000 steps."""
+    w = inputs.WORKLOADS["cavity64_ra1e3"]
+    cfg = {k: v for k, v in w.items() if k != "seed"}
+    gpu, ora = _pair(seed=w["seed"], **cfg)
+    gpu.step(1000)
+    ora.step(1000)
+    assert gpu.time == ora.time == 1000
+    _assert_moments(gpu, ora)
+    _assert_nusselt(gpu, ora)
+
+
+def test_ragged_rectangle_odd_step_count():
+    """nx, ny not multiples of the tile (67 x 53) and an odd step count, so
+    the state is read back in the odd A-A layout (neighbour slots, wall side
+    buffer)."""
+    cfg = dict(nx=67, ny=53, Ra=2e4, Pr=6.2, phi0=0.02, dp_nm=40.0, tau_f=0.8)
+    gpu, ora = _pair(seed=11, **cfg)
+    gpu.step(301)
+    ora.step(301)
+    _assert_moments(gpu, ora)
+    _assert_nusselt(gpu, ora)
+
+
+@pytest.mark.parametrize("nsteps", [1, 2, 3])
+def test_first_steps_match_tightly(nsteps):
+    """The first steps exercise every wall rule and both A-A parities; FP32
+    round-off alone separates the two sides."""
+    cfg = dict(nx=16, ny=12, Ra=5e4, Pr=6.2, phi0=0.03, dp_nm=50.0, tau_f=0.7)
+    gpu, ora = _pair(seed=3, **cfg)
+    gpu.step(nsteps)
+    ora.step(nsteps)
+    _assert_moments(gpu, ora, tol=1e-6)
+    pg, po = gpu.populations(), ora.populations()
+    scale = np.abs(po).reshape(3, -1).max(axis=1)[:, None, None, None]
+    assert (np.abs(pg - po) / scale).max() < 1e-6
+
+
+def test_minimum_size_and_empty_particle_lattice():
+    for cfg in (dict(nx=4, ny=4, Ra=1e3, phi0=0.01, dp_nm=100.0),
+                dict(nx=20, ny=20, Ra=1e4, phi0=0.0, dp_nm=100.0)):
+        gpu, ora = _pair(seed=5, **cfg)
+        gpu.step(101)
+        ora.step(101)
+        _assert_moments(gpu, ora)
+        _assert_nusselt(gpu, ora)
+
+
+@pytest.mark.parametrize("bit,scale", [(mc.F_DRAG, 1.0), (mc.F_BROWN, 1e9), (mc.F_THERMO, 1.0),
+                                       (mc.F_SAFF, 1.0), (mc.F_MAGROT, 1.0), (mc.F_GRAV, 1.0),
+                                       (mc.F_DRAG | mc.F_THERMO | mc.F_GRAV, 1.0),
+                                       (mc.F_DRAG, 1e-8)])
+def test_each_slip_force(bit, scale):
+    """One force (or a subset) at a time; a scale lifts the tiny Brownian
+    force above round-off, a small drag scale exercises the non-stiff
+    branch of the drag integrator."""
+    scales = [scale if (bit >> k) & 1 else 1.0 for k in range(6)]
+    cfg = dict(nx=32, ny=32, Ra=1e4, phi0=0.02, dp_nm=50.0, force_mask=bit, force_scale=scales)
+    gpu, ora = _pair(seed=9, **cfg)
+    gpu.step(400)
+    ora.step(400)
+    _assert_moments(gpu, ora)
+
+
+def test_bench_workload_full_size():
+    """512^2, Ra 1e5, phi 3 %, 50 nm (the benchmarked workload, default
+    launch shape): full fields after 200 steps."""
+    w = inputs.WORKLOADS["cavity512_ra1e5"]
+    cfg = {k: v for k, v in w.items() if k != "seed"}
+    gpu, ora = _pair(seed=w["seed"], **cfg)
+    gpu.step(200)
+    ora.step(200)
+    _assert_moments(gpu, ora)
+    _assert_nusselt(gpu, ora)
+
+
+def test_large_cavity_2048_short_run_and_mass():
+    """2048^2, Ra 1e6, phi 4 %, 30 nm: full fields after 20 steps and exact
+    component masses (conserved by the scheme, FP32 round-off only)."""
+    w = inputs.WORKLOADS["cavity2048_ra1e6"]
+    cfg = {k: v for k, v in w.items() if k != "seed"}
+    gpu, ora = _pair(seed=w["seed"], **cfg)
+    m0 = gpu.moments(("rho_f", "phi"))
+    gpu.step(20)
+    ora.step(20)
+    _assert_moments(gpu, ora, fields=("rho_f", "ux_f", "uy_f", "phi", "theta"))
+    gpu.step(180)
+    m1 = gpu.moments(("rho_f", "phi"))
+    for k in ("rho_f", "phi"):
+        rel = abs(m1[k].sum() - m0[k].sum()) / m0[k].sum()
+        print(k, "mass drift", rel)
+        assert rel < 1e-9, (k, rel)
+
+
+def test_block_shapes_bitwise_identical_and_deterministic():
+    cfg = dict(nx=70, ny=45, Ra=3e4, phi0=0.02, dp_nm=40.0)
+    xi = inputs.phi_perturbation(7, 70, 45)
+    ref = None
+    for bx, by in ((64, 4), (32, 2), (256, 1), (128, 2), (64, 4)):
+        c = mc.Cavity(xi=xi, block_x=bx, block_y=by, **cfg)
+        c.step(77)
+        pops = c.populations()
+        if ref is None:
+            ref = pops
+        else:
+            assert np.array_equal(pops, ref), (bx, by)
+
+
+def test_conduction_limit_on_gpu():
+    """Ra = 0 without slip forces: the GPU reaches the linear profile and
+    Nu = 1 (FP32 round-off level)."""
+    c = mc.Cavity(nx=16, ny=16, Ra=0.0, Pr=0.71, phi0=0.0, force_mask=0, phi_perturb_amp=0.0)
+    c.step(6000)
+    th = c.moments("theta")["theta"]
+    lin = 0.5 - (np.arange(16) + 0.5) / 16
+    assert np.abs(th - lin[None, :]).max() < 1e-6
+    nh, nc, nk = c.nusselt()
+    assert abs(nh - 1) < 1e-5 and abs(nc - 1) < 1e-5 and abs(nk - 1) < 1e-5
+
+
+def test_residual_and_steady_nusselt_match_oracle():
+    """Relative change over 1000 steps and the steady-state Nu (run until
+    both residuals drop below 1e-8) agree with the oracle."""
+    cfg = dict(nx=32, ny=32, Ra=1e4, Pr=6.2, phi0=0.01, dp_nm=100.0, tau_f=0.8)
+    gpu, ora = _pair(seed=1, **cfg)
+    for it in range(200):
+        gpu.step(1000)
+        ora.step(1000)
+        rg, ro = gpu.residual(), ora.residual()
+        if it < 3:
+            for a, b in zip(rg, ro):
+                assert abs(a - b) <= 1e-4 * abs(b), (rg, ro)
+        if max(ro) < 1e-8:
+            break
+    print("steady after", gpu.time, "residual gpu", rg, "oracle", ro)
+    assert max(ro) < 1e-8
+    _assert_nusselt(gpu, ora)
+
+
+def test_centro_symmetry_pure_fluid_gpu():
+    c = mc.Cavity(nx=128, ny=128, Ra=1e5, phi0=0.0, force_mask=0, phi_perturb_amp=0.0)
+    c.step(2000)
+    m = c.moments(("theta", "ux_ns", "uy_ns"))
+    for k, v in m.items():
+        assert np.abs(v + v[::-1, ::-1]).max() <= 1e-5 * np.abs(v).max(), k
+    nh, nc, _ = c.nusselt()
+    assert abs(nh - nc) < 1e-5 * nh
+
+
+def test_reset_and_set_properties():
+    c = mc.Cavity(nx=24, ny=24, Ra=1e4)
+    m0 = c.moments()
+    c.step(57)
+    c.reset()
+    assert c.time == 0
+    m1 = c.moments()
+    for k in m0:
+        assert np.array_equal(m0[k], m1[k]), k
+    c.set_properties(2e4, 0.02, 40e-9)
+    d = c.derived()
+    o = oracle.Oracle(nx=24, ny=24, Ra=2e4, phi0=0.02, dp_nm=40.0).derived()
+    for k in d:
+        assert abs(d[k] - o[k]) <= 1e-14 * max(abs(o[k]), 1e-300)
+    assert abs(c.moments("phi")["phi"].mean() - 0.02) < 1e-9
+
+
+def test_divergence_is_reported():
+    """An unstable configuration (Ra 1e12 with tau_f 0.51 on 16^2, which the
+    oracle also drives to non-finite values) turns non-finite; the next sync
+    call reports MCLBM_EDIVERGED.  Every kernel still exits normally."""
+    c = mc.Cavity(nx=16, ny=16, Ra=1e12, tau_f=0.51, phi0=0.0, force_mask=0)
+    c.step(3000)
+    with pytest.raises(mc.MclbmError) as e:
+        c.residual()
+    assert e.value.code == mc.EDIVERGED
