@@ -48,6 +48,10 @@ __host__ __device__ constexpr int opp(int i) {
 __host__ __device__ constexpr float wgt(int i) {
   return i == 0 ? 4.0f / 9.0f : (i < 5 ? 1.0f / 9.0f : 1.0f / 36.0f);
 }
+// exact weights in double precision (shift of the storage, exports)
+__host__ __device__ constexpr double wgt_d(int i) {
+  return i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
+}
 // side-buffer slot of a wall-row unknown: bottom row N, NE, NW; top S, SE, SW
 __host__ __device__ constexpr int d5slot(int i) {
   return (i == 2 || i == 4) ? 0 : ((i == 5 || i == 8) ? 1 : 2);
@@ -93,6 +97,7 @@ struct StepParams {
   float inv_scale[3];
   // reference state and relaxation
   float rho_f_ref, rho_p_ref, dref_p;  // dref_p = rho_p_ref - R phi0
+  float rho_p0;                        // R phi0
   float tau_f, omega_f;
   // properties (Eqs 7-11, 22-24)
   float invR, Rm1, crc, crb, Ck, alpha3;
@@ -104,7 +109,7 @@ struct StepParams {
   float dT_T0;
   float cS;              // Saffman
   float cM, cR;          // Magnus, particle rotation
-  float cG, cGref;       // settling per particle mass; fluid reference
+  float cG;              // settling per particle mass, (1 - 1/R) g
   float cRe, cD;         // drag: Re_d and Stokes rate coefficients
   unsigned force_on;     // bit k set when force k has a non-zero coefficient
 };
@@ -216,20 +221,49 @@ __device__ __forceinline__ void store_node(const StepParams& P,
 }
 
 // ---- BGK collision with forcing in deviation form (Eqs 18-19, 26-27) ------
-// h* = h + omega (h_eq - h) + 3 W_i e_i.F,
-// h_eq = W_i [d + a (3 e.u + 4.5 (e.u)^2 - 1.5 u^2)], with d = sum h the
-// deviation of the density and a the full density (for g: d = a = theta).
-__device__ __forceinline__ void collide(float h[9], float d, float a, float ux,
-                                        float uy, float omega, float Fx,
-                                        float Fy) {
-  const float base = d - 1.5f * a * (ux * ux + uy * uy);
-#pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    const float eu = (float)ex(i) * ux + (float)ey(i) * uy;
-    const float heq = wgt(i) * (base + a * eu * (3.0f + 4.5f * eu));
-    const float s = 3.0f * wgt(i) * ((float)ex(i) * Fx + (float)ey(i) * Fy);
-    h[i] = fmaf(omega, heq - h[i], h[i]) + s;
-  }
+// h* = h + omega (h_eq - h) + S,
+// h_eq_i = W_i [d + a (3 e.u + 4.5 (e.u)^2 - 1.5 u^2)], S_i = 3 W_i e_i.F,
+// with d = sum h the density deviation, a the full density and j = a u the
+// first moment (for g: d = a = theta, j = theta u_ns).
+// The weights 1/9 and 1/36 are inexact in binary floating point, so the
+// textbook per-direction form leaks mass and momentum by ~1e-8 of the state
+// per step.  Here the equilibrium is assembled from its symmetric and
+// antisymmetric parts per direction pair so that sum h_eq = d and
+// sum h_eq e = j (and sum S = 0, sum S e = F) hold by construction: the
+// diagonal pairs take their exact-weight values, the axis pairs take what
+// remains of j/2, and the rest population what remains of d.
+__device__ __forceinline__ void collide(float h[9], float d, float a, float jx,
+                                        float jy, float ux, float uy,
+                                        float omega, float Fx, float Fy) {
+  constexpr float W1 = 1.0f / 9.0f, W5 = 1.0f / 36.0f;
+  const float base = fmaf(-1.5f * a, fmaf(ux, ux, uy * uy), d);
+  const float a45 = 4.5f * a;
+  const float up = ux + uy, um = ux - uy;
+  // symmetric parts of the pairs (1,3), (2,4), (5,7), (8,6)
+  const float S1 = W1 * fmaf(a45 * ux, ux, base);
+  const float S2 = W1 * fmaf(a45 * uy, uy, base);
+  const float S5 = W5 * fmaf(a45 * up, up, base);
+  const float S8 = W5 * fmaf(a45 * um, um, base);
+  // antisymmetric parts: diagonals exact-weight, axes close the momentum
+  const float A5 = (3.0f * W5) * (jx + jy);
+  const float A8 = (3.0f * W5) * (jx - jy);
+  const float A1 = fmaf(0.5f, jx, -(A5 + A8));
+  const float A2 = fmaf(0.5f, jy, A8 - A5);
+  const float S0 = d - 2.0f * ((S1 + S2) + (S5 + S8));
+  // forcing, same construction
+  const float B5 = (3.0f * W5) * (Fx + Fy);
+  const float B8 = (3.0f * W5) * (Fx - Fy);
+  const float B1 = fmaf(0.5f, Fx, -(B5 + B8));
+  const float B2 = fmaf(0.5f, Fy, B8 - B5);
+  h[0] = fmaf(omega, S0 - h[0], h[0]);
+  h[1] = fmaf(omega, (S1 + A1) - h[1], h[1]) + B1;
+  h[3] = fmaf(omega, (S1 - A1) - h[3], h[3]) - B1;
+  h[2] = fmaf(omega, (S2 + A2) - h[2], h[2]) + B2;
+  h[4] = fmaf(omega, (S2 - A2) - h[4], h[4]) - B2;
+  h[5] = fmaf(omega, (S5 + A5) - h[5], h[5]) + B5;
+  h[7] = fmaf(omega, (S5 - A5) - h[7], h[7]) - B5;
+  h[8] = fmaf(omega, (S8 + A8) - h[8], h[8]) + B8;
+  h[6] = fmaf(omega, (S8 - A8) - h[6], h[6]) - B8;
 }
 
 struct NodeMoments {
@@ -328,12 +362,14 @@ __device__ __forceinline__ float2 node_update(const StepParams& P, float f[9],
     const float aGy = -P.cG;  // settling per particle mass (0 when off)
     if (on & 1u) {
       // Drag integrated exactly over the step (stiff: kappa ~ 1e4).  Its
-      // mean combined with the other particle forces gives, without forming
-      // the large cancelling terms,
+      // mean combined with the other particle forces is
       //   F^p = rho_p [phi1 (a_int + beta w) + beta phi2 Fext_f / rho_f
       //               + a_G (r + phi1) / (1 + r)],
       // r = rho_p/rho_f, kappa = beta (1 + r), phi1 = (1 - e^-kappa)/kappa,
-      // phi2 = (1 - phi1)/kappa, Fext_f the non-reacting fluid force.
+      // phi2 = (1 - phi1)/kappa, a_int the interaction forces per particle
+      // mass, a_G settling, Fext_f buoyancy plus the fluid's gravity
+      // reference.  Written this way no large terms cancel (the reacting
+      // forces and the drag nearly balance each other).
       const float r = rho_p * irf;
       const float Red = P.cRe * wn / r_mu;
       const float beta = P.cD * r_mu * fmaf(0.15f, __powf(Red, 0.687f), 1.0f);
@@ -346,10 +382,14 @@ __device__ __forceinline__ float2 node_update(const StepParams& P, float f[9],
         ph1 = -expm1f(-kap) / kap;
         ph2 = (1.0f - ph1) / kap;
       }
-      const float fext = Fbuoy + P.cGref;
+      // The gravity terms (settling, fluid reference) combine, with
+      // beta phi2 = (1 - phi1)/(1 + r), into
+      //   -cG [ (rho_p - R phi0) + phi1 (R phi0 + rho_f) ] / rho_m
+      // and buoyancy into (1 - phi1) Fbuoy / rho_m: no cancellation.
+      const float om1 = kap < 0.05f ? kap * ph2 : 1.0f - ph1;
+      const float ext = fmaf(om1, Fbuoy, -P.cG * fmaf(ph1, P.rho_p0 + rho_f, dp_true)) * irm;
       Fpx = rho_p * ph1 * fmaf(beta, wx, aix);
-      Fpy = rho_p * fmaf(ph1, fmaf(beta, wy, aiy),
-                         fmaf(beta * ph2 * irf, fext, aGy * (r + ph1) / (1.0f + r)));
+      Fpy = rho_p * fmaf(ph1, fmaf(beta, wy, aiy), ext);
     } else {
       Fpx = rho_p * aix;
       Fpy = rho_p * (aiy + aGy);
@@ -359,9 +399,10 @@ __device__ __forceinline__ float2 node_update(const StepParams& P, float f[9],
   const float Ffy = fmaf(-P.cG, dp_true, Fbuoy) - Fpy;
 
   // S6: collisions; f and p relax to their own velocities, g to u_ns
-  collide(f, m.drf, rho_f, uxf, uyf, P.omega_f, Ffx, Ffy);
-  collide(p, m.drp, rho_p, uxp, uyp, 1.0f / tau_p, Fpx, Fpy);
-  collide(g, th, th, uxn, uyn, 1.0f / tau_th, 0.0f, 0.0f);
+  collide(f, m.drf, rho_f, m.jxf, m.jyf, uxf, uyf, P.omega_f, Ffx, Ffy);
+  collide(p, m.drp, rho_p, empty ? rho_p * uxf : m.jxp, empty ? rho_p * uyf : m.jyp, uxp, uyp,
+          1.0f / tau_p, Fpx, Fpy);
+  collide(g, th, th, th * uxn, th * uyn, uxn, uyn, 1.0f / tau_th, 0.0f, 0.0f);
   return make_float2(m.drp * P.invR, th);
 }
 

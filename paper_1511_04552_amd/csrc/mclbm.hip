@@ -45,7 +45,7 @@ __global__ __launch_bounds__(256) void k_init(StepParams P,
   float f[9], p[9], g[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
-    const double w = (double)wgt(i);
+    const double w = wgt_d(i);
     f[i] = (float)(w * dev_f);
     p[i] = (float)(w * dp);
     g[i] = 0.0f;
@@ -273,7 +273,7 @@ __global__ __launch_bounds__(256) void k_export_pops(StepParams P,
   float f[9], p[9], g[9];
   load_node<ODD, S>(P, const_cast<typename S::T*>(pop), d5, x, y, f, p, g);
   for (int i = 0; i < 9; ++i) {
-    const double w = (double)wgt(i);
+    const double w = wgt_d(i);
     const double vf = (double)f[i] + w * rho_f_ref;
     const double vp = (double)p[i] + w * rho_p_ref;
     const double vg = (double)g[i];
@@ -475,6 +475,7 @@ StepParams make_params(const mclbm_config& c, const Derived& D, const Layout& L)
   P.rho_f_ref = rf_ref;
   P.rho_p_ref = rp_ref;
   P.dref_p = (float)((double)rp_ref - v[MCLBM_D_RHO_P0]);
+  P.rho_p0 = (float)v[MCLBM_D_RHO_P0];
   P.tau_f = (float)tau_f;
   P.omega_f = (float)(1.0 / tau_f);
   P.invR = (float)(1.0 / R);
@@ -511,9 +512,8 @@ StepParams make_params(const mclbm_config& c, const Derived& D, const Layout& L)
   // Magnus: (|v_M|/d)(v_p - v_M); rotation: mu rho_p gdot A_p / (rho m_p)
   P.cM = (float)(s[4] * dx / d);
   P.cR = (float)(s[4] * 8.0 * R * mu * Ap * dt / (H * mp));
-  // settling -(1 - rho_f/rho_p) g; fluid reference R phi0 (1 - 1/R) g
+  // settling -(1 - rho_f/rho_p) g (the fluid carries R phi0 (1 - 1/R) g)
   P.cG = (float)(s[5] * (1.0 - 1.0 / R) * v[MCLBM_D_GRAV_L]);
-  P.cGref = (float)(s[5] * (1.0 - 1.0 / R) * v[MCLBM_D_GRAV_L] * v[MCLBM_D_RHO_P0]);
   // drag: Re_d = rho_p d |w| / mu_ns, beta = 18 mu_ns (1 + 0.15 Re^0.687)/(rho_p d^2)
   P.cRe = (float)(c.particle.rho * d * (dx / dt) / mu);
   P.cD = (float)(s[0] * 18.0 * mu * dt / (c.particle.rho * d * d));
