@@ -104,9 +104,10 @@ typedef struct {
   double phi_perturb_amp;  /* initial phi = max(phi0 + amp * xi, 0) */
   mclbm_material fluid, particle;
   int32_t storage;         /* enum mclbm_storage */
-  int32_t block_x, block_y;/* step-kernel block shape; 0 = default (64x4).
-                              block_x in {32, 64, 128, 256},
-                              block_x * block_y in {64, 128, 256, 512, 1024} */
+  int32_t block_x, block_y;/* step-kernel workgroup shape; 0 = default
+                              (256 x 1 when nx >= 256, else 64 x 1);
+                              block_x in {32, 64, 128, 256} and
+                              block_x * block_y in {64, 128, 256} */
 } mclbm_config;
 
 typedef struct mclbm_cavity mclbm_cavity; /* opaque host-side handle */

@@ -16,7 +16,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libmclbm.so")
+# MCLBM_LIBRARY may point at another build of the same C ABI.
+LIB_PATH = os.environ.get("MCLBM_LIBRARY") or os.path.join(_HERE, "libmclbm.so")
 
 # Interface constants of include/mclbm.h.
 OK, EINVAL, ENOMEM, EHIP, EDIVERGED, ESTATE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6

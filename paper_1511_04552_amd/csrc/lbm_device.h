@@ -62,14 +62,39 @@ static_assert(opp(1) == 3 && opp(2) == 4 && opp(5) == 7 && opp(6) == 8 &&
               "opposite directions");
 
 // ---- population storage -------------------------------------------------
-// FP32 deviations; 16-bit deviations scaled by a power of two per lattice
-// (scale[l] on store, 1/scale[l] on load) so that typical deviations sit in
-// the normal range of the 16-bit format.
+// Element access through a base pointer and an element index of type I
+// (uint32_t when the population array is below 2 GiB, so that loads and
+// stores take the scalar-base + 32-bit vector-offset form; uint64_t above).
+template <class T, class I>
+__device__ __forceinline__ const T* elem(const T* base, I idx) {
+  if constexpr (sizeof(I) == 4)
+    return reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) +
+                                      (uint32_t)(idx * (uint32_t)sizeof(T)));
+  else
+    return base + idx;
+}
+template <class T, class I>
+__device__ __forceinline__ T* elem(T* base, I idx) {
+  return const_cast<T*>(elem(const_cast<const T*>(base), idx));
+}
+
+// FP32 deviations.  NT = true marks the population traffic non-temporal
+// (streamed past the caches) for cavities larger than the last-level cache.
+template <bool NT>
 struct StorF32 {
   using T = float;
-  static __device__ __forceinline__ float ld(const T* p, float) { return *p; }
-  static __device__ __forceinline__ void st(T* p, float v, float) { *p = v; }
+  static __device__ __forceinline__ float ld(const T* p, float) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+  }
+  static __device__ __forceinline__ void st(T* p, float v, float) {
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+  }
 };
+// 16-bit deviations scaled by a power of two per lattice (scale[l] on store,
+// 1/scale[l] on load) so that typical deviations sit in the normal range.
+template <bool NT>
 struct StorF16 {
   using T = __half;
   static __device__ __forceinline__ float ld(const T* p, float inv) {
@@ -79,6 +104,7 @@ struct StorF16 {
     *p = __float2half_rn(v * sc);
   }
 };
+template <bool NT>
 struct StorBF16 {
   using T = __hip_bfloat16;
   static __device__ __forceinline__ float ld(const T* p, float inv) {
@@ -88,6 +114,14 @@ struct StorBF16 {
     *p = __float2bfloat16(v * sc);
   }
 };
+
+// Reciprocal: hardware estimate refined by one Newton step (~0.5 ulp),
+// instead of the long IEEE division sequence.
+__device__ __forceinline__ float frcp(float x) {
+  const float r = __builtin_amdgcn_rcpf(x);
+  return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
 // ---- kernel parameters (kernarg, by value) -------------------------------
 struct StepParams {
@@ -115,36 +149,36 @@ struct StepParams {
 };
 
 // ---- A-A access: read the nine populations of each lattice --------------
-template <bool ODD, class S>
+template <bool ODD, class S, class I>
 __device__ __forceinline__ void load_node(const StepParams& P,
                                           const typename S::T* __restrict__ pop,
                                           const float* __restrict__ d5, int x,
                                           int y, float f[9], float p[9],
                                           float g[9]) {
-  const long long n = (long long)y * P.px + x;
-  const long long pl = P.plane;
+  const I px = (I)P.px, pl = (I)P.plane;
+  const I n = (I)y * px + (I)x;
   const bool xl = x == 0, xr = x == P.nx - 1, yb = y == 0, yt = y == P.ny - 1;
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     if (!ODD) {
-      f[i] = S::ld(pop + pl * i + n, P.inv_scale[0]);
-      p[i] = S::ld(pop + pl * (9 + i) + n, P.inv_scale[1]);
-      g[i] = S::ld(pop + pl * (18 + i) + n, P.inv_scale[2]);
+      f[i] = S::ld(elem(pop, pl * (I)i + n), P.inv_scale[0]);
+      p[i] = S::ld(elem(pop, pl * (I)(9 + i) + n), P.inv_scale[1]);
+      g[i] = S::ld(elem(pop, pl * (I)(18 + i) + n), P.inv_scale[2]);
     } else {
       const bool outx = (ex(i) == 1 && xl) || (ex(i) == -1 && xr);
       const bool outy = (ey(i) == 1 && yb) || (ey(i) == -1 && yt);
       const bool out = outx || outy;
       // inside: upstream node's slot opp(i); wall link: own slot i
-      const long long a = out ? (pl * i + n)
-                              : (pl * opp(i) + n - ex(i) - (long long)ey(i) * P.px);
-      f[i] = S::ld(pop + a, P.inv_scale[0]);
-      p[i] = S::ld(pop + pl * 9 + a, P.inv_scale[1]);
+      const I up = n - (I)ex(i) - (I)ey(i) * px;  // wraps only when unused
+      const I a = out ? (pl * (I)i + n) : (pl * (I)opp(i) + up);
+      f[i] = S::ld(elem(pop, a), P.inv_scale[0]);
+      p[i] = S::ld(elem(pop, pl * (I)9 + a), P.inv_scale[1]);
       if (i == 0) {
-        g[i] = S::ld(pop + pl * 18 + a, P.inv_scale[2]);
+        g[i] = S::ld(elem(pop, pl * (I)18 + a), P.inv_scale[2]);
       } else if (outy) {
-        g[i] = d5[(long long)((ey(i) == 1 ? 0 : 3) + d5slot(i)) * P.px + x];
+        g[i] = d5[((ey(i) == 1 ? 0 : 3) + d5slot(i)) * P.px + x];
       } else {
-        const float v = S::ld(pop + pl * 18 + a, P.inv_scale[2]);
+        const float v = S::ld(elem(pop, pl * (I)18 + a), P.inv_scale[2]);
         g[i] = outx ? (xl ? wgt(i) : -wgt(i)) - v : v;
       }
     }
@@ -152,53 +186,53 @@ __device__ __forceinline__ void load_node(const StepParams& P,
 }
 
 // ---- A-A access: write the post-collision populations --------------------
-template <bool ODD, class S>
+template <bool ODD, class S, class I>
 __device__ __forceinline__ void store_node(const StepParams& P,
                                            typename S::T* __restrict__ pop,
                                            float* __restrict__ d5, int x, int y,
                                            const float f[9], const float p[9],
                                            const float g[9]) {
-  const long long n = (long long)y * P.px + x;
-  const long long pl = P.plane;
+  const I px = (I)P.px, pl = (I)P.plane;
+  const I n = (I)y * px + (I)x;
   const int nx = P.nx, ny = P.ny;
   const bool xl = x == 0, xr = x == nx - 1, yb = y == 0, yt = y == ny - 1;
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     if (!ODD) {
-      S::st(pop + pl * opp(i) + n, f[i], P.scale[0]);
-      S::st(pop + pl * (9 + opp(i)) + n, p[i], P.scale[1]);
-      S::st(pop + pl * (18 + opp(i)) + n, g[i], P.scale[2]);
+      S::st(elem(pop, pl * (I)opp(i) + n), f[i], P.scale[0]);
+      S::st(elem(pop, pl * (I)(9 + opp(i)) + n), p[i], P.scale[1]);
+      S::st(elem(pop, pl * (I)(18 + opp(i)) + n), g[i], P.scale[2]);
     } else {
       const bool outx = (ex(i) == 1 && xr) || (ex(i) == -1 && xl);
       const bool outy = (ey(i) == 1 && yt) || (ey(i) == -1 && yb);
       const bool out = outx || outy;
-      const long long a = out ? (pl * opp(i) + n)
-                              : (pl * i + n + ex(i) + (long long)ey(i) * P.px);
-      S::st(pop + a, f[i], P.scale[0]);
-      S::st(pop + pl * 9 + a, p[i], P.scale[1]);
+      const I down = n + (I)ex(i) + (I)ey(i) * px;  // wraps only when unused
+      const I a = out ? (pl * (I)opp(i) + n) : (pl * (I)i + down);
+      S::st(elem(pop, a), f[i], P.scale[0]);
+      S::st(elem(pop, pl * (I)9 + a), p[i], P.scale[1]);
       if (i == 0) {
-        S::st(pop + pl * 18 + a, g[i], P.scale[2]);
+        S::st(elem(pop, pl * (I)18 + a), g[i], P.scale[2]);
       } else if (!out) {
-        S::st(pop + pl * 18 + a, g[i], P.scale[2]);
+        S::st(elem(pop, pl * (I)18 + a), g[i], P.scale[2]);
         // the wall row takes the same value (copy of the adiabatic wall)
         if ((ey(i) == 1 && yb) || (ey(i) == -1 && yt))
-          S::st(pop + pl * (18 + i) + n + ex(i), g[i], P.scale[2]);
+          S::st(elem(pop, pl * (I)(18 + i) + n + (I)ex(i)), g[i], P.scale[2]);
       } else if (!outy) {
         // isothermal wall: anti-bounce-back into the own slot opp(i)
         const float v = (ex(i) == -1 ? wgt(i) : -wgt(i)) - g[i];
-        S::st(pop + pl * 18 + a, v, P.scale[2]);
+        S::st(elem(pop, pl * (I)18 + a), v, P.scale[2]);
         // corner: the wall row next to this one copies it
         if (ey(opp(i)) == 1 && y == 1)
-          S::st(pop + pl * 18 + a - P.px, v, P.scale[2]);
+          S::st(elem(pop, pl * (I)18 + a - px), v, P.scale[2]);
         if (ey(opp(i)) == -1 && y == ny - 2)
-          S::st(pop + pl * 18 + a + P.px, v, P.scale[2]);
+          S::st(elem(pop, pl * (I)18 + a + px), v, P.scale[2]);
       }
       // out through an adiabatic wall: the value leaves the domain
     }
   }
   if (!ODD) {
     // side buffer for the adiabatic copy of the next (odd) step
-    const long long px = P.px;
+    const int px = P.px;
     if (yb) {
       d5[0 * px + x] = g[2];
       if (!xr) d5[1 * px + x + 1] = g[5];
@@ -294,14 +328,14 @@ __device__ __forceinline__ float2 node_update(const StepParams& P, float f[9],
   // S1/S2: Eqs 29-32 (partial densities; mass-averaged mixture velocity)
   const float rho_f = P.rho_f_ref + m.drf;
   const float rho_p = P.rho_p_ref + m.drp;
-  const float irf = 1.0f / rho_f;
+  const float irf = frcp(rho_f);
   const float uxf = m.jxf * irf, uyf = m.jyf * irf;
   const bool empty = !(rho_p > 1e-12f);
-  const float irp = empty ? 0.0f : 1.0f / rho_p;
+  const float irp = empty ? 0.0f : frcp(rho_p);
   const float uxp = empty ? uxf : m.jxp * irp;
   const float uyp = empty ? uyf : m.jyp * irp;
   const float rho_m = rho_f + rho_p;
-  const float irm = 1.0f / rho_m;
+  const float irm = frcp(rho_m);
   const float uxn = (m.jxf + m.jxp) * irm, uyn = (m.jyf + m.jyp) * irm;
   const float th = m.th;
 
@@ -313,11 +347,11 @@ __device__ __forceinline__ float2 node_update(const StepParams& P, float f[9],
   const float r_beta = fmaf(phi, P.crb, 1.0f);
   const float r_mu = fmaf(phi, fmaf(222.4f, phi, 4.93f), 1.0f);
   const float r_k = fmaf(P.Ck, __powf(phic, 0.764f), 1.0f);
-  const float ir_rho = 1.0f / r_rho;
+  const float ir_rho = frcp(r_rho);
   float tau_p = P.tau_f + P.tp_a * rho_m * fmaf(222.4f, phi, P.tp_b) * ir_rho;
   tau_p = fminf(fmaxf(tau_p, 0.505f), 5.0f);
   if (empty) tau_p = P.tau_f;
-  const float tau_th = fmaf(P.alpha3 * r_k, 1.0f / r_rhoc, 0.5f);
+  const float tau_th = fmaf(P.alpha3 * r_k, frcp(r_rhoc), 0.5f);
 
   // S5: forces.  The fluid carries buoyancy (Eq 20) and the net weight of
   // the particles relative to the uniform suspension; every interaction
@@ -328,33 +362,34 @@ __device__ __forceinline__ float2 node_update(const StepParams& P, float f[9],
   if (!empty) {
     const unsigned on = P.force_on;
     const float wx = uxf - uxp, wy = uyf - uyp;
-    const float wn = sqrtf(fmaf(wx, wx, wy * wy));
-    const float upn = sqrtf(fmaf(uxp, uxp, uyp * uyp));
+    const float wn = fsqrt(fmaf(wx, wx, wy * wy));
+    const float upn = fsqrt(fmaf(uxp, uxp, uyp * uyp));
     const float r_mu2 = r_mu * r_mu;
+    const float ir_mu = frcp(r_mu);
     float aix = 0.0f, aiy = 0.0f;  // interaction forces per particle mass
     if (on & 2u) {  // Brownian, down the phi gradient
       const float Tr = fmaf(P.dT_T0, th, 1.0f);
-      const float c = -P.cB * Tr * Tr / r_mu2;
+      const float c = -P.cB * Tr * Tr * (ir_mu * ir_mu);
       aix = fmaf(c, gphix, aix);
       aiy = fmaf(c, gphiy, aiy);
     }
     if (on & 4u) {  // thermophoresis, down the temperature gradient
       const float Tr = fmaf(P.dT_T0, th, 1.0f);
       const float ks = P.kfp * r_k;
-      const float CT = P.A2 * (ks + P.A1) / fmaf(2.0f, ks + P.A1, 1.0f);
-      const float c = -P.cT * CT * r_mu2 * ir_rho / Tr;
+      const float CT = P.A2 * (ks + P.A1) * frcp(fmaf(2.0f, ks + P.A1, 1.0f));
+      const float c = -P.cT * CT * r_mu2 * ir_rho * frcp(Tr);
       aix = fmaf(c, gthx, aix);
       aiy = fmaf(c, gthy, aiy);
     }
     if (on & 8u) {  // Saffman lift, along the rotated slip
-      const float c = P.cS * sqrtf(r_mu * r_rho * upn);
+      const float c = P.cS * fsqrt(r_mu * r_rho * upn);
       aix = fmaf(-c, wy, aix);
       aiy = fmaf(c, wx, aiy);
     }
     if (on & 16u) {  // Magnus (opposes the slip) + particle rotation
       const float vmx = 0.5f * (uxf + uxp), vmy = 0.5f * (uyf + uyp);
-      const float cm = -0.5f * P.cM * sqrtf(fmaf(vmx, vmx, vmy * vmy));
-      const float iwn = wn > 0.0f ? 1.0f / wn : 0.0f;
+      const float cm = -0.5f * P.cM * fsqrt(fmaf(vmx, vmx, vmy * vmy));
+      const float iwn = wn > 0.0f ? frcp(wn) : 0.0f;
       const float cr = P.cR * r_mu * ir_rho * upn * iwn;
       aix = fmaf(cm, wx, fmaf(-cr, wy, aix));
       aiy = fmaf(cm, wy, fmaf(cr, wx, aiy));
@@ -371,7 +406,7 @@ __device__ __forceinline__ float2 node_update(const StepParams& P, float f[9],
       // reference.  Written this way no large terms cancel (the reacting
       // forces and the drag nearly balance each other).
       const float r = rho_p * irf;
-      const float Red = P.cRe * wn / r_mu;
+      const float Red = P.cRe * wn * ir_mu;
       const float beta = P.cD * r_mu * fmaf(0.15f, __powf(Red, 0.687f), 1.0f);
       const float kap = beta * (1.0f + r);
       float ph1, ph2;
@@ -379,8 +414,9 @@ __device__ __forceinline__ float2 node_update(const StepParams& P, float f[9],
         ph1 = fmaf(kap, fmaf(kap, fmaf(kap, -1.0f / 24.0f, 1.0f / 6.0f), -0.5f), 1.0f);
         ph2 = fmaf(kap, fmaf(kap, fmaf(kap, -1.0f / 120.0f, 1.0f / 24.0f), -1.0f / 6.0f), 0.5f);
       } else {
-        ph1 = -expm1f(-kap) / kap;
-        ph2 = (1.0f - ph1) / kap;
+        const float ik = frcp(kap);
+        ph1 = -expm1f(-kap) * ik;
+        ph2 = (1.0f - ph1) * ik;
       }
       // The gravity terms (settling, fluid reference) combine, with
       // beta phi2 = (1 - phi1)/(1 + r), into
@@ -401,8 +437,8 @@ __device__ __forceinline__ float2 node_update(const StepParams& P, float f[9],
   // S6: collisions; f and p relax to their own velocities, g to u_ns
   collide(f, m.drf, rho_f, m.jxf, m.jyf, uxf, uyf, P.omega_f, Ffx, Ffy);
   collide(p, m.drp, rho_p, empty ? rho_p * uxf : m.jxp, empty ? rho_p * uyf : m.jyp, uxp, uyp,
-          1.0f / tau_p, Fpx, Fpy);
-  collide(g, th, th, th * uxn, th * uyn, uxn, uyn, 1.0f / tau_th, 0.0f, 0.0f);
+          frcp(tau_p), Fpx, Fpy);
+  collide(g, th, th, th * uxn, th * uyn, uxn, uyn, frcp(tau_th), 0.0f, 0.0f);
   return make_float2(m.drp * P.invR, th);
 }
 

@@ -22,7 +22,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/mclbm.h"
+#include "mclbm.h"
 #include "lbm_device.h"
 
 using namespace mclbm;
@@ -65,17 +65,29 @@ __global__ __launch_bounds__(256) void k_init(StepParams P,
   d2prev[n] = make_float2(m.drp * P.invR, m.th);
 }
 
-template <bool ODD, class S>
+// Workgroups are dealt round-robin to the 8 XCDs of the chip, each with its
+// own L2.  The step kernel runs on a 1-D grid and maps workgroup b to tile
+// start(b % 8) + b / 8, so that each XCD sweeps one contiguous band of rows:
+// the neighbour rows an odd step and the lag-field stencil touch are then
+// mostly in the same L2.
+__device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned nb) {
+  const unsigned q = nb >> 3, r = nb & 7u, k = b & 7u;
+  return k * q + (k < r ? k : r) + (b >> 3);
+}
+
+template <bool ODD, class S, class I>
 __global__ __launch_bounds__(256) void k_step(StepParams P,
                                               typename S::T* __restrict__ pop,
                                               const float2* __restrict__ d2p,
                                               float2* __restrict__ d2c,
-                                              float* __restrict__ d5) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+                                              float* __restrict__ d5,
+                                              int tiles_x) {
+  const unsigned t = xcd_tile(blockIdx.x, gridDim.x);
+  const int x = (int)(t % (unsigned)tiles_x) * blockDim.x + threadIdx.x;
+  const int y = (int)(t / (unsigned)tiles_x) * blockDim.y + threadIdx.y;
   if (x >= P.nx || y >= P.ny) return;
   float f[9], p[9], g[9];
-  load_node<ODD, S>(P, pop, d5, x, y, f, p, g);
+  load_node<ODD, S, I>(P, pop, d5, x, y, f, p, g);
 
   // S4: central differences of the previous step's (phi, theta); zero-flux
   // mirror ghosts for phi on all walls and for theta on the adiabatic walls,
@@ -94,7 +106,7 @@ __global__ __launch_bounds__(256) void k_step(StepParams P,
   const float gthx = 0.5f * (thE - thW), gthy = 0.5f * (vN.y - vS.y);
 
   const float2 keep = node_update(P, f, p, g, gphix, gphiy, gthx, gthy);
-  store_node<ODD, S>(P, pop, d5, x, y, f, p, g);
+  store_node<ODD, S, I>(P, pop, d5, x, y, f, p, g);
   d2c[n] = keep;
 }
 
@@ -114,7 +126,7 @@ __device__ double block_sum(double v, double* lds) {
   return r;
 }
 
-template <bool ODD, class S>
+template <bool ODD, class S, class I>
 __global__ __launch_bounds__(256) void k_nusselt(StepParams P,
                                                  const typename S::T* __restrict__ pop,
                                                  const float* __restrict__ d5,
@@ -130,7 +142,7 @@ __global__ __launch_bounds__(256) void k_nusselt(StepParams P,
     double rp = rho_p_ref;
     for (int q = 0; q < 4; ++q) {
       float f[9], p[9], g[9];
-      load_node<ODD, S>(P, const_cast<typename S::T*>(pop), d5, xs[q], y, f, p, g);
+      load_node<ODD, S, I>(P, pop, d5, xs[q], y, f, p, g);
       double t = 0.0;
       for (int i = 0; i < 9; ++i) t += (double)g[i];
       th[q] = t;
@@ -161,7 +173,7 @@ __global__ __launch_bounds__(256) void k_nusselt(StepParams P,
 
 // Per-block partial sums of |u - u_ref|^2, |u|^2, (theta - theta_ref)^2,
 // theta^2 and a non-finite count; the snapshot is replaced by the state.
-template <bool ODD, class S>
+template <bool ODD, class S, class I>
 __global__ __launch_bounds__(256) void k_residual(StepParams P,
                                                   const typename S::T* __restrict__ pop,
                                                   const float* __restrict__ d5,
@@ -175,7 +187,7 @@ __global__ __launch_bounds__(256) void k_residual(StepParams P,
   if (k < nn) {
     const int x = (int)(k % P.nx), y = (int)(k / P.nx);
     float f[9], p[9], g[9];
-    load_node<ODD, S>(P, const_cast<typename S::T*>(pop), d5, x, y, f, p, g);
+    load_node<ODD, S, I>(P, pop, d5, x, y, f, p, g);
     double rf = rho_f_ref, rp = rho_p_ref, jx = 0.0, jy = 0.0, th = 0.0;
     for (int i = 0; i < 9; ++i) {
       rf += (double)f[i];
@@ -220,7 +232,7 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__
 }
 
 // Snapshot of the initial state for the first residual call.
-template <bool ODD, class S>
+template <bool ODD, class S, class I>
 __global__ __launch_bounds__(256) void k_export(StepParams P,
                                                 const typename S::T* __restrict__ pop,
                                                 const float* __restrict__ d5,
@@ -232,7 +244,7 @@ __global__ __launch_bounds__(256) void k_export(StepParams P,
   if (k >= nn) return;
   const int x = (int)(k % P.nx), y = (int)(k / P.nx);
   float f[9], p[9], g[9];
-  load_node<ODD, S>(P, const_cast<typename S::T*>(pop), d5, x, y, f, p, g);
+  load_node<ODD, S, I>(P, pop, d5, x, y, f, p, g);
   double rf = rho_f_ref, rp = rho_p_ref, jxf = 0, jyf = 0, jxp = 0, jyp = 0, th = 0;
   for (int i = 0; i < 9; ++i) {
     rf += (double)f[i];
@@ -260,7 +272,7 @@ __global__ __launch_bounds__(256) void k_export(StepParams P,
 // Populations after streaming with the storage shift added back; q < 0
 // writes all 27 planes, otherwise only plane q (lattice q / 9, direction
 // q % 9) into out[0 .. nx*ny).
-template <bool ODD, class S>
+template <bool ODD, class S, class I>
 __global__ __launch_bounds__(256) void k_export_pops(StepParams P,
                                                      const typename S::T* __restrict__ pop,
                                                      const float* __restrict__ d5,
@@ -271,7 +283,7 @@ __global__ __launch_bounds__(256) void k_export_pops(StepParams P,
   if (k >= nn) return;
   const int x = (int)(k % P.nx), y = (int)(k / P.nx);
   float f[9], p[9], g[9];
-  load_node<ODD, S>(P, const_cast<typename S::T*>(pop), d5, x, y, f, p, g);
+  load_node<ODD, S, I>(P, pop, d5, x, y, f, p, g);
   for (int i = 0; i < 9; ++i) {
     const double w = wgt_d(i);
     const double vf = (double)f[i] + w * rho_f_ref;
@@ -402,7 +414,7 @@ int validate(const mclbm_config* c) {
   if (c->storage != MCLBM_FP32S)
     return fail(MCLBM_EUNSUPPORTED, "16-bit population storage is not available in this build");
   const int bx = c->block_x == 0 ? 64 : c->block_x;
-  const int by = c->block_y == 0 ? 4 : c->block_y;
+  const int by = c->block_y == 0 ? 1 : c->block_y;
   if (!(bx == 32 || bx == 64 || bx == 128 || bx == 256) || by < 1 ||
       !(bx * by == 64 || bx * by == 128 || bx * by == 256))
     return fail(MCLBM_EINVAL, "block shape must have block_x in {32,64,128,256} and 64..256 threads");
@@ -540,10 +552,14 @@ struct mclbm_cavity {
   Derived D;
   StepParams P;
   int64_t t;
-  dim3 block, grid;
-  std::vector<double> host_dev_p;  // initial phi deviations (kept for async copy)
+  dim3 block;          // step-kernel workgroup shape
+  unsigned nblocks;    // step-kernel 1-D grid (tiles)
+  int tiles_x;
+  bool nt;             // non-temporal population traffic
+  bool idx32;          // 32-bit element offsets
+  std::vector<double> host_dev_p;  // initial phi deviations (source of an async copy)
 
-  typename StorF32::T* pop() { return reinterpret_cast<float*>(base + L.off_pop); }
+  void* pop() { return base + L.off_pop; }
   float2* d2(int k) { return reinterpret_cast<float2*>(base + L.off_d2) + (size_t)k * L.plane; }
   float* d5() { return reinterpret_cast<float*>(base + L.off_d5); }
   double* snap() { return reinterpret_cast<double*>(base + L.off_snap); }
@@ -558,6 +574,31 @@ int launch_check(const char* what) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, what);
   return MCLBM_OK;
+}
+
+// Kernel type selection: storage format S (temporal access), its streaming
+// variant SN used by the step kernel, and the index type I.
+template <class S_, class SN_, class I_>
+struct KTypes {
+  using S = S_;
+  using SN = SN_;
+  using I = I_;
+};
+
+template <class Fn>
+int dispatch(const mclbm_cavity* c, Fn&& fn) {
+  if (c->cfg.storage != MCLBM_FP32S) return fail(MCLBM_EUNSUPPORTED, "storage type not built");
+  if (c->idx32) {
+    if (c->nt) return fn(KTypes<StorF32<false>, StorF32<true>, uint32_t>{});
+    return fn(KTypes<StorF32<false>, StorF32<false>, uint32_t>{});
+  }
+  if (c->nt) return fn(KTypes<StorF32<false>, StorF32<true>, uint64_t>{});
+  return fn(KTypes<StorF32<false>, StorF32<false>, uint64_t>{});
+}
+
+// Grid over all nodes for the auxiliary kernels.
+unsigned node_blocks(const mclbm_cavity* c) {
+  return (unsigned)(((long long)c->cfg.nx * c->cfg.ny + 255) / 256);
 }
 
 int enqueue_init(mclbm_cavity* c) {
@@ -575,30 +616,70 @@ int enqueue_init(mclbm_cavity* c) {
   const double dev_f = c->D.v[MCLBM_D_RHO_F0] - (double)c->P.rho_f_ref;
   HIP_TRY(hipMemcpyAsync(c->stage(), c->host_dev_p.data(), (size_t)nn * sizeof(double),
                          hipMemcpyHostToDevice, c->stream));
-  k_init<StorF32><<<c->grid, c->block, 0, c->stream>>>(c->P, c->pop(), c->stage(), dev_f, c->d2(1));
-  int rc = launch_check("k_init");
-  if (rc) return rc;
   HIP_TRY(hipMemsetAsync(c->d5(), 0, (size_t)6 * c->L.px * sizeof(float), c->stream));
-  c->t = 0;
-  // snapshot of the initial state for the first residual call
-  const unsigned rb = (unsigned)c->L.red_blocks;
-  k_residual<false, StorF32><<<rb, 256, 0, c->stream>>>(
-      c->P, c->pop(), c->d5(), (double)c->P.rho_f_ref, (double)c->P.rho_p_ref, c->snap(), c->part());
-  rc = launch_check("k_residual");
+  int rc = dispatch(c, [&](auto k) {
+    using S = typename decltype(k)::S;
+    using I = typename decltype(k)::I;
+    auto* pop = reinterpret_cast<typename S::T*>(c->pop());
+    const dim3 b2(64, 4, 1), g2((cfg.nx + 63) / 64, (cfg.ny + 3) / 4, 1);
+    k_init<S><<<g2, b2, 0, c->stream>>>(c->P, pop, c->stage(), dev_f, c->d2(1));
+    int r = launch_check("k_init");
+    if (r) return r;
+    // snapshot of the initial state for the first residual call
+    k_residual<false, S, I><<<c->L.red_blocks, 256, 0, c->stream>>>(
+        c->P, pop, c->d5(), (double)c->P.rho_f_ref, (double)c->P.rho_p_ref, c->snap(), c->part());
+    return launch_check("k_residual");
+  });
   if (rc) return rc;
+  c->t = 0;
   HIP_TRY(hipStreamSynchronize(c->stream));
   return MCLBM_OK;
 }
+
+// Working sets above this size stream from HBM; below it they stay in the
+// 256 MB last-level (Infinity) cache, where non-temporal access hurts.
+constexpr size_t kStreamingBytes = 160u << 20;
 
 int setup_cavity(mclbm_cavity* c) {
   derive(c->cfg, c->D);
   c->L = make_layout(c->cfg);
   c->P = make_params(c->cfg, c->D, c->L);
-  const int bx = c->cfg.block_x == 0 ? 64 : c->cfg.block_x;
-  const int by = c->cfg.block_y == 0 ? 4 : c->cfg.block_y;
+  int bx = c->cfg.block_x, by = c->cfg.block_y;
+  if (bx == 0) bx = c->cfg.nx >= 256 ? 256 : 64;
+  if (by == 0) by = 1;
   c->block = dim3(bx, by, 1);
-  c->grid = dim3((c->cfg.nx + bx - 1) / bx, (c->cfg.ny + by - 1) / by, 1);
+  c->tiles_x = (c->cfg.nx + bx - 1) / bx;
+  c->nblocks = (unsigned)c->tiles_x * (unsigned)((c->cfg.ny + by - 1) / by);
+  const size_t pop_bytes = (size_t)27 * c->L.plane * storage_bytes(c->cfg.storage);
+  c->nt = pop_bytes + (size_t)2 * c->L.plane * sizeof(float2) > kStreamingBytes;
+  c->idx32 = pop_bytes < ((size_t)1 << 31);
   return MCLBM_OK;
+}
+
+template <class K>
+int launch_step(mclbm_cavity* c) {
+  using SN = typename K::SN;
+  using I = typename K::I;
+  auto* pop = reinterpret_cast<typename SN::T*>(c->pop());
+  if ((c->t & 1) == 0)
+    k_step<false, SN, I><<<c->nblocks, c->block, 0, c->stream>>>(c->P, pop, c->d2(1), c->d2(0), c->d5(), c->tiles_x);
+  else
+    k_step<true, SN, I><<<c->nblocks, c->block, 0, c->stream>>>(c->P, pop, c->d2(0), c->d2(1), c->d5(), c->tiles_x);
+  return launch_check("k_step");
+}
+
+int export_pops(mclbm_cavity* c, int q, double* dev_out) {
+  const double rf = (double)c->P.rho_f_ref, rp = (double)c->P.rho_p_ref;
+  return dispatch(c, [&](auto k) {
+    using S = typename decltype(k)::S;
+    using I = typename decltype(k)::I;
+    const auto* pop = reinterpret_cast<const typename S::T*>(c->pop());
+    if (c->t & 1)
+      k_export_pops<true, S, I><<<node_blocks(c), 256, 0, c->stream>>>(c->P, pop, c->d5(), rf, rp, q, dev_out);
+    else
+      k_export_pops<false, S, I><<<node_blocks(c), 256, 0, c->stream>>>(c->P, pop, c->d5(), rf, rp, q, dev_out);
+    return launch_check("k_export_pops");
+  });
 }
 
 }  // namespace
@@ -696,17 +777,14 @@ int mclbm_reset(mclbm_cavity* c) {
 int mclbm_step(mclbm_cavity* c, int64_t nsteps) {
   if (!c) return fail(MCLBM_EINVAL, "cavity is NULL");
   if (nsteps < 0) return fail(MCLBM_EINVAL, "nsteps must be >= 0");
-  for (int64_t s = 0; s < nsteps; ++s) {
-    const int k = (int)(c->t & 1);
-    if (k == 0)
-      k_step<false, StorF32><<<c->grid, c->block, 0, c->stream>>>(c->P, c->pop(), c->d2(1), c->d2(0), c->d5());
-    else
-      k_step<true, StorF32><<<c->grid, c->block, 0, c->stream>>>(c->P, c->pop(), c->d2(0), c->d2(1), c->d5());
-    int rc = launch_check("k_step");
-    if (rc) return rc;
-    c->t += 1;
-  }
-  return MCLBM_OK;
+  return dispatch(c, [&](auto k) {
+    for (int64_t s = 0; s < nsteps; ++s) {
+      int rc = launch_step<decltype(k)>(c);
+      if (rc) return rc;
+      c->t += 1;
+    }
+    return (int)MCLBM_OK;
+  });
 }
 
 int64_t mclbm_time(const mclbm_cavity* c) { return c ? c->t : -1; }
@@ -717,14 +795,18 @@ int mclbm_export_moments(mclbm_cavity* c, uint32_t mask, double* dev_out, size_t
   const long long nn = (long long)c->cfg.nx * c->cfg.ny;
   const int nf = __builtin_popcount(mask);
   if (n_doubles < (size_t)nf * nn) return fail(MCLBM_EINVAL, "output too small");
-  const unsigned nb = (unsigned)((nn + 255) / 256);
   const double rf = (double)c->P.rho_f_ref, rp = (double)c->P.rho_p_ref;
   const double invR = 1.0 / c->D.v[MCLBM_D_R];
-  if (c->t & 1)
-    k_export<true, StorF32><<<nb, 256, 0, c->stream>>>(c->P, c->pop(), c->d5(), rf, rp, invR, mask, dev_out);
-  else
-    k_export<false, StorF32><<<nb, 256, 0, c->stream>>>(c->P, c->pop(), c->d5(), rf, rp, invR, mask, dev_out);
-  return launch_check("k_export");
+  return dispatch(c, [&](auto k) {
+    using S = typename decltype(k)::S;
+    using I = typename decltype(k)::I;
+    const auto* pop = reinterpret_cast<const typename S::T*>(c->pop());
+    if (c->t & 1)
+      k_export<true, S, I><<<node_blocks(c), 256, 0, c->stream>>>(c->P, pop, c->d5(), rf, rp, invR, mask, dev_out);
+    else
+      k_export<false, S, I><<<node_blocks(c), 256, 0, c->stream>>>(c->P, pop, c->d5(), rf, rp, invR, mask, dev_out);
+    return launch_check("k_export");
+  });
 }
 
 int mclbm_read_moments(mclbm_cavity* c, uint32_t mask, double* host_out, size_t n_doubles) {
@@ -745,18 +827,6 @@ int mclbm_read_moments(mclbm_cavity* c, uint32_t mask, double* host_out, size_t 
   return MCLBM_OK;
 }
 
-namespace {
-int export_pops(mclbm_cavity* c, int q, double* dev_out) {
-  const long long nn = (long long)c->cfg.nx * c->cfg.ny;
-  const unsigned nb = (unsigned)((nn + 255) / 256);
-  const double rf = (double)c->P.rho_f_ref, rp = (double)c->P.rho_p_ref;
-  if (c->t & 1)
-    k_export_pops<true, StorF32><<<nb, 256, 0, c->stream>>>(c->P, c->pop(), c->d5(), rf, rp, q, dev_out);
-  else
-    k_export_pops<false, StorF32><<<nb, 256, 0, c->stream>>>(c->P, c->pop(), c->d5(), rf, rp, q, dev_out);
-  return launch_check("k_export_pops");
-}
-}  // namespace
 
 int mclbm_export_populations(mclbm_cavity* c, double* dev_out, size_t n_doubles) {
   if (!c || !dev_out) return fail(MCLBM_EINVAL, "NULL argument");
@@ -782,11 +852,16 @@ int mclbm_read_populations(mclbm_cavity* c, double* host_out, size_t n_doubles) 
 int mclbm_nusselt(mclbm_cavity* c, double* nu_hot, double* nu_cold, double* nu_hot_k) {
   if (!c) return fail(MCLBM_EINVAL, "cavity is NULL");
   const double rp = (double)c->P.rho_p_ref, R = c->D.v[MCLBM_D_R], Ck = c->D.v[MCLBM_D_CK];
-  if (c->t & 1)
-    k_nusselt<true, StorF32><<<1, 256, 0, c->stream>>>(c->P, c->pop(), c->d5(), rp, R, Ck, c->res());
-  else
-    k_nusselt<false, StorF32><<<1, 256, 0, c->stream>>>(c->P, c->pop(), c->d5(), rp, R, Ck, c->res());
-  int rc = launch_check("k_nusselt");
+  int rc = dispatch(c, [&](auto k) {
+    using S = typename decltype(k)::S;
+    using I = typename decltype(k)::I;
+    const auto* pop = reinterpret_cast<const typename S::T*>(c->pop());
+    if (c->t & 1)
+      k_nusselt<true, S, I><<<1, 256, 0, c->stream>>>(c->P, pop, c->d5(), rp, R, Ck, c->res());
+    else
+      k_nusselt<false, S, I><<<1, 256, 0, c->stream>>>(c->P, pop, c->d5(), rp, R, Ck, c->res());
+    return launch_check("k_nusselt");
+  });
   if (rc) return rc;
   double h[4];
   HIP_TRY(hipMemcpyAsync(h, c->res(), sizeof(h), hipMemcpyDeviceToHost, c->stream));
@@ -802,11 +877,16 @@ int mclbm_residual(mclbm_cavity* c, double* res_u, double* res_theta) {
   if (!c) return fail(MCLBM_EINVAL, "cavity is NULL");
   const unsigned rb = (unsigned)c->L.red_blocks;
   const double rf = (double)c->P.rho_f_ref, rp = (double)c->P.rho_p_ref;
-  if (c->t & 1)
-    k_residual<true, StorF32><<<rb, 256, 0, c->stream>>>(c->P, c->pop(), c->d5(), rf, rp, c->snap(), c->part());
-  else
-    k_residual<false, StorF32><<<rb, 256, 0, c->stream>>>(c->P, c->pop(), c->d5(), rf, rp, c->snap(), c->part());
-  int rc = launch_check("k_residual");
+  int rc = dispatch(c, [&](auto k) {
+    using S = typename decltype(k)::S;
+    using I = typename decltype(k)::I;
+    const auto* pop = reinterpret_cast<const typename S::T*>(c->pop());
+    if (c->t & 1)
+      k_residual<true, S, I><<<rb, 256, 0, c->stream>>>(c->P, pop, c->d5(), rf, rp, c->snap(), c->part());
+    else
+      k_residual<false, S, I><<<rb, 256, 0, c->stream>>>(c->P, pop, c->d5(), rf, rp, c->snap(), c->part());
+    return launch_check("k_residual");
+  });
   if (rc) return rc;
   k_sum_partials<<<1, 256, 0, c->stream>>>(c->part(), (int)rb, c->res() + 4);
   rc = launch_check("k_sum_partials");
