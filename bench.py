@@ -26,7 +26,7 @@ BYTES_PER_LUP_FP32 = 232        # 27 populations read + written (4 B), lag field
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--steps", type=int, default=50000)
     ap.add_argument("--warmup", type=int, default=2000)
     ap.add_argument("--workload", default="cavity512_ra1e5")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
@@ -34,6 +34,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="HBM bytes per launch measured by rocprofv3 counters")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the 2048^2 (larger than the last-level cache) measurement")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="summarise two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this "
+                         "bench into the traffic file and exit")
     return ap.parse_args()
 
 
@@ -53,6 +58,52 @@ def copy_bandwidth(torch, mc, nbytes=1 << 30, reps=20):
     ms = e0.elapsed_time(e1) / reps
     del src, dst
     return 2.0 * nbytes / (ms * 1e-3) / 1e9
+
+
+def time_steps(torch, cav, n):
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(cav.stream)
+    cav.step(n)
+    e1.record(cav.stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / n
+
+
+def _counter_rows(d):
+    import csv
+    import glob
+    rows = []
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        rows += list(csv.DictReader(open(f)))
+    return rows
+
+
+def pmc_summary(fetch_dir, write_dir, workload, out_path):
+    """Bytes per launch of the step kernels from FETCH_SIZE / WRITE_SIZE
+    (KiB per dispatch), each scaled by what the same counter reads for the
+    1 GiB copy kernel this bench runs (known to move 1 GiB each way)."""
+    res = {}
+    for name, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        per = {}
+        for r in _counter_rows(d):
+            if r["Counter_Name"] != name:
+                continue
+            k = r["Kernel_Name"]
+            key = "copy" if k.startswith("k_copy") else ("step_even" if "k_step<false" in k else
+                                                         "step_odd" if "k_step<true" in k else None)
+            if key:
+                per.setdefault(key, []).append(float(r["Counter_Value"]))
+        scale = (1 << 20) / (sum(per["copy"]) / len(per["copy"]))  # KiB of 1 GiB / counted
+        res[name] = {"scale": scale, **{k: sum(v) / len(v) * 1024 * scale for k, v in per.items() if k != "copy"}}
+    per_launch = {k: res["FETCH_SIZE"][k] + res["WRITE_SIZE"][k] for k in ("step_even", "step_odd")}
+    out = {"workload": workload, "kernel_hash": kernel_hash(),
+           "bytes_per_launch": 0.5 * (per_launch["step_even"] + per_launch["step_odd"]),
+           "fetch_bytes": {k: res["FETCH_SIZE"][k] for k in ("step_even", "step_odd")},
+           "write_bytes": {k: res["WRITE_SIZE"][k] for k in ("step_even", "step_odd")},
+           "fetch_scale": res["FETCH_SIZE"]["scale"], "write_scale": res["WRITE_SIZE"]["scale"]}
+    json.dump(out, open(out_path, "w"), indent=1)
+    print(json.dumps(out, indent=1))
 
 
 def cpu_baseline(w, xi, seconds):
@@ -78,6 +129,9 @@ def cpu_baseline(w, xi, seconds):
 
 def main():
     a = parse()
+    if a.pmc_summary:
+        pmc_summary(a.pmc_summary[0], a.pmc_summary[1], a.workload, a.traffic)
+        return
     if a.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {a.gpus}); the multi-GPU "
               "decomposition is a design only in this build.", file=sys.stderr)
@@ -125,6 +179,22 @@ def main():
         except Exception:
             traffic = None
     copy_gbps = copy_bandwidth(torch, mc)
+    secondary = None
+    if not a.no_secondary:
+        w2 = inputs.WORKLOADS["cavity2048_ra1e6"]
+        cfg2 = {k: v for k, v in w2.items() if k != "seed"}
+        del cav
+        torch.cuda.empty_cache()
+        cav2 = mc.Cavity(xi=inputs.phi_perturbation(w2["seed"], cfg2["nx"], cfg2["ny"]), **cfg2)
+        cav2.step(20)
+        ms2 = time_steps(torch, cav2, 200)
+        n2 = cfg2["nx"] * cfg2["ny"]
+        gbs2 = BYTES_PER_LUP_FP32 * n2 / (ms2 * 1e-3) / 1e9
+        secondary = {"workload": "cavity2048_ra1e6", "nx": cfg2["nx"], "ny": cfg2["ny"], "steps": 200,
+                     "ms_per_step": round(ms2, 5), "MLUPS": round(n2 / (ms2 * 1e-3) / 1e6, 1),
+                     "achieved_GBps": round(gbs2, 1), "frac": round(gbs2 / HBM_PEAK_GBPS, 4)}
+        del cav2
+        torch.cuda.empty_cache()
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
             "kernel": "k_step (even and odd A-A parities)",
@@ -140,6 +210,7 @@ def main():
                    "storage": "fp32 shifted SoA, A-A in place", "parallelism": "single GPU"},
         "roofline": roof,
         "nu_hot": nu_hot,
+        "larger_than_llc": secondary,
     }
     if not a.no_cpu_baseline:
         print("# cpu baseline (FP64 oracle) ...", file=sys.stderr, flush=True)

@@ -78,18 +78,30 @@ __device__ __forceinline__ T* elem(T* base, I idx) {
   return const_cast<T*>(elem(const_cast<const T*>(base), idx));
 }
 
-// FP32 deviations.  NT = true marks the population traffic non-temporal
-// (streamed past the caches) for cavities larger than the last-level cache.
-template <bool NT>
+// FP32 deviations.  NTL / NTS mark the population loads / stores
+// non-temporal (streamed past the caches), for cavities larger than the
+// last-level cache.
+// Buffer-resource forms (bld / bst) take a byte offset per lane (voff) and
+// a wave-uniform byte offset (soff); policy bit 2 is the non-temporal hint.
+template <bool NTL, bool NTS = NTL>
 struct StorF32 {
   using T = float;
+  static constexpr int kLdPol = NTL ? 2 : 0, kStPol = NTS ? 2 : 0;
   static __device__ __forceinline__ float ld(const T* p, float) {
-    if constexpr (NT) return __builtin_nontemporal_load(p);
+    if constexpr (NTL) return __builtin_nontemporal_load(p);
     else return *p;
   }
   static __device__ __forceinline__ void st(T* p, float v, float) {
-    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    if constexpr (NTS) __builtin_nontemporal_store(v, p);
     else *p = v;
+  }
+  static __device__ __forceinline__ float bld(__amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                              uint32_t soff, float) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, kLdPol));
+  }
+  static __device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff,
+                                             float v, float) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)voff, (int)soff, kStPol);
   }
 };
 // 16-bit deviations scaled by a power of two per lattice (scale[l] on store,
@@ -148,86 +160,176 @@ struct StepParams {
   unsigned force_on;     // bit k set when force k has a non-zero coefficient
 };
 
-// ---- A-A access: read the nine populations of each lattice --------------
+// ---- A-A access ------------------------------------------------------------
+// Arrays below 2 GiB are accessed through a buffer resource: one per-lane
+// byte offset shared by all 27 accesses of a node, and a wave-uniform scalar
+// offset per plane that also carries the neighbour shift (x and row), so no
+// per-access address arithmetic runs on the vector units.  Lanes next to a
+// wall take a separate, exec-masked path, which waves away from the walls
+// skip.  Larger arrays use 64-bit pointer arithmetic.
+// Buffer resource over the population array (raw, byte-addressed, range
+// checked against its size).
+template <class T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t pop_rsrc(const T* pop, const StepParams& P) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(pop), 0,
+                                           (int)(27u * (uint32_t)P.plane * (uint32_t)sizeof(T)),
+                                           0x00020000);
+}
+// wave-uniform byte offset of plane q shifted by (dx, dy) nodes
+template <class T>
+__device__ __forceinline__ uint32_t soff(const StepParams& P, int q, int dx, int dy) {
+  return (uint32_t)(q * (int)P.plane + dy * P.px + dx) * (uint32_t)sizeof(T);
+}
+
+// ---- read the nine populations of each lattice ------------------------------
 template <bool ODD, class S, class I>
 __device__ __forceinline__ void load_node(const StepParams& P,
                                           const typename S::T* __restrict__ pop,
                                           const float* __restrict__ d5, int x,
                                           int y, float f[9], float p[9],
                                           float g[9]) {
+  using T = typename S::T;
   const I px = (I)P.px, pl = (I)P.plane;
   const I n = (I)y * px + (I)x;
   const bool xl = x == 0, xr = x == P.nx - 1, yb = y == 0, yt = y == P.ny - 1;
+  if constexpr (sizeof(I) == 4) {
+    const __amdgpu_buffer_rsrc_t R = pop_rsrc(pop, P);
+    const uint32_t vo = (uint32_t)n * (uint32_t)sizeof(T);
 #pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    if (!ODD) {
-      f[i] = S::ld(elem(pop, pl * (I)i + n), P.inv_scale[0]);
-      p[i] = S::ld(elem(pop, pl * (I)(9 + i) + n), P.inv_scale[1]);
-      g[i] = S::ld(elem(pop, pl * (I)(18 + i) + n), P.inv_scale[2]);
-    } else {
-      const bool outx = (ex(i) == 1 && xl) || (ex(i) == -1 && xr);
-      const bool outy = (ey(i) == 1 && yb) || (ey(i) == -1 && yt);
-      const bool out = outx || outy;
-      // inside: upstream node's slot opp(i); wall link: own slot i
-      const I up = n - (I)ex(i) - (I)ey(i) * px;  // wraps only when unused
-      const I a = out ? (pl * (I)i + n) : (pl * (I)opp(i) + up);
-      f[i] = S::ld(elem(pop, a), P.inv_scale[0]);
-      p[i] = S::ld(elem(pop, pl * (I)9 + a), P.inv_scale[1]);
-      if (i == 0) {
-        g[i] = S::ld(elem(pop, pl * (I)18 + a), P.inv_scale[2]);
-      } else if (outy) {
-        g[i] = d5[((ey(i) == 1 ? 0 : 3) + d5slot(i)) * P.px + x];
+    for (int i = 0; i < 9; ++i) {
+      if (!ODD) {
+        f[i] = S::bld(R, vo, soff<T>(P, i, 0, 0), P.inv_scale[0]);
+        p[i] = S::bld(R, vo, soff<T>(P, 9 + i, 0, 0), P.inv_scale[1]);
+        g[i] = S::bld(R, vo, soff<T>(P, 18 + i, 0, 0), P.inv_scale[2]);
       } else {
-        const float v = S::ld(elem(pop, pl * (I)18 + a), P.inv_scale[2]);
-        g[i] = outx ? (xl ? wgt(i) : -wgt(i)) - v : v;
+        const bool outx = (ex(i) == 1 && xl) || (ex(i) == -1 && xr);
+        const bool outy = (ey(i) == 1 && yb) || (ey(i) == -1 && yt);
+        if (!(outx || outy)) {
+          // upstream node x - e_i, slot opp(i)
+          f[i] = S::bld(R, vo, soff<T>(P, opp(i), -ex(i), -ey(i)), P.inv_scale[0]);
+          p[i] = S::bld(R, vo, soff<T>(P, 9 + opp(i), -ex(i), -ey(i)), P.inv_scale[1]);
+          g[i] = S::bld(R, vo, soff<T>(P, 18 + opp(i), -ex(i), -ey(i)), P.inv_scale[2]);
+        } else {
+          // wall link: own slot i (bounce-back); g by the wall rule
+          f[i] = S::bld(R, vo, soff<T>(P, i, 0, 0), P.inv_scale[0]);
+          p[i] = S::bld(R, vo, soff<T>(P, 9 + i, 0, 0), P.inv_scale[1]);
+          if (outy) {
+            g[i] = d5[((ey(i) == 1 ? 0 : 3) + d5slot(i)) * P.px + x];
+          } else {
+            const float v = S::bld(R, vo, soff<T>(P, 18 + i, 0, 0), P.inv_scale[2]);
+            g[i] = (xl ? wgt(i) : -wgt(i)) - v;
+          }
+        }
+      }
+    }
+    return;
+  } else {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      if (!ODD) {
+        f[i] = S::ld(elem(pop, pl * (I)i + n), P.inv_scale[0]);
+        p[i] = S::ld(elem(pop, pl * (I)(9 + i) + n), P.inv_scale[1]);
+        g[i] = S::ld(elem(pop, pl * (I)(18 + i) + n), P.inv_scale[2]);
+      } else {
+        const bool outx = (ex(i) == 1 && xl) || (ex(i) == -1 && xr);
+        const bool outy = (ey(i) == 1 && yb) || (ey(i) == -1 && yt);
+        const bool out = outx || outy;
+        // inside: upstream node's slot opp(i); wall link: own slot i
+        const I up = n - (I)ex(i) - (I)ey(i) * px;  // wraps only when unused
+        const I a = out ? (pl * (I)i + n) : (pl * (I)opp(i) + up);
+        f[i] = S::ld(elem(pop, a), P.inv_scale[0]);
+        p[i] = S::ld(elem(pop, pl * (I)9 + a), P.inv_scale[1]);
+        if (i == 0) {
+          g[i] = S::ld(elem(pop, pl * (I)18 + a), P.inv_scale[2]);
+        } else if (outy) {
+          g[i] = d5[((ey(i) == 1 ? 0 : 3) + d5slot(i)) * P.px + x];
+        } else {
+          const float v = S::ld(elem(pop, pl * (I)18 + a), P.inv_scale[2]);
+          g[i] = outx ? (xl ? wgt(i) : -wgt(i)) - v : v;
+        }
       }
     }
   }
 }
 
-// ---- A-A access: write the post-collision populations --------------------
+// ---- write the post-collision populations -----------------------------------
 template <bool ODD, class S, class I>
 __device__ __forceinline__ void store_node(const StepParams& P,
                                            typename S::T* __restrict__ pop,
                                            float* __restrict__ d5, int x, int y,
                                            const float f[9], const float p[9],
                                            const float g[9]) {
+  using T = typename S::T;
   const I px = (I)P.px, pl = (I)P.plane;
   const I n = (I)y * px + (I)x;
   const int nx = P.nx, ny = P.ny;
   const bool xl = x == 0, xr = x == nx - 1, yb = y == 0, yt = y == ny - 1;
+  if constexpr (sizeof(I) == 4) {
+    const __amdgpu_buffer_rsrc_t R = pop_rsrc(pop, P);
+    const uint32_t vo = (uint32_t)n * (uint32_t)sizeof(T);
 #pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    if (!ODD) {
-      S::st(elem(pop, pl * (I)opp(i) + n), f[i], P.scale[0]);
-      S::st(elem(pop, pl * (I)(9 + opp(i)) + n), p[i], P.scale[1]);
-      S::st(elem(pop, pl * (I)(18 + opp(i)) + n), g[i], P.scale[2]);
-    } else {
-      const bool outx = (ex(i) == 1 && xr) || (ex(i) == -1 && xl);
-      const bool outy = (ey(i) == 1 && yt) || (ey(i) == -1 && yb);
-      const bool out = outx || outy;
-      const I down = n + (I)ex(i) + (I)ey(i) * px;  // wraps only when unused
-      const I a = out ? (pl * (I)opp(i) + n) : (pl * (I)i + down);
-      S::st(elem(pop, a), f[i], P.scale[0]);
-      S::st(elem(pop, pl * (I)9 + a), p[i], P.scale[1]);
-      if (i == 0) {
-        S::st(elem(pop, pl * (I)18 + a), g[i], P.scale[2]);
-      } else if (!out) {
-        S::st(elem(pop, pl * (I)18 + a), g[i], P.scale[2]);
-        // the wall row takes the same value (copy of the adiabatic wall)
-        if ((ey(i) == 1 && yb) || (ey(i) == -1 && yt))
-          S::st(elem(pop, pl * (I)(18 + i) + n + (I)ex(i)), g[i], P.scale[2]);
-      } else if (!outy) {
-        // isothermal wall: anti-bounce-back into the own slot opp(i)
-        const float v = (ex(i) == -1 ? wgt(i) : -wgt(i)) - g[i];
-        S::st(elem(pop, pl * (I)18 + a), v, P.scale[2]);
-        // corner: the wall row next to this one copies it
-        if (ey(opp(i)) == 1 && y == 1)
-          S::st(elem(pop, pl * (I)18 + a - px), v, P.scale[2]);
-        if (ey(opp(i)) == -1 && y == ny - 2)
-          S::st(elem(pop, pl * (I)18 + a + px), v, P.scale[2]);
+    for (int i = 0; i < 9; ++i) {
+      if (!ODD) {
+        S::bst(R, vo, soff<T>(P, opp(i), 0, 0), f[i], P.scale[0]);
+        S::bst(R, vo, soff<T>(P, 9 + opp(i), 0, 0), p[i], P.scale[1]);
+        S::bst(R, vo, soff<T>(P, 18 + opp(i), 0, 0), g[i], P.scale[2]);
+      } else {
+        const bool outx = (ex(i) == 1 && xr) || (ex(i) == -1 && xl);
+        const bool outy = (ey(i) == 1 && yt) || (ey(i) == -1 && yb);
+        if (!(outx || outy)) {
+          // downstream node x + e_i, slot i
+          S::bst(R, vo, soff<T>(P, i, ex(i), ey(i)), f[i], P.scale[0]);
+          S::bst(R, vo, soff<T>(P, 9 + i, ex(i), ey(i)), p[i], P.scale[1]);
+          S::bst(R, vo, soff<T>(P, 18 + i, ex(i), ey(i)), g[i], P.scale[2]);
+          // the wall row takes the same value (copy of the adiabatic wall)
+          if ((ey(i) == 1 && yb) || (ey(i) == -1 && yt))
+            S::bst(R, vo, soff<T>(P, 18 + i, ex(i), 0), g[i], P.scale[2]);
+        } else {
+          // wall link: own slot opp(i)
+          S::bst(R, vo, soff<T>(P, opp(i), 0, 0), f[i], P.scale[0]);
+          S::bst(R, vo, soff<T>(P, 9 + opp(i), 0, 0), p[i], P.scale[1]);
+          if (!outy) {
+            // isothermal wall: anti-bounce-back into the own slot opp(i)
+            const float v = (ex(i) == -1 ? wgt(i) : -wgt(i)) - g[i];
+            S::bst(R, vo, soff<T>(P, 18 + opp(i), 0, 0), v, P.scale[2]);
+            // corner: the wall row next to this one copies it
+            if (ey(opp(i)) == 1 && y == 1)
+              S::bst(R, vo, soff<T>(P, 18 + opp(i), 0, -1), v, P.scale[2]);
+            if (ey(opp(i)) == -1 && y == ny - 2)
+              S::bst(R, vo, soff<T>(P, 18 + opp(i), 0, 1), v, P.scale[2]);
+          }
+          // out through an adiabatic wall: the value leaves the domain
+        }
       }
-      // out through an adiabatic wall: the value leaves the domain
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      if (!ODD) {
+        S::st(elem(pop, pl * (I)opp(i) + n), f[i], P.scale[0]);
+        S::st(elem(pop, pl * (I)(9 + opp(i)) + n), p[i], P.scale[1]);
+        S::st(elem(pop, pl * (I)(18 + opp(i)) + n), g[i], P.scale[2]);
+      } else {
+        const bool outx = (ex(i) == 1 && xr) || (ex(i) == -1 && xl);
+        const bool outy = (ey(i) == 1 && yt) || (ey(i) == -1 && yb);
+        const bool out = outx || outy;
+        const I down = n + (I)ex(i) + (I)ey(i) * px;  // wraps only when unused
+        const I a = out ? (pl * (I)opp(i) + n) : (pl * (I)i + down);
+        S::st(elem(pop, a), f[i], P.scale[0]);
+        S::st(elem(pop, pl * (I)9 + a), p[i], P.scale[1]);
+        if (i == 0) {
+          S::st(elem(pop, pl * (I)18 + a), g[i], P.scale[2]);
+        } else if (!out) {
+          S::st(elem(pop, pl * (I)18 + a), g[i], P.scale[2]);
+          if ((ey(i) == 1 && yb) || (ey(i) == -1 && yt))
+            S::st(elem(pop, pl * (I)(18 + i) + n + (I)ex(i)), g[i], P.scale[2]);
+        } else if (!outy) {
+          const float v = (ex(i) == -1 ? wgt(i) : -wgt(i)) - g[i];
+          S::st(elem(pop, pl * (I)18 + a), v, P.scale[2]);
+          if (ey(opp(i)) == 1 && y == 1) S::st(elem(pop, pl * (I)18 + a - px), v, P.scale[2]);
+          if (ey(opp(i)) == -1 && y == ny - 2) S::st(elem(pop, pl * (I)18 + a + px), v, P.scale[2]);
+        }
+      }
     }
   }
   if (!ODD) {

@@ -576,24 +576,33 @@ int launch_check(const char* what) {
   return MCLBM_OK;
 }
 
-// Kernel type selection: storage format S (temporal access), its streaming
-// variant SN used by the step kernel, and the index type I.
-template <class S_, class SN_, class I_>
+// Kernel type selection: storage format S (cached access, auxiliary
+// kernels), the access policies of the even (SE) and odd (SO) step kernels,
+// and the index type I.  Above the last-level cache the even step streams
+// loads and stores past the caches; the odd step streams its loads but
+// keeps its stores cached: they are shifted by one node, so the edge lines
+// of two neighbouring workgroups are each written half by either, and L2
+// merges the halves instead of sending two partial lines to HBM.
+template <class S_, class SE_, class SO_, class I_>
 struct KTypes {
   using S = S_;
-  using SN = SN_;
+  using SE = SE_;
+  using SO = SO_;
   using I = I_;
 };
 
 template <class Fn>
 int dispatch(const mclbm_cavity* c, Fn&& fn) {
   if (c->cfg.storage != MCLBM_FP32S) return fail(MCLBM_EUNSUPPORTED, "storage type not built");
+  using C = StorF32<false>;
+  using E = StorF32<true, true>;
+  using O = StorF32<true, false>;
   if (c->idx32) {
-    if (c->nt) return fn(KTypes<StorF32<false>, StorF32<true>, uint32_t>{});
-    return fn(KTypes<StorF32<false>, StorF32<false>, uint32_t>{});
+    if (c->nt) return fn(KTypes<C, E, O, uint32_t>{});
+    return fn(KTypes<C, C, C, uint32_t>{});
   }
-  if (c->nt) return fn(KTypes<StorF32<false>, StorF32<true>, uint64_t>{});
-  return fn(KTypes<StorF32<false>, StorF32<false>, uint64_t>{});
+  if (c->nt) return fn(KTypes<C, E, O, uint64_t>{});
+  return fn(KTypes<C, C, C, uint64_t>{});
 }
 
 // Grid over all nodes for the auxiliary kernels.
@@ -658,13 +667,15 @@ int setup_cavity(mclbm_cavity* c) {
 
 template <class K>
 int launch_step(mclbm_cavity* c) {
-  using SN = typename K::SN;
   using I = typename K::I;
-  auto* pop = reinterpret_cast<typename SN::T*>(c->pop());
+  using T = typename K::S::T;
+  auto* pop = reinterpret_cast<T*>(c->pop());
   if ((c->t & 1) == 0)
-    k_step<false, SN, I><<<c->nblocks, c->block, 0, c->stream>>>(c->P, pop, c->d2(1), c->d2(0), c->d5(), c->tiles_x);
+    k_step<false, typename K::SE, I><<<c->nblocks, c->block, 0, c->stream>>>(c->P, pop, c->d2(1), c->d2(0),
+                                                                           c->d5(), c->tiles_x);
   else
-    k_step<true, SN, I><<<c->nblocks, c->block, 0, c->stream>>>(c->P, pop, c->d2(0), c->d2(1), c->d5(), c->tiles_x);
+    k_step<true, typename K::SO, I><<<c->nblocks, c->block, 0, c->stream>>>(c->P, pop, c->d2(0), c->d2(1),
+                                                                          c->d5(), c->tiles_x);
   return launch_check("k_step");
 }
 
