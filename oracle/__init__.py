@@ -164,8 +164,11 @@ class Oracle:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            lib().mclbm_oracle_destroy(h)
+        if h is not None and h.value and _lib is not None:
+            try:
+                _lib.mclbm_oracle_destroy(h)
+            except Exception:
+                pass
             self._h = None
 
     @property

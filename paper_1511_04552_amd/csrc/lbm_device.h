@@ -104,28 +104,58 @@ struct StorF32 {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)voff, (int)soff, kStPol);
   }
 };
-// 16-bit deviations scaled by a power of two per lattice (scale[l] on store,
-// 1/scale[l] on load) so that typical deviations sit in the normal range.
-template <bool NT>
-struct StorF16 {
-  using T = __half;
-  static __device__ __forceinline__ float ld(const T* p, float inv) {
-    return __half2float(*p) * inv;
+// 16-bit deviations, FP16 scaled by a power of two per lattice (scale[l] on
+// store, 1/scale[l] on load) so that typical deviations sit in the normal
+// range, or BF16 (FP32's exponent range, scale 1).  Rounding to nearest even.
+template <class H>
+struct Half16;
+template <>
+struct Half16<__half> {
+  static __device__ __forceinline__ float to_f(unsigned short b) {
+    return __half2float(__ushort_as_half(b));
   }
-  static __device__ __forceinline__ void st(T* p, float v, float sc) {
-    *p = __float2half_rn(v * sc);
-  }
-};
-template <bool NT>
-struct StorBF16 {
-  using T = __hip_bfloat16;
-  static __device__ __forceinline__ float ld(const T* p, float inv) {
-    return __bfloat162float(*p) * inv;
-  }
-  static __device__ __forceinline__ void st(T* p, float v, float sc) {
-    *p = __float2bfloat16(v * sc);
+  static __device__ __forceinline__ unsigned short from_f(float v) {
+    return __half_as_ushort(__float2half_rn(v));
   }
 };
+template <>
+struct Half16<__hip_bfloat16> {
+  static __device__ __forceinline__ float to_f(unsigned short b) {
+    return __uint_as_float((unsigned)b << 16);
+  }
+  static __device__ __forceinline__ unsigned short from_f(float v) {
+    return __bfloat16_as_ushort(__float2bfloat16(v));
+  }
+};
+
+template <class H, bool NTL, bool NTS = NTL>
+struct Stor16 {
+  using T = H;
+  static constexpr int kLdPol = NTL ? 2 : 0, kStPol = NTS ? 2 : 0;
+  static __device__ __forceinline__ float ld(const T* p, float inv) {
+    unsigned short b;
+    if constexpr (NTL) b = __builtin_nontemporal_load(reinterpret_cast<const unsigned short*>(p));
+    else b = *reinterpret_cast<const unsigned short*>(p);
+    return Half16<H>::to_f(b) * inv;
+  }
+  static __device__ __forceinline__ void st(T* p, float v, float sc) {
+    const unsigned short b = Half16<H>::from_f(v * sc);
+    if constexpr (NTS) __builtin_nontemporal_store(b, reinterpret_cast<unsigned short*>(p));
+    else *reinterpret_cast<unsigned short*>(p) = b;
+  }
+  static __device__ __forceinline__ float bld(__amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                              uint32_t soff, float inv) {
+    return Half16<H>::to_f(__builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, kLdPol)) * inv;
+  }
+  static __device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff,
+                                             float v, float sc) {
+    __builtin_amdgcn_raw_buffer_store_b16(Half16<H>::from_f(v * sc), r, (int)voff, (int)soff, kStPol);
+  }
+};
+template <bool NTL, bool NTS = NTL>
+using StorF16 = Stor16<__half, NTL, NTS>;
+template <bool NTL, bool NTS = NTL>
+using StorBF16 = Stor16<__hip_bfloat16, NTL, NTS>;
 
 // Reciprocal: hardware estimate refined by one Newton step (~0.5 ulp),
 // instead of the long IEEE division sequence.

@@ -411,8 +411,6 @@ int validate(const mclbm_config* c) {
     return fail(MCLBM_EINVAL, "phi_perturb_amp must be >= 0");
   if (c->storage != MCLBM_FP32S && c->storage != MCLBM_FP16S && c->storage != MCLBM_BF16S)
     return fail(MCLBM_EINVAL, "unknown storage type");
-  if (c->storage != MCLBM_FP32S)
-    return fail(MCLBM_EUNSUPPORTED, "16-bit population storage is not available in this build");
   const int bx = c->block_x == 0 ? 64 : c->block_x;
   const int by = c->block_y == 0 ? 1 : c->block_y;
   if (!(bx == 32 || bx == 64 || bx == 128 || bx == 256) || by < 1 ||
@@ -476,9 +474,15 @@ StepParams make_params(const mclbm_config& c, const Derived& D, const Layout& L)
   P.ny = c.ny;
   P.px = L.px;
   P.plane = L.plane;
+  // FP16 stores the deviations scaled by a power of two per lattice:
+  // fluid and particle deviations (~1e-7 .. 2e-2) by 2^16, temperature
+  // populations (|g| <= 0.25) by 2^12, keeping both ends inside the normal
+  // range (6.1e-5 .. 65504).  FP32 and BF16 are unscaled.
   for (int l = 0; l < 3; ++l) {
-    P.scale[l] = 1.0f;
-    P.inv_scale[l] = 1.0f;
+    float sc = 1.0f;
+    if (c.storage == MCLBM_FP16S) sc = l < 2 ? 65536.0f : 4096.0f;
+    P.scale[l] = sc;
+    P.inv_scale[l] = 1.0f / sc;
   }
   const double R = v[MCLBM_D_R], dx = v[MCLBM_D_DX], dt = v[MCLBM_D_DT], H = v[MCLBM_D_H];
   const double tau_f = v[MCLBM_D_TAU_F];
@@ -591,18 +595,34 @@ struct KTypes {
   using I = I_;
 };
 
-template <class Fn>
-int dispatch(const mclbm_cavity* c, Fn&& fn) {
-  if (c->cfg.storage != MCLBM_FP32S) return fail(MCLBM_EUNSUPPORTED, "storage type not built");
-  using C = StorF32<false>;
-  using E = StorF32<true, true>;
-  using O = StorF32<true, false>;
+template <template <bool, bool> class St, class Fn>
+int dispatch_storage(const mclbm_cavity* c, Fn&& fn) {
+  using C = St<false, false>;
+  using E = St<true, true>;
+  using O = St<true, false>;
   if (c->idx32) {
     if (c->nt) return fn(KTypes<C, E, O, uint32_t>{});
     return fn(KTypes<C, C, C, uint32_t>{});
   }
   if (c->nt) return fn(KTypes<C, E, O, uint64_t>{});
   return fn(KTypes<C, C, C, uint64_t>{});
+}
+
+template <bool L, bool S>
+using F32 = StorF32<L, S>;
+template <bool L, bool S>
+using F16 = StorF16<L, S>;
+template <bool L, bool S>
+using BF16 = StorBF16<L, S>;
+
+template <class Fn>
+int dispatch(const mclbm_cavity* c, Fn&& fn) {
+  switch (c->cfg.storage) {
+    case MCLBM_FP32S: return dispatch_storage<F32>(c, fn);
+    case MCLBM_FP16S: return dispatch_storage<F16>(c, fn);
+    case MCLBM_BF16S: return dispatch_storage<BF16>(c, fn);
+    default: return fail(MCLBM_EUNSUPPORTED, "unknown storage type");
+  }
 }
 
 // Grid over all nodes for the auxiliary kernels.
