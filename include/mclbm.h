@@ -198,6 +198,71 @@ int mclbm_destroy(mclbm_cavity* c);
 /* Thread-local message describing the last failure ("" if none). */
 const char* mclbm_last_error(void);
 
+/* ---- Batched parameter sweeps ------------------------------------------
+ * A batch holds n independent cavities of uneven sizes and parameters (the
+ * sweeps over Ra, phi and d_p of Section 3) in one device buffer.  One
+ * persistent kernel launch per time step updates every active cavity; the
+ * step loop is replayed from a captured HIP graph.  Every cavity gives
+ * bitwise the same result as the same cavity created alone.  All cavities of
+ * a batch share the storage type; each keeps its own workgroup shape. */
+typedef struct mclbm_batch mclbm_batch;
+
+/* Bytes of device memory for a batch of n cavities; 0 if any configuration
+ * is invalid or the storage types differ. */
+size_t mclbm_batch_device_bytes(const mclbm_config* cfgs, int32_t n);
+
+/* Create a batch on dev_buf (>= mclbm_batch_device_bytes, 256-byte aligned)
+ * and enqueue every cavity's initial state on `stream`.  xis: NULL, or n
+ * pointers each NULL or to nx*ny host doubles (as for mclbm_create).  Sync. */
+int mclbm_batch_create(const mclbm_config* cfgs, int32_t n, const double* const* xis,
+                       void* dev_buf, size_t bytes, void* stream, mclbm_batch** out);
+
+/* Advance every active cavity by nsteps >= 0 steps.  Async. */
+int mclbm_batch_step(mclbm_batch* b, int64_t nsteps);
+
+/* Steps replayed per graph launch (an even number >= 2), or 0 to launch
+ * every step directly.  Default 32. */
+int mclbm_batch_set_graph_steps(mclbm_batch* b, int32_t steps);
+
+/* Mark cavities active (1) or dropped (0); dropped cavities stop stepping
+ * and keep their state.  A dropped cavity may only rejoin when its step
+ * count has the parity of the active ones.  Sync. */
+int mclbm_batch_set_active(mclbm_batch* b, const int32_t* active);
+
+/* Residual (as mclbm_residual) of every active cavity: out[2k], out[2k+1];
+ * status[k] = 0 still running, 1 converged (both below tol; dropped),
+ * 2 diverged (non-finite; dropped), 3 inactive.  tol <= 0 only reports.
+ * Sync. */
+int mclbm_batch_residual(mclbm_batch* b, double tol, double* out, int32_t* status);
+
+/* Nusselt numbers (as mclbm_nusselt) of every cavity: out[3k .. 3k+2].
+ * Non-finite values are reported as such.  Sync. */
+int mclbm_batch_nusselt(mclbm_batch* b, double* out);
+
+/* Project-written autotuner: for every size class of the batch time
+ * `steps` steps with each candidate workgroup shape (256x1, 128x2, 64x4,
+ * 32x8), keep the fastest per class, then restart every cavity from its
+ * initial state.  The shapes do not change any result.  Sync. */
+int mclbm_batch_autotune(mclbm_batch* b, int32_t steps);
+
+/* Workgroup shape chosen for cavity idx. */
+int mclbm_batch_tile_shape(const mclbm_batch* b, int32_t idx, int32_t* bx, int32_t* by);
+
+/* Restart every cavity from its initial state and reactivate it.  Sync. */
+int mclbm_batch_reset(mclbm_batch* b);
+
+/* Number of cavities; steps taken by cavity idx (-1 on bad arguments). */
+int32_t mclbm_batch_size(const mclbm_batch* b);
+int64_t mclbm_batch_time(const mclbm_batch* b, int32_t idx);
+
+/* The cavity idx of the batch as a cavity handle owned by the batch (valid
+ * until mclbm_batch_destroy): moments, populations, Nusselt, residual and
+ * derived constants of that cavity.  Do not step, reset or destroy it. */
+mclbm_cavity* mclbm_batch_cavity(mclbm_batch* b, int32_t idx);
+
+/* Release the batch (waits for its stream).  Does not free dev_buf. */
+int mclbm_batch_destroy(mclbm_batch* b);
+
 /* Measurement helper: copy `bytes` (multiple of 16) from src to dst, both
  * device buffers, with a plain streaming kernel on `stream`.  Async.
  * Used to calibrate the achievable HBM bandwidth and the byte counters. */

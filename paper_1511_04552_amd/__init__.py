@@ -33,7 +33,12 @@ EXPORTED = ("mclbm_config_defaults", "mclbm_device_bytes", "mclbm_derive_constan
             "mclbm_export_moments", "mclbm_read_moments", "mclbm_read_populations",
             "mclbm_export_populations", "mclbm_nusselt", "mclbm_residual",
             "mclbm_derived", "mclbm_destroy", "mclbm_last_error", "mclbm_copy_kernel",
-            "mclbm_version", "mclbm_abi_version")
+            "mclbm_version", "mclbm_abi_version",
+            "mclbm_batch_device_bytes", "mclbm_batch_create", "mclbm_batch_step",
+            "mclbm_batch_set_graph_steps", "mclbm_batch_set_active", "mclbm_batch_residual",
+            "mclbm_batch_nusselt", "mclbm_batch_autotune", "mclbm_batch_tile_shape",
+            "mclbm_batch_reset", "mclbm_batch_size", "mclbm_batch_time", "mclbm_batch_cavity",
+            "mclbm_batch_destroy")
 
 
 class MclbmError(RuntimeError):
@@ -100,6 +105,26 @@ def lib(load_torch: bool = True):
     L.mclbm_copy_kernel.argtypes = [P, P, ctypes.c_size_t, P]
     L.mclbm_version.restype = ctypes.c_char_p
     L.mclbm_abi_version.restype = I
+    I32P = ctypes.POINTER(ctypes.c_int32)
+    L.mclbm_batch_device_bytes.argtypes = [CP, ctypes.c_int32]
+    L.mclbm_batch_device_bytes.restype = ctypes.c_size_t
+    L.mclbm_batch_create.argtypes = [CP, ctypes.c_int32, ctypes.POINTER(D), P, ctypes.c_size_t, P,
+                                     ctypes.POINTER(P)]
+    L.mclbm_batch_step.argtypes = [P, ctypes.c_int64]
+    L.mclbm_batch_set_graph_steps.argtypes = [P, ctypes.c_int32]
+    L.mclbm_batch_set_active.argtypes = [P, I32P]
+    L.mclbm_batch_residual.argtypes = [P, ctypes.c_double, D, I32P]
+    L.mclbm_batch_nusselt.argtypes = [P, D]
+    L.mclbm_batch_autotune.argtypes = [P, ctypes.c_int32]
+    L.mclbm_batch_tile_shape.argtypes = [P, ctypes.c_int32, I32P, I32P]
+    L.mclbm_batch_reset.argtypes = [P]
+    L.mclbm_batch_size.argtypes = [P]
+    L.mclbm_batch_size.restype = ctypes.c_int32
+    L.mclbm_batch_time.argtypes = [P, ctypes.c_int32]
+    L.mclbm_batch_time.restype = ctypes.c_int64
+    L.mclbm_batch_cavity.argtypes = [P, ctypes.c_int32]
+    L.mclbm_batch_cavity.restype = P
+    L.mclbm_batch_destroy.argtypes = [P]
     _lib = L
     return L
 
@@ -259,6 +284,107 @@ class Cavity:
         out = np.zeros(len(DERIVED))
         _check(lib().mclbm_derived(self._h, _dptr(out), out.size))
         return dict(zip(DERIVED, out.tolist()))
+
+
+class _BatchMember(Cavity):
+    """A cavity owned by a batch (outputs only; stepping goes through the batch)."""
+
+    def __init__(self, batch, idx, handle, cfg):
+        self._batch, self._idx = batch, idx
+        self._h = ctypes.c_void_p(handle)
+        self.cfg = cfg
+        self.nx, self.ny = int(cfg.nx), int(cfg.ny)
+        self.stream = batch.stream
+        self._buf = batch._buf
+
+    def close(self):
+        self._h = None
+
+    def step(self, n):
+        raise MclbmError(ESTATE, "step the batch, not its members")
+
+
+class Batch:
+    """Uneven cavities stepped together by one persistent launch per step
+    (graph-replayed).  ``cfgs``: list of keyword dicts as for ``Cavity``;
+    ``xis``: optional list of perturbation fields (or None entries)."""
+
+    def __init__(self, cfgs, xis=None, stream=None, device=None, graph_steps=None):
+        import torch
+        L = lib()
+        n = len(cfgs)
+        self._cfgs = (Config * n)(*[make_config(**c) for c in cfgs])
+        nbytes = L.mclbm_batch_device_bytes(self._cfgs, n)
+        if nbytes == 0:
+            raise MclbmError(EINVAL, L.mclbm_last_error().decode())
+        dev = torch.device("cuda" if device is None else device)
+        self._buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        base = (self._buf.data_ptr() + 255) // 256 * 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        self.n = n
+        xp = None
+        if xis is not None:
+            self._xis = [None if x is None else np.ascontiguousarray(x, dtype=np.float64).reshape(-1) for x in xis]
+            arr = (ctypes.POINTER(ctypes.c_double) * n)()
+            for k, x in enumerate(self._xis):
+                if x is not None:
+                    if x.size != self._cfgs[k].nx * self._cfgs[k].ny:
+                        raise ValueError(f"xi {k} must hold nx*ny values")
+                    arr[k] = _dptr(x)
+            xp = arr
+        self._h = ctypes.c_void_p()
+        _check(L.mclbm_batch_create(self._cfgs, n, xp, ctypes.c_void_p(base), ctypes.c_size_t(nbytes),
+                                    ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(self._h)))
+        if graph_steps is not None:
+            self.set_graph_steps(graph_steps)
+        self.members = [_BatchMember(self, k, L.mclbm_batch_cavity(self._h, k), self._cfgs[k]) for k in range(n)]
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().mclbm_batch_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n: int) -> None:
+        _check(lib().mclbm_batch_step(self._h, int(n)))
+
+    def set_graph_steps(self, steps: int) -> None:
+        _check(lib().mclbm_batch_set_graph_steps(self._h, int(steps)))
+
+    def set_active(self, active) -> None:
+        a = (ctypes.c_int32 * self.n)(*[1 if v else 0 for v in active])
+        _check(lib().mclbm_batch_set_active(self._h, a))
+
+    def residual(self, tol: float = 0.0):
+        out = np.zeros(2 * self.n)
+        st = (ctypes.c_int32 * self.n)()
+        _check(lib().mclbm_batch_residual(self._h, float(tol), _dptr(out), st))
+        return out.reshape(self.n, 2), np.array(st[:], dtype=np.int32)
+
+    def nusselt(self) -> np.ndarray:
+        out = np.zeros(3 * self.n)
+        _check(lib().mclbm_batch_nusselt(self._h, _dptr(out)))
+        return out.reshape(self.n, 3)
+
+    def autotune(self, steps: int = 20) -> list:
+        _check(lib().mclbm_batch_autotune(self._h, int(steps)))
+        return [self.tile_shape(k) for k in range(self.n)]
+
+    def tile_shape(self, idx: int) -> tuple:
+        bx, by = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().mclbm_batch_tile_shape(self._h, int(idx), ctypes.byref(bx), ctypes.byref(by)))
+        return bx.value, by.value
+
+    def reset(self) -> None:
+        _check(lib().mclbm_batch_reset(self._h))
+
+    def time(self, idx: int) -> int:
+        return int(lib().mclbm_batch_time(self._h, int(idx)))
 
 
 def copy_kernel(dst, src, stream=None) -> None:

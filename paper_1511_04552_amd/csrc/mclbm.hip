@@ -75,17 +75,11 @@ __device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned nb) {
   return k * q + (k < r ? k : r) + (b >> 3);
 }
 
+// One node of one time step (the whole hot path for that node).
 template <bool ODD, class S, class I>
-__global__ __launch_bounds__(256) void k_step(StepParams P,
-                                              typename S::T* __restrict__ pop,
-                                              const float2* __restrict__ d2p,
-                                              float2* __restrict__ d2c,
-                                              float* __restrict__ d5,
-                                              int tiles_x) {
-  const unsigned t = xcd_tile(blockIdx.x, gridDim.x);
-  const int x = (int)(t % (unsigned)tiles_x) * blockDim.x + threadIdx.x;
-  const int y = (int)(t / (unsigned)tiles_x) * blockDim.y + threadIdx.y;
-  if (x >= P.nx || y >= P.ny) return;
+__device__ __forceinline__ void step_node(const StepParams& P, typename S::T* __restrict__ pop,
+                                          const float2* __restrict__ d2p, float2* __restrict__ d2c,
+                                          float* __restrict__ d5, int x, int y) {
   float f[9], p[9], g[9];
   load_node<ODD, S, I>(P, pop, d5, x, y, f, p, g);
 
@@ -108,6 +102,53 @@ __global__ __launch_bounds__(256) void k_step(StepParams P,
   const float2 keep = node_update(P, f, p, g, gphix, gphiy, gthx, gthy);
   store_node<ODD, S, I>(P, pop, d5, x, y, f, p, g);
   d2c[n] = keep;
+}
+
+template <bool ODD, class S, class I>
+__global__ __launch_bounds__(256) void k_step(StepParams P,
+                                              typename S::T* __restrict__ pop,
+                                              const float2* __restrict__ d2p,
+                                              float2* __restrict__ d2c,
+                                              float* __restrict__ d5,
+                                              int tiles_x) {
+  const unsigned t = xcd_tile(blockIdx.x, gridDim.x);
+  const int x = (int)(t % (unsigned)tiles_x) * blockDim.x + threadIdx.x;
+  const int y = (int)(t / (unsigned)tiles_x) * blockDim.y + threadIdx.y;
+  if (x >= P.nx || y >= P.ny) return;
+  step_node<ODD, S, I>(P, pop, d2p, d2c, d5, x, y);
+}
+
+// Batched sweep: one persistent launch per time step updates every active
+// cavity of a batch of uneven cavities.  Each entry of the tile table names
+// a cavity and one 256-node tile of it (shape bx x by chosen per cavity);
+// workgroup b takes entries b, b + G, b + 2G, ...  The table is laid out so
+// that the entries a workgroup takes, and those of its XCD, are neighbours
+// in space.  The entry count is read from device memory, so a captured
+// graph of this launch stays valid when cavities drop out of the table.
+struct CavDesc {
+  StepParams P;
+  void* pop;
+  float2* d2[2];
+  float* d5;
+  int tiles_x, bx, by, pad;
+};
+
+template <bool ODD, class S, class I>
+__global__ __launch_bounds__(256) void k_step_batch(const CavDesc* __restrict__ cavs,
+                                                    const int2* __restrict__ tiles,
+                                                    const int* __restrict__ ntiles_p) {
+  const int ntiles = *ntiles_p;
+  for (int k = blockIdx.x; k < ntiles; k += gridDim.x) {
+    const int2 tr = tiles[k];
+    if (tr.x < 0) continue;  // padding entry
+    const CavDesc& C = cavs[tr.x];
+    const int bx = C.bx;
+    const int x = (tr.y % C.tiles_x) * bx + (int)threadIdx.x % bx;
+    const int y = (tr.y / C.tiles_x) * C.by + (int)threadIdx.x / bx;
+    if (x < C.P.nx && y < C.P.ny)
+      step_node<ODD, S, I>(C.P, reinterpret_cast<typename S::T*>(C.pop), C.d2[ODD ? 0 : 1],
+                           C.d2[ODD ? 1 : 0], C.d5, x, y);
+  }
 }
 
 // Block-wide FP64 sum; wave64 shuffles then one LDS slot per wave.
@@ -561,6 +602,7 @@ struct mclbm_cavity {
   int tiles_x;
   bool nt;             // non-temporal population traffic
   bool idx32;          // 32-bit element offsets
+  bool in_batch;       // owned by a batch: stepped only through it
   std::vector<double> host_dev_p;  // initial phi deviations (source of an async copy)
 
   void* pop() { return base + L.off_pop; }
@@ -596,15 +638,15 @@ struct KTypes {
 };
 
 template <template <bool, bool> class St, class Fn>
-int dispatch_storage(const mclbm_cavity* c, Fn&& fn) {
+int dispatch_storage(bool idx32, bool nt, Fn&& fn) {
   using C = St<false, false>;
   using E = St<true, true>;
   using O = St<true, false>;
-  if (c->idx32) {
-    if (c->nt) return fn(KTypes<C, E, O, uint32_t>{});
+  if (idx32) {
+    if (nt) return fn(KTypes<C, E, O, uint32_t>{});
     return fn(KTypes<C, C, C, uint32_t>{});
   }
-  if (c->nt) return fn(KTypes<C, E, O, uint64_t>{});
+  if (nt) return fn(KTypes<C, E, O, uint64_t>{});
   return fn(KTypes<C, C, C, uint64_t>{});
 }
 
@@ -616,13 +658,18 @@ template <bool L, bool S>
 using BF16 = StorBF16<L, S>;
 
 template <class Fn>
-int dispatch(const mclbm_cavity* c, Fn&& fn) {
-  switch (c->cfg.storage) {
-    case MCLBM_FP32S: return dispatch_storage<F32>(c, fn);
-    case MCLBM_FP16S: return dispatch_storage<F16>(c, fn);
-    case MCLBM_BF16S: return dispatch_storage<BF16>(c, fn);
+int dispatch_kinds(int storage, bool idx32, bool nt, Fn&& fn) {
+  switch (storage) {
+    case MCLBM_FP32S: return dispatch_storage<F32>(idx32, nt, fn);
+    case MCLBM_FP16S: return dispatch_storage<F16>(idx32, nt, fn);
+    case MCLBM_BF16S: return dispatch_storage<BF16>(idx32, nt, fn);
     default: return fail(MCLBM_EUNSUPPORTED, "unknown storage type");
   }
+}
+
+template <class Fn>
+int dispatch(const mclbm_cavity* c, Fn&& fn) {
+  return dispatch_kinds(c->cfg.storage, c->idx32, c->nt, fn);
 }
 
 // Grid over all nodes for the auxiliary kernels.
@@ -789,6 +836,7 @@ int mclbm_create(const mclbm_config* cfg, const double* xi_host, void* dev_buf, 
 
 int mclbm_set_properties(mclbm_cavity* c, double Ra, double phi0, double dp_m) {
   if (!c) return fail(MCLBM_EINVAL, "cavity is NULL");
+  if (c->in_batch) return fail(MCLBM_ESTATE, "cavity belongs to a batch: use the batch calls");
   mclbm_config nc = c->cfg;
   nc.Ra = Ra;
   nc.phi0 = phi0;
@@ -802,11 +850,13 @@ int mclbm_set_properties(mclbm_cavity* c, double Ra, double phi0, double dp_m) {
 
 int mclbm_reset(mclbm_cavity* c) {
   if (!c) return fail(MCLBM_EINVAL, "cavity is NULL");
+  if (c->in_batch) return fail(MCLBM_ESTATE, "cavity belongs to a batch: use the batch calls");
   return enqueue_init(c);
 }
 
 int mclbm_step(mclbm_cavity* c, int64_t nsteps) {
   if (!c) return fail(MCLBM_EINVAL, "cavity is NULL");
+  if (c->in_batch) return fail(MCLBM_ESTATE, "cavity belongs to a batch: use the batch calls");
   if (nsteps < 0) return fail(MCLBM_EINVAL, "nsteps must be >= 0");
   return dispatch(c, [&](auto k) {
     for (int64_t s = 0; s < nsteps; ++s) {
@@ -941,6 +991,7 @@ int mclbm_derived(const mclbm_cavity* c, double* out, int n) {
 
 int mclbm_destroy(mclbm_cavity* c) {
   if (!c) return MCLBM_OK;
+  if (c->in_batch) return fail(MCLBM_ESTATE, "cavity belongs to a batch: destroy the batch");
   hipError_t e = hipStreamSynchronize(c->stream);
   delete c;
   if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
@@ -966,5 +1017,464 @@ int mclbm_copy_kernel(void* dst, const void* src, size_t bytes, void* stream) {
 
 const char* mclbm_version(void) { return "mclbm 0.1.0 (gfx950)"; }
 int mclbm_abi_version(void) { return MCLBM_ABI_VERSION; }
+
+}  // extern "C"
+
+// ===========================================================================
+// Batched sweeps (host side)
+// ===========================================================================
+
+struct mclbm_batch {
+  int n = 0;
+  std::vector<mclbm_cavity> cav;
+  hipStream_t stream = nullptr;
+  hipStream_t cap_stream = nullptr;  // private stream the step graph is captured on
+  char* base = nullptr;
+  size_t bytes = 0;
+  size_t off_desc = 0, off_ntiles = 0, off_tiles = 0;
+  int tile_cap = 0;
+  std::vector<char> active;
+  std::vector<CavDesc> host_desc;
+  std::vector<int2> host_tiles;
+  int ntiles = 0;
+  int64_t t = 0;  // steps of the active cavities
+  int storage = MCLBM_FP32S;
+  bool nt = false, idx32 = true;
+  unsigned grid = 0;
+  int graph_steps = 32;
+  hipGraphExec_t gexec = nullptr;
+  int gexec_steps = 0;
+
+  CavDesc* d_desc() { return reinterpret_cast<CavDesc*>(base + off_desc); }
+  int* d_ntiles() { return reinterpret_cast<int*>(base + off_ntiles); }
+  int2* d_tiles() { return reinterpret_cast<int2*>(base + off_tiles); }
+};
+
+namespace {
+
+constexpr int kShapes[4][2] = {{256, 1}, {128, 2}, {64, 4}, {32, 8}};
+
+int tiles_of(int nx, int ny, int bx, int by) { return ((nx + bx - 1) / bx) * ((ny + by - 1) / by); }
+
+struct BatchLayout {
+  size_t off_desc, off_ntiles, off_tiles, total;
+  int tile_cap;
+  std::vector<size_t> off_cav;
+};
+
+int batch_layout(const mclbm_config* cfgs, int n, BatchLayout& B) {
+  if (!cfgs || n < 1) return fail(MCLBM_EINVAL, "batch needs n >= 1 configurations");
+  long long cap = 0;
+  for (int k = 0; k < n; ++k) {
+    int rc = validate(&cfgs[k]);
+    if (rc) return fail(rc, "cavity " + std::to_string(k) + ": " + g_err);
+    if (cfgs[k].storage != cfgs[0].storage) return fail(MCLBM_EINVAL, "all cavities of a batch share the storage type");
+    int m = 0;
+    for (const auto& sh : kShapes) m = std::max(m, tiles_of(cfgs[k].nx, cfgs[k].ny, sh[0], sh[1]));
+    cap += m;
+  }
+  if (cap > (1LL << 30)) return fail(MCLBM_EINVAL, "batch too large");
+  B.tile_cap = (int)(8 * ((cap + 7) / 8) + 8);
+  size_t off = 0;
+  B.off_desc = off;
+  off = align_up(off + (size_t)n * sizeof(CavDesc));
+  B.off_ntiles = off;
+  off = align_up(off + sizeof(int));
+  B.off_tiles = off;
+  off = align_up(off + (size_t)B.tile_cap * sizeof(int2));
+  B.off_cav.resize(n);
+  for (int k = 0; k < n; ++k) {
+    B.off_cav[k] = off;
+    off = align_up(off + make_layout(cfgs[k]).total);
+  }
+  B.total = off;
+  return MCLBM_OK;
+}
+
+CavDesc make_desc(mclbm_cavity* c) {
+  CavDesc d{};
+  d.P = c->P;
+  d.pop = c->pop();
+  d.d2[0] = c->d2(0);
+  d.d2[1] = c->d2(1);
+  d.d5 = c->d5();
+  d.bx = (int)c->block.x;
+  d.by = (int)c->block.y;
+  d.tiles_x = c->tiles_x;
+  return d;
+}
+
+// Tile table: the tiles of the active cavities (cavity-major, row-major
+// within a cavity) cut into 8 contiguous chunks; chunk j takes entries
+// j, j + 8, j + 16, ... so that the workgroups one XCD receives (b = j mod 8
+// under round-robin dealing) sweep one contiguous band.  Then uploaded with
+// the descriptors.  Sync.
+int upload_tables(mclbm_batch* b) {
+  std::vector<int2> list;
+  for (int k = 0; k < b->n; ++k) {
+    if (b->cav[k].block.x * b->cav[k].block.y != 256)
+      return fail(MCLBM_EINVAL, "batched tiles must cover 256 nodes");
+    if (!b->active[k]) continue;
+    const int nt = tiles_of(b->cav[k].cfg.nx, b->cav[k].cfg.ny, b->cav[k].block.x, b->cav[k].block.y);
+    for (int t = 0; t < nt; ++t) list.push_back(make_int2(k, t));
+  }
+  const int L = (int)list.size();
+  const int m = (L + 7) / 8;
+  b->host_tiles.assign((size_t)8 * m, make_int2(-1, 0));
+  for (int j = 0; j < 8; ++j)
+    for (int q = 0; q < m; ++q) {
+      const int src = j * m + q;
+      if (src < L) b->host_tiles[(size_t)8 * q + j] = list[src];
+    }
+  b->ntiles = 8 * m;
+  if (b->ntiles > b->tile_cap) return fail(MCLBM_EINVAL, "tile table overflow");
+  b->host_desc.resize(b->n);
+  for (int k = 0; k < b->n; ++k) b->host_desc[k] = make_desc(&b->cav[k]);
+  HIP_TRY(hipMemcpyAsync(b->d_desc(), b->host_desc.data(), b->host_desc.size() * sizeof(CavDesc),
+                         hipMemcpyHostToDevice, b->stream));
+  if (b->ntiles > 0)
+    HIP_TRY(hipMemcpyAsync(b->d_tiles(), b->host_tiles.data(), (size_t)b->ntiles * sizeof(int2),
+                           hipMemcpyHostToDevice, b->stream));
+  HIP_TRY(hipMemcpyAsync(b->d_ntiles(), &b->ntiles, sizeof(int), hipMemcpyHostToDevice, b->stream));
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  return MCLBM_OK;
+}
+
+template <class K>
+void batch_launch(mclbm_batch* b, hipStream_t s, bool odd) {
+  using I = typename K::I;
+  if (!odd)
+    k_step_batch<false, typename K::SE, I><<<b->grid, 256, 0, s>>>(b->d_desc(), b->d_tiles(), b->d_ntiles());
+  else
+    k_step_batch<true, typename K::SO, I><<<b->grid, 256, 0, s>>>(b->d_desc(), b->d_tiles(), b->d_ntiles());
+}
+
+void batch_advance(mclbm_batch* b, int64_t k) {
+  b->t += k;
+  for (int c = 0; c < b->n; ++c)
+    if (b->active[c]) b->cav[c].t += k;
+}
+
+int batch_direct_step(mclbm_batch* b) {
+  int rc = dispatch_kinds(b->storage, b->idx32, b->nt, [&](auto k) {
+    batch_launch<decltype(k)>(b, b->stream, (b->t & 1) != 0);
+    return launch_check("k_step_batch");
+  });
+  if (rc) return rc;
+  batch_advance(b, 1);
+  return MCLBM_OK;
+}
+
+void drop_graph(mclbm_batch* b) {
+  if (b->gexec) hipGraphExecDestroy(b->gexec);
+  b->gexec = nullptr;
+  b->gexec_steps = 0;
+}
+
+// Capture graph_steps launches (even, odd, even, ...) on the private
+// stream; the graph is replayed on the batch's stream.
+int capture_graph(mclbm_batch* b) {
+  drop_graph(b);
+  HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+  int rc = dispatch_kinds(b->storage, b->idx32, b->nt, [&](auto k) {
+    for (int q = 0; q < b->graph_steps; ++q) batch_launch<decltype(k)>(b, b->cap_stream, (q & 1) != 0);
+    return (int)MCLBM_OK;
+  });
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
+  if (rc) {
+    if (g) hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+  e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    b->gexec = nullptr;
+    return hip_fail(e, "hipGraphInstantiate");
+  }
+  b->gexec_steps = b->graph_steps;
+  return MCLBM_OK;
+}
+
+int batch_reset_all(mclbm_batch* b) {
+  for (int k = 0; k < b->n; ++k) {
+    int rc = enqueue_init(&b->cav[k]);
+    if (rc) return rc;
+    b->active[k] = 1;
+  }
+  b->t = 0;
+  return upload_tables(b);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t mclbm_batch_device_bytes(const mclbm_config* cfgs, int32_t n) {
+  BatchLayout B;
+  if (batch_layout(cfgs, n, B)) return 0;
+  return B.total;
+}
+
+int mclbm_batch_create(const mclbm_config* cfgs, int32_t n, const double* const* xis, void* dev_buf,
+                       size_t bytes, void* stream, mclbm_batch** out) {
+  if (!out) return fail(MCLBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  BatchLayout B;
+  int rc = batch_layout(cfgs, n, B);
+  if (rc) return rc;
+  if (!dev_buf) return fail(MCLBM_EINVAL, "dev_buf is NULL");
+  if (reinterpret_cast<uintptr_t>(dev_buf) % kAlign != 0) return fail(MCLBM_EINVAL, "dev_buf must be 256-byte aligned");
+  if (bytes < B.total) return fail(MCLBM_ENOMEM, "device buffer too small: need " + std::to_string(B.total) + " bytes");
+  mclbm_batch* b = new (std::nothrow) mclbm_batch();
+  if (!b) return fail(MCLBM_ENOMEM, "host allocation failed");
+  b->n = n;
+  b->stream = reinterpret_cast<hipStream_t>(stream);
+  b->base = reinterpret_cast<char*>(dev_buf);
+  b->bytes = bytes;
+  b->off_desc = B.off_desc;
+  b->off_ntiles = B.off_ntiles;
+  b->off_tiles = B.off_tiles;
+  b->tile_cap = B.tile_cap;
+  b->storage = cfgs[0].storage;
+  b->cav.resize(n);
+  b->active.assign(n, 1);
+  size_t work = 0;
+  bool idx32 = true;
+  for (int k = 0; k < n; ++k) {
+    mclbm_cavity* c = &b->cav[k];
+    c->cfg = cfgs[k];
+    if (xis && xis[k]) c->xi.assign(xis[k], xis[k] + (size_t)cfgs[k].nx * cfgs[k].ny);
+    c->stream = b->stream;
+    c->base = b->base + B.off_cav[k];
+    c->bytes = make_layout(cfgs[k]).total;
+    c->in_batch = true;
+    setup_cavity(c);
+    // the batched kernel runs 256-thread workgroups: every tile shape must
+    // cover exactly 256 nodes (bx * by == 256)
+    if (c->block.x * c->block.y != 256) {
+      const int bx = cfgs[k].nx >= 256 ? 256 : (cfgs[k].nx >= 128 ? 128 : 64);
+      c->block = dim3(bx, 256 / bx, 1);
+      c->tiles_x = (cfgs[k].nx + bx - 1) / bx;
+    }
+    work += (size_t)27 * c->L.plane * storage_bytes(b->storage) + (size_t)2 * c->L.plane * sizeof(float2);
+    idx32 = idx32 && c->idx32;
+  }
+  // one access policy for the whole launch, from the working set of the batch
+  b->nt = work > kStreamingBytes;
+  b->idx32 = idx32;
+  for (int k = 0; k < n; ++k) {
+    b->cav[k].nt = b->nt;
+    b->cav[k].idx32 = b->idx32;
+  }
+  int dev = 0, ncu = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) ncu = v;
+  }
+  b->grid = (unsigned)(ncu * 8);
+  hipError_t e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    delete b;
+    return hip_fail(e, "hipStreamCreateWithFlags");
+  }
+  rc = batch_reset_all(b);
+  if (rc) {
+    hipStreamDestroy(b->cap_stream);
+    delete b;
+    return rc;
+  }
+  *out = b;
+  return MCLBM_OK;
+}
+
+int mclbm_batch_step(mclbm_batch* b, int64_t nsteps) {
+  if (!b) return fail(MCLBM_EINVAL, "batch is NULL");
+  if (nsteps < 0) return fail(MCLBM_EINVAL, "nsteps must be >= 0");
+  bool any = false;
+  for (int k = 0; k < b->n; ++k) any = any || b->active[k];
+  if (!any) return MCLBM_OK;
+  while (nsteps > 0) {
+    if (b->graph_steps > 0 && nsteps >= b->graph_steps && (b->t & 1) == 0) {
+      if (!b->gexec || b->gexec_steps != b->graph_steps) {
+        int rc = capture_graph(b);
+        if (rc) return rc;
+      }
+      HIP_TRY(hipGraphLaunch(b->gexec, b->stream));
+      batch_advance(b, b->graph_steps);
+      nsteps -= b->graph_steps;
+    } else {
+      int rc = batch_direct_step(b);
+      if (rc) return rc;
+      nsteps -= 1;
+    }
+  }
+  return MCLBM_OK;
+}
+
+int mclbm_batch_set_graph_steps(mclbm_batch* b, int32_t steps) {
+  if (!b) return fail(MCLBM_EINVAL, "batch is NULL");
+  if (steps != 0 && (steps < 2 || (steps & 1))) return fail(MCLBM_EINVAL, "graph steps must be 0 or an even number >= 2");
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  b->graph_steps = steps;
+  drop_graph(b);
+  return MCLBM_OK;
+}
+
+int mclbm_batch_set_active(mclbm_batch* b, const int32_t* active) {
+  if (!b || !active) return fail(MCLBM_EINVAL, "NULL argument");
+  for (int k = 0; k < b->n; ++k)
+    if (active[k] && !b->active[k] && ((b->cav[k].t - b->t) & 1))
+      return fail(MCLBM_EINVAL, "cavity " + std::to_string(k) + " cannot rejoin: step parity differs");
+  for (int k = 0; k < b->n; ++k) b->active[k] = active[k] ? 1 : 0;
+  return upload_tables(b);
+}
+
+int mclbm_batch_residual(mclbm_batch* b, double tol, double* out, int32_t* status) {
+  if (!b || !out) return fail(MCLBM_EINVAL, "NULL argument");
+  bool changed = false;
+  for (int k = 0; k < b->n; ++k) {
+    int32_t st = 3;
+    out[2 * k] = out[2 * k + 1] = NAN;
+    if (b->active[k]) {
+      double ru = 0.0, rt = 0.0;
+      const int rc = mclbm_residual(&b->cav[k], &ru, &rt);
+      out[2 * k] = ru;
+      out[2 * k + 1] = rt;
+      if (rc == MCLBM_EDIVERGED) {
+        st = 2;
+      } else if (rc) {
+        return rc;
+      } else {
+        st = (tol > 0.0 && ru < tol && rt < tol) ? 1 : 0;
+      }
+      if (st != 0 && tol > 0.0) {
+        b->active[k] = 0;
+        changed = true;
+      }
+    }
+    if (status) status[k] = st;
+  }
+  g_err.clear();
+  if (changed) return upload_tables(b);
+  return MCLBM_OK;
+}
+
+int mclbm_batch_nusselt(mclbm_batch* b, double* out) {
+  if (!b || !out) return fail(MCLBM_EINVAL, "NULL argument");
+  for (int k = 0; k < b->n; ++k) {
+    const int rc = mclbm_nusselt(&b->cav[k], &out[3 * k], &out[3 * k + 1], &out[3 * k + 2]);
+    if (rc && rc != MCLBM_EDIVERGED) return rc;
+  }
+  g_err.clear();
+  return MCLBM_OK;
+}
+
+int mclbm_batch_autotune(mclbm_batch* b, int32_t steps) {
+  if (!b) return fail(MCLBM_EINVAL, "batch is NULL");
+  if (steps < 2) return fail(MCLBM_EINVAL, "autotune needs >= 2 steps per trial");
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  std::vector<char> saved_active = b->active;
+  const int saved_graph = b->graph_steps;
+  b->graph_steps = 0;
+  // size classes
+  std::vector<std::pair<int, int>> classes;
+  for (int k = 0; k < b->n; ++k) {
+    auto key = std::make_pair(b->cav[k].cfg.nx, b->cav[k].cfg.ny);
+    if (std::find(classes.begin(), classes.end(), key) == classes.end()) classes.push_back(key);
+  }
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  int rc = MCLBM_OK;
+  for (const auto& cl : classes) {
+    float best = 1e30f;
+    int best_s = 0;
+    for (int si = 0; si < 4 && !rc; ++si) {
+      for (int k = 0; k < b->n; ++k) {
+        mclbm_cavity* c = &b->cav[k];
+        const bool in = c->cfg.nx == cl.first && c->cfg.ny == cl.second;
+        b->active[k] = in ? 1 : 0;
+        if (in) {
+          c->block = dim3(kShapes[si][0], kShapes[si][1], 1);
+          c->tiles_x = (c->cfg.nx + kShapes[si][0] - 1) / kShapes[si][0];
+          rc = enqueue_init(c);
+          if (rc) break;
+        }
+      }
+      if (rc) break;
+      b->t = 0;
+      rc = upload_tables(b);
+      if (rc) break;
+      for (int w = 0; w < 2 && !rc; ++w) rc = batch_direct_step(b);
+      if (rc) break;
+      hipEventRecord(e0, b->stream);
+      for (int q = 0; q < steps && !rc; ++q) rc = batch_direct_step(b);
+      hipEventRecord(e1, b->stream);
+      if (rc) break;
+      hipError_t he = hipEventSynchronize(e1);
+      if (he != hipSuccess) {
+        rc = hip_fail(he, "hipEventSynchronize");
+        break;
+      }
+      float ms = 0.0f;
+      hipEventElapsedTime(&ms, e0, e1);
+      if (ms < best) {
+        best = ms;
+        best_s = si;
+      }
+    }
+    if (rc) break;
+    for (int k = 0; k < b->n; ++k) {
+      mclbm_cavity* c = &b->cav[k];
+      if (c->cfg.nx == cl.first && c->cfg.ny == cl.second) {
+        c->block = dim3(kShapes[best_s][0], kShapes[best_s][1], 1);
+        c->tiles_x = (c->cfg.nx + kShapes[best_s][0] - 1) / kShapes[best_s][0];
+      }
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  b->graph_steps = saved_graph;
+  drop_graph(b);
+  (void)saved_active;
+  if (rc) return rc;
+  return batch_reset_all(b);
+}
+
+int mclbm_batch_tile_shape(const mclbm_batch* b, int32_t idx, int32_t* bx, int32_t* by) {
+  if (!b || idx < 0 || idx >= b->n) return fail(MCLBM_EINVAL, "bad batch index");
+  if (bx) *bx = (int32_t)b->cav[idx].block.x;
+  if (by) *by = (int32_t)b->cav[idx].block.y;
+  return MCLBM_OK;
+}
+
+int mclbm_batch_reset(mclbm_batch* b) {
+  if (!b) return fail(MCLBM_EINVAL, "batch is NULL");
+  return batch_reset_all(b);
+}
+
+int32_t mclbm_batch_size(const mclbm_batch* b) { return b ? b->n : -1; }
+
+int64_t mclbm_batch_time(const mclbm_batch* b, int32_t idx) {
+  if (!b || idx < 0 || idx >= b->n) return -1;
+  return b->cav[idx].t;
+}
+
+mclbm_cavity* mclbm_batch_cavity(mclbm_batch* b, int32_t idx) {
+  if (!b || idx < 0 || idx >= b->n) return nullptr;
+  return &b->cav[idx];
+}
+
+int mclbm_batch_destroy(mclbm_batch* b) {
+  if (!b) return MCLBM_OK;
+  hipError_t e = hipStreamSynchronize(b->stream);
+  drop_graph(b);
+  if (b->cap_stream) hipStreamDestroy(b->cap_stream);
+  delete b;
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  return MCLBM_OK;
+}
 
 }  // extern "C"
