@@ -34,6 +34,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="HBM bytes per launch measured by rocprofv3 counters")
+    ap.add_argument("--batch", type=int, default=256,
+                    help="cavities in the batched-sweep measurement (0 skips it)")
     ap.add_argument("--no-secondary", action="store_true",
                     help="skip the 2048^2 (larger than the last-level cache) measurement")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -106,6 +108,37 @@ def pmc_summary(fetch_dir, write_dir, workload, out_path):
     print(json.dumps(out, indent=1))
 
 
+def batch_measure(torch, mc, inputs, n, steps=64):
+    """Uneven-cavity parameter sweep: n cavities with sides from
+    {64, 128, 256, 384, 512}, Ra log-uniform in [1e3, 1e6], phi in [0, 5 %],
+    d_p in [10, 100] nm (automatic tau_f), tile shapes from the autotuner,
+    one launch per step replayed from a captured graph."""
+    cfgs = inputs.sweep_parameters(3, n)
+    for c in cfgs:
+        c["tau_f"] = -1.0
+    xis = [inputs.phi_perturbation(c["seed"], c["nx"], c["ny"]) for c in cfgs]
+    b = mc.Batch(cfgs, xis=xis)
+    shapes = b.autotune(steps=8)
+    nodes = sum(c["nx"] * c["ny"] for c in cfgs)
+    b.step(32)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(b.stream)
+    b.step(steps)
+    e1.record(b.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    gbs = BYTES_PER_LUP_FP32 * nodes / (ms * 1e-3) / 1e9
+    out = {"workload": f"sweep of {n} uneven cavities (seed 3)", "nodes": nodes, "steps": steps,
+           "ms_per_step": round(ms, 5), "MLUPS": round(nodes / (ms * 1e-3) / 1e6, 1),
+           "achieved_GBps": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBPS, 4),
+           "tile_shapes": sorted({f"{c['nx']}: {bx}x{by}" for c, (bx, by) in zip(cfgs, shapes)})}
+    b.close()
+    del b
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(w, xi, seconds):
     """The FP64 oracle as it stands, on this host's cores, on a bounded
     sample of the same workload (same cavity, first steps)."""
@@ -113,17 +146,17 @@ def cpu_baseline(w, xi, seconds):
     cfg = {k: v for k, v in w.items() if k != "seed"}
     o = oracle.Oracle(xi=xi, **cfg)
     nodes = cfg["nx"] * cfg["ny"]
-    t0 = time.perf_counter()
     o.step(2)
-    probe = time.perf_counter() - t0
-    steps = max(2, int(seconds / max(probe / 2, 1e-9)))
-    steps = min(steps, 100000)
+    t0 = time.perf_counter()
+    o.step(5)
+    per_step = (time.perf_counter() - t0) / 5
+    steps = max(2, min(int(seconds / max(per_step, 1e-9)), 100000))
     t0 = time.perf_counter()
     o.step(steps)
     dt = time.perf_counter() - t0
     return {"value": nodes * steps / dt / 1e6, "unit": "MLUPS", "cores": oracle.max_threads(),
             "kind": "oracle",
-            "sample": f"{cfg['nx']}x{cfg['ny']} cavity, {steps} steps after 2 warm-up steps, FP64, "
+            "sample": f"{cfg['nx']}x{cfg['ny']} cavity, {steps} steps after 7 warm-up steps, FP64, "
                       f"{dt:.1f} s"}
 
 
@@ -195,6 +228,9 @@ def main():
                      "achieved_GBps": round(gbs2, 1), "frac": round(gbs2 / HBM_PEAK_GBPS, 4)}
         del cav2
         torch.cuda.empty_cache()
+    batched = None
+    if a.batch > 0 and not a.no_secondary:
+        batched = batch_measure(torch, mc, inputs, a.batch)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
             "kernel": "k_step (even and odd A-A parities)",
@@ -211,6 +247,7 @@ def main():
         "roofline": roof,
         "nu_hot": nu_hot,
         "larger_than_llc": secondary,
+        "batched_sweep": batched,
     }
     if not a.no_cpu_baseline:
         print("# cpu baseline (FP64 oracle) ...", file=sys.stderr, flush=True)
@@ -219,10 +256,15 @@ def main():
 
 
 def kernel_hash() -> str:
+    """Hash of the step kernel's device source (the device header and the
+    step_node / k_step text), which the measured traffic belongs to."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("paper_1511_04552_amd/csrc/mclbm.hip", "paper_1511_04552_amd/csrc/lbm_device.h"):
-        h.update(open(os.path.join(ROOT, f), "rb").read())
+    h.update(open(os.path.join(ROOT, "paper_1511_04552_amd/csrc/lbm_device.h"), "rb").read())
+    src = open(os.path.join(ROOT, "paper_1511_04552_amd/csrc/mclbm.hip")).read()
+    a = src.index("// One node of one time step")
+    b = src.index("// Batched sweep:")
+    h.update(src[a:b].encode())
     return h.hexdigest()[:16]
 
 
