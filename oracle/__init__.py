@@ -91,6 +91,7 @@ def lib():
         L.mclbm_oracle_forcing.argtypes = [ctypes.c_double] * 2 + [D]
         L.mclbm_oracle_forcing.restype = None
         L.mclbm_oracle_node_forces.argtypes = [P, D, D]
+        L.mclbm_oracle_load_fields.argtypes = [P, D, D, D, D]
         L.mclbm_oracle_destroy.argtypes = [P]
         L.mclbm_oracle_destroy.restype = None
         L.mclbm_oracle_set_threads.argtypes = [ctypes.c_int]
@@ -179,6 +180,16 @@ class Oracle:
         rc = lib().mclbm_oracle_step(self._h, int(n))
         if rc != 0:
             raise RuntimeError(f"oracle step failed: {rc}")
+
+    def load_fields(self, ux, uy, theta, phi) -> None:
+        """Warm start: equilibrium populations of the given (ny, nx) fields
+        (mixture velocity, temperature, particle volume fraction); t = 0."""
+        arrs = [np.ascontiguousarray(a, dtype=np.float64).reshape(-1) for a in (ux, uy, theta, phi)]
+        if any(a.size != self.nx * self.ny for a in arrs):
+            raise ValueError("fields must hold nx*ny values")
+        rc = lib().mclbm_oracle_load_fields(self._h, *[_dptr(a) for a in arrs])
+        if rc != 0:
+            raise RuntimeError(f"load_fields failed: {rc}")
 
     def moments(self, names=FIELDS) -> dict:
         if isinstance(names, str):

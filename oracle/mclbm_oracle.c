@@ -440,6 +440,21 @@ static void node_moments(const mo_state* o, size_t n, double* rho_f,
   *rho_f = a; *jxf = bx; *jyf = by; *rho_p = c; *jxp = cx; *jyp = cy; *th = t;
 }
 
+/* Lag fields of the first step and the residual snapshot, from the
+ * populations of the initial state. */
+static void init_lag_and_snapshot(mo_state* o) {
+  const size_t nn = o->nn;
+  for (size_t n = 0; n < nn; ++n) {
+    double rf, jxf, jyf, rp, jxp, jyp, th;
+    node_moments(o, n, &rf, &jxf, &jyf, &rp, &jxp, &jyp, &th);
+    o->phi_prev[n] = rp / o->s.R;
+    o->th_prev[n] = th;
+    o->snap_ux[n] = (jxf + jxp) / (rf + rp);
+    o->snap_uy[n] = (jyf + jyp) / (rf + rp);
+    o->snap_th[n] = th;
+  }
+}
+
 int mclbm_oracle_create(const mo_config* cfg, const double* xi,
                         mo_state** out) {
   if (!cfg || !out) return MO_EINVAL;
@@ -489,17 +504,30 @@ int mclbm_oracle_create(const mo_config* cfg, const double* xi,
       o->g[i * nn + n] = 0.0;
     }
   }
-  for (size_t n = 0; n < nn; ++n) {
-    double rf, jxf, jyf, rp, jxp, jyp, th;
-    node_moments(o, n, &rf, &jxf, &jyf, &rp, &jxp, &jyp, &th);
-    o->phi_prev[n] = rp / o->s.R;
-    o->th_prev[n] = th;
-    o->snap_ux[n] = (jxf + jxp) / (rf + rp);
-    o->snap_uy[n] = (jyf + jyp) / (rf + rp);
-    o->snap_th[n] = th;
-  }
+  init_lag_and_snapshot(o);
   o->t = 0;
   *out = o;
+  return MO_OK;
+}
+
+/* Warm start: every node at the second-order equilibrium (Eqs 26-27) of
+ * the given fields, with the fluid partial density of the cold start
+ * (1 - phi0), rho_p~ = R phi and the mixture velocity for both phases;
+ * time restarts at 0. */
+int mclbm_oracle_load_fields(mo_state* o, const double* ux, const double* uy,
+                             const double* theta, const double* phi) {
+  if (!o || !ux || !uy || !theta || !phi) return MO_EINVAL;
+  const size_t nn = o->nn;
+  for (size_t n = 0; n < nn; ++n) {
+    const double rf = o->s.rho_f0, rp = o->s.R * phi[n];
+    for (int i = 0; i < 9; ++i) {
+      o->f[i * nn + n] = equilibrium(i, rf, ux[n], uy[n]);
+      o->p[i * nn + n] = equilibrium(i, rp, ux[n], uy[n]);
+      o->g[i * nn + n] = equilibrium(i, theta[n], ux[n], uy[n]);
+    }
+  }
+  init_lag_and_snapshot(o);
+  o->t = 0;
   return MO_OK;
 }
 
