@@ -148,6 +148,28 @@ int mclbm_set_properties(mclbm_cavity* c, double Ra, double phi0,
 /* Restart from the initial state (time 0).  Async. */
 int mclbm_reset(mclbm_cavity* c);
 
+/* Warm start: restart at time 0 from given fields instead of the fluid at
+ * rest.  The initial state of the method is an equilibrium one (Eqs 26-27);
+ * here every node takes the equilibrium of the given fields instead, so a
+ * prediction of the steady flow shortens the transient while the time
+ * stepping, and so the steady state it converges to, are unchanged.
+ *   dev_fields: device FP32, sy x sx x 4 channel-last (row y, column x):
+ *     mixture velocity u_x, u_y (lattice units), dimensionless temperature
+ *     theta and particle volume fraction phi, sampled at the cell centres of
+ *     an sx x sy grid over the cavity (sx, sy >= 1);
+ *   affine: NULL (identity) or 8 host doubles: channel c is taken as
+ *     affine[c] * v + affine[4 + c].
+ * Lattice node (x, y) samples position s_x = (x + 1/2) sx / nx - 1/2
+ * (clamped to [0, sx - 1]; likewise y) bilinearly in FP64.  phi is clipped
+ * at 0 and rescaled so that its lattice sum equals that of the cold start,
+ * sum max(phi0 + A xi, 0) (the particle mass of the closed cavity is
+ * conserved); if nothing is left it becomes uniform.  The fluid partial
+ * density is that of the cold start, rho_f~ = 1 - phi0, rho_p~ = R phi, and
+ * both phases move with u.  Synchronous on the cavity's stream.  Members of
+ * a batch are rejected (MCLBM_ESTATE). */
+int mclbm_load_fields(mclbm_cavity* c, const float* dev_fields, int32_t sx,
+                      int32_t sy, const double* affine);
+
 /* Advance nsteps >= 0 time steps (Eqs 18-36: collision with the slip
  * forces, streaming, walls).  Each step is one fused kernel launch.  Async. */
 int mclbm_step(mclbm_cavity* c, int64_t nsteps);

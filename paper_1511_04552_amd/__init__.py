@@ -29,7 +29,7 @@ FIELD_BIT = {name: 1 << i for i, name in enumerate(FIELDS)}
 DERIVED = ("nu_L", "alpha_L", "H", "dx", "dt", "G_L", "grav_L", "Ck", "R", "tau_f",
            "rhoc_ratio", "beta_ratio", "rho_f0", "rho_p0", "nu_f", "alpha_f")
 EXPORTED = ("mclbm_config_defaults", "mclbm_device_bytes", "mclbm_derive_constants", "mclbm_create",
-            "mclbm_set_properties", "mclbm_reset", "mclbm_step", "mclbm_time",
+            "mclbm_set_properties", "mclbm_reset", "mclbm_load_fields", "mclbm_step", "mclbm_time",
             "mclbm_export_moments", "mclbm_read_moments", "mclbm_read_populations",
             "mclbm_export_populations", "mclbm_nusselt", "mclbm_residual",
             "mclbm_derived", "mclbm_destroy", "mclbm_last_error", "mclbm_copy_kernel",
@@ -38,7 +38,9 @@ EXPORTED = ("mclbm_config_defaults", "mclbm_device_bytes", "mclbm_derive_constan
             "mclbm_batch_set_graph_steps", "mclbm_batch_set_active", "mclbm_batch_residual",
             "mclbm_batch_nusselt", "mclbm_batch_autotune", "mclbm_batch_tile_shape",
             "mclbm_batch_reset", "mclbm_batch_size", "mclbm_batch_time", "mclbm_batch_cavity",
-            "mclbm_batch_destroy")
+            "mclbm_batch_destroy",
+            "mclbm_nn_gemm", "mclbm_nn_bias_act", "mclbm_nn_act_backward", "mclbm_nn_colsum_scratch",
+            "mclbm_nn_colsum", "mclbm_nn_mse_scratch", "mclbm_nn_mse", "mclbm_nn_adamw")
 
 
 class MclbmError(RuntimeError):
@@ -90,6 +92,7 @@ def lib(load_torch: bool = True):
     L.mclbm_create.argtypes = [CP, D, P, ctypes.c_size_t, P, ctypes.POINTER(P)]
     L.mclbm_set_properties.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_double]
     L.mclbm_reset.argtypes = [P]
+    L.mclbm_load_fields.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32, D]
     L.mclbm_step.argtypes = [P, ctypes.c_int64]
     L.mclbm_time.argtypes = [P]
     L.mclbm_time.restype = ctypes.c_int64
@@ -125,6 +128,18 @@ def lib(load_torch: bool = True):
     L.mclbm_batch_cavity.argtypes = [P, ctypes.c_int32]
     L.mclbm_batch_cavity.restype = P
     L.mclbm_batch_destroy.argtypes = [P]
+    i64, i32, f32 = ctypes.c_int64, ctypes.c_int32, ctypes.c_float
+    L.mclbm_nn_gemm.argtypes = [i32, i32, i32, i32, i32, f32, P, i64, i64, i64, P, i64, i64, i64,
+                                f32, P, i64, i64, i64, i32, i32, P]
+    L.mclbm_nn_bias_act.argtypes = [P, P, i64, i32, i32, P, P]
+    L.mclbm_nn_act_backward.argtypes = [P, P, i64, i32, P]
+    L.mclbm_nn_colsum_scratch.argtypes = [i64, i32]
+    L.mclbm_nn_colsum_scratch.restype = i64
+    L.mclbm_nn_colsum.argtypes = [P, P, i64, i32, f32, P, P]
+    L.mclbm_nn_mse_scratch.argtypes = [i64]
+    L.mclbm_nn_mse_scratch.restype = i64
+    L.mclbm_nn_mse.argtypes = [P, P, P, i64, P, P, P]
+    L.mclbm_nn_adamw.argtypes = [P, P, P, P, i64, f32, f32, f32, f32, f32, i32, P]
     _lib = L
     return L
 
@@ -235,6 +250,23 @@ class Cavity:
 
     def set_properties(self, Ra: float, phi0: float, dp_m: float) -> None:
         _check(lib().mclbm_set_properties(self._h, float(Ra), float(phi0), float(dp_m)))
+
+    def load_fields(self, fields, affine=None) -> None:
+        """Warm start from fields: a float32 device tensor (sy, sx, 4) holding
+        (u_x, u_y, theta, phi) per cell; affine: None or 8 floats mapping
+        channel c to affine[c] * v + affine[4 + c].  Restarts at t = 0."""
+        import torch
+        if fields.dtype != torch.float32 or not fields.is_cuda or fields.dim() != 3 or fields.shape[2] != 4:
+            raise ValueError("fields must be a float32 device tensor of shape (sy, sx, 4)")
+        f = fields.contiguous()
+        aff = None
+        if affine is not None:
+            self._affine = np.ascontiguousarray(affine, dtype=np.float64)
+            if self._affine.size != 8:
+                raise ValueError("affine must hold 8 values")
+            aff = _dptr(self._affine)
+        _check(lib().mclbm_load_fields(self._h, ctypes.c_void_p(f.data_ptr()), int(f.shape[1]),
+                                       int(f.shape[0]), aff))
 
     # ---- outputs ------------------------------------------------------------
     @staticmethod

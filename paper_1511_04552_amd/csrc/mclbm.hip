@@ -272,6 +272,100 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__
   }
 }
 
+// Warm start: bilinear samples of channel-last fields (sy x sx x 4) at the
+// lattice nodes, cell-centred on both grids, in FP64.
+struct FieldMap {
+  const float* F;
+  int sx, sy;
+  double a[4], b[4];
+};
+
+__device__ __forceinline__ void field_axis(int i, int n_dst, int n_src, int& i0, int& i1, double& w) {
+  double s = ((double)i + 0.5) * (double)n_src / (double)n_dst - 0.5;
+  s = fmin(fmax(s, 0.0), (double)(n_src - 1));
+  i0 = (int)floor(s);
+  i1 = min(i0 + 1, n_src - 1);
+  w = s - (double)i0;
+}
+
+__device__ __forceinline__ double field_sample(const FieldMap& M, int c, int x0, int x1, double wx, int y0,
+                                               int y1, double wy) {
+  auto v = [&](int yy, int xx) {
+    return M.a[c] * (double)M.F[((long long)yy * M.sx + xx) * 4 + c] + M.b[c];
+  };
+  return (1.0 - wy) * ((1.0 - wx) * v(y0, x0) + wx * v(y0, x1)) +
+         wy * ((1.0 - wx) * v(y1, x0) + wx * v(y1, x1));
+}
+
+// Per-block sums of the clipped phi samples (slot 0 of 5 per block).
+__global__ __launch_bounds__(256) void k_load_phi_sum(FieldMap M, int nx, int ny,
+                                                      double* __restrict__ partial) {
+  __shared__ double lds[4];
+  const long long nn = (long long)nx * ny;
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  double s = 0.0;
+  if (k < nn) {
+    const int x = (int)(k % nx), y = (int)(k / nx);
+    int x0, x1, y0, y1;
+    double wx, wy;
+    field_axis(x, nx, M.sx, x0, x1, wx);
+    field_axis(y, ny, M.sy, y0, y1, wy);
+    s = fmax(field_sample(M, 3, x0, x1, wx, y0, y1, wy), 0.0);
+  }
+  s = block_sum(s, lds);
+  if (threadIdx.x == 0) {
+    double* o = partial + 5 * (long long)blockIdx.x;
+    o[0] = s; o[1] = 0.0; o[2] = 0.0; o[3] = 0.0; o[4] = 0.0;
+  }
+}
+
+// Equilibrium populations (Eqs 26-27) of the sampled fields, with phi
+// rescaled to the cold-start inventory; then the lag field of the first
+// step from the stored state, as at a cold start.
+template <class S>
+__global__ __launch_bounds__(256) void k_load_fields(StepParams P, FieldMap M,
+                                                     typename S::T* __restrict__ pop,
+                                                     const double* __restrict__ phi_sum,
+                                                     double inventory, double rho_f0, double R,
+                                                     float2* __restrict__ d2prev) {
+  const long long nn = (long long)P.nx * P.ny;
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nn) return;
+  const int x = (int)(k % P.nx), y = (int)(k / P.nx);
+  int x0, x1, y0, y1;
+  double wx, wy;
+  field_axis(x, P.nx, M.sx, x0, x1, wx);
+  field_axis(y, P.ny, M.sy, y0, y1, wy);
+  const double ux = field_sample(M, 0, x0, x1, wx, y0, y1, wy);
+  const double uy = field_sample(M, 1, x0, x1, wx, y0, y1, wy);
+  const double th = field_sample(M, 2, x0, x1, wx, y0, y1, wy);
+  const double total = phi_sum[0];
+  double phi = fmax(field_sample(M, 3, x0, x1, wx, y0, y1, wy), 0.0);
+  phi = total > 0.0 ? phi * (inventory / total) : inventory / (double)nn;
+  const double rf = rho_f0, rp = R * phi;
+  const double rf_ref = (double)P.rho_f_ref, rp_ref = (double)P.rho_p_ref;
+  const double uu = ux * ux + uy * uy;
+  const long long n = (long long)y * P.px + x;
+  float f[9], p[9], g[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const double eu = (double)ex(i) * ux + (double)ey(i) * uy;
+    const double shape = 3.0 * eu + 4.5 * eu * eu - 1.5 * uu;
+    const double w = wgt_d(i);
+    S::st(pop + P.plane * i + n, (float)(w * ((rf - rf_ref) + rf * shape)), P.scale[0]);
+    S::st(pop + P.plane * (9 + i) + n, (float)(w * ((rp - rp_ref) + rp * shape)), P.scale[1]);
+    S::st(pop + P.plane * (18 + i) + n, (float)(w * th * (1.0 + shape)), P.scale[2]);
+  }
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    f[i] = S::ld(pop + P.plane * i + n, P.inv_scale[0]);
+    p[i] = S::ld(pop + P.plane * (9 + i) + n, P.inv_scale[1]);
+    g[i] = S::ld(pop + P.plane * (18 + i) + n, P.inv_scale[2]);
+  }
+  const NodeMoments m = moments(f, p, g);
+  d2prev[n] = make_float2(m.drp * P.invR, m.th);
+}
+
 // Snapshot of the initial state for the first residual call.
 template <bool ODD, class S, class I>
 __global__ __launch_bounds__(256) void k_export(StepParams P,
@@ -359,6 +453,14 @@ __global__ __launch_bounds__(256) void k_copy(float4* __restrict__ dst,
 namespace {
 
 thread_local std::string g_err;
+
+}  // namespace
+
+namespace mclbm_host {
+void set_last_error(const std::string& msg) { g_err = msg; }
+}  // namespace mclbm_host
+
+namespace {
 
 int fail(int code, const std::string& msg) {
   g_err = msg;
@@ -760,6 +862,50 @@ int export_pops(mclbm_cavity* c, int q, double* dev_out) {
   });
 }
 
+int enqueue_load_fields(mclbm_cavity* c, const float* F, int sx, int sy, const double* affine) {
+  const mclbm_config& cfg = c->cfg;
+  const long long nn = (long long)cfg.nx * cfg.ny;
+  FieldMap M{};
+  M.F = F;
+  M.sx = sx;
+  M.sy = sy;
+  for (int q = 0; q < 4; ++q) {
+    M.a[q] = affine ? affine[q] : 1.0;
+    M.b[q] = affine ? affine[4 + q] : 0.0;
+  }
+  // particle inventory of the cold start (the initial state of mclbm_create)
+  double inventory = 0.0;
+  for (long long k = 0; k < nn; ++k) {
+    double phi = cfg.phi0;
+    if (!c->xi.empty()) phi += cfg.phi_perturb_amp * c->xi[(size_t)k];
+    inventory += phi < 0.0 ? 0.0 : phi;
+  }
+  HIP_TRY(hipMemsetAsync(c->d5(), 0, (size_t)6 * c->L.px * sizeof(float), c->stream));
+  k_load_phi_sum<<<c->L.red_blocks, 256, 0, c->stream>>>(M, cfg.nx, cfg.ny, c->part());
+  int rc = launch_check("k_load_phi_sum");
+  if (rc) return rc;
+  k_sum_partials<<<1, 256, 0, c->stream>>>(c->part(), c->L.red_blocks, c->res());
+  rc = launch_check("k_sum_partials");
+  if (rc) return rc;
+  rc = dispatch(c, [&](auto k) {
+    using S = typename decltype(k)::S;
+    using I = typename decltype(k)::I;
+    auto* pop = reinterpret_cast<typename S::T*>(c->pop());
+    k_load_fields<S><<<node_blocks(c), 256, 0, c->stream>>>(c->P, M, pop, c->res(), inventory,
+                                                            c->D.v[MCLBM_D_RHO_F0], c->D.v[MCLBM_D_R],
+                                                            c->d2(1));
+    int r = launch_check("k_load_fields");
+    if (r) return r;
+    k_residual<false, S, I><<<c->L.red_blocks, 256, 0, c->stream>>>(
+        c->P, pop, c->d5(), (double)c->P.rho_f_ref, (double)c->P.rho_p_ref, c->snap(), c->part());
+    return launch_check("k_residual");
+  });
+  if (rc) return rc;
+  c->t = 0;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return MCLBM_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -852,6 +998,18 @@ int mclbm_reset(mclbm_cavity* c) {
   if (!c) return fail(MCLBM_EINVAL, "cavity is NULL");
   if (c->in_batch) return fail(MCLBM_ESTATE, "cavity belongs to a batch: use the batch calls");
   return enqueue_init(c);
+}
+
+int mclbm_load_fields(mclbm_cavity* c, const float* dev_fields, int32_t sx, int32_t sy,
+                      const double* affine) {
+  if (!c || !dev_fields) return fail(MCLBM_EINVAL, "load_fields: NULL cavity or fields");
+  if (c->in_batch) return fail(MCLBM_ESTATE, "load_fields: cavity belongs to a batch");
+  if (sx < 1 || sy < 1 || (long long)sx * sy > (1LL << 30))
+    return fail(MCLBM_EINVAL, "load_fields: source grid must be at least 1 x 1 and at most 2^30 cells");
+  if (affine)
+    for (int q = 0; q < 8; ++q)
+      if (!std::isfinite(affine[q])) return fail(MCLBM_EINVAL, "load_fields: affine map not finite");
+  return enqueue_load_fields(c, dev_fields, sx, sy, affine);
 }
 
 int mclbm_step(mclbm_cavity* c, int64_t nsteps) {
@@ -1166,7 +1324,7 @@ int batch_direct_step(mclbm_batch* b) {
 }
 
 void drop_graph(mclbm_batch* b) {
-  if (b->gexec) hipGraphExecDestroy(b->gexec);
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
   b->gexec = nullptr;
   b->gexec_steps = 0;
 }
@@ -1183,12 +1341,12 @@ int capture_graph(mclbm_batch* b) {
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
   if (rc) {
-    if (g) hipGraphDestroy(g);
+    if (g) (void)hipGraphDestroy(g);
     return rc;
   }
   if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
   e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
-  hipGraphDestroy(g);
+  (void)hipGraphDestroy(g);
   if (e != hipSuccess) {
     b->gexec = nullptr;
     return hip_fail(e, "hipGraphInstantiate");
@@ -1286,7 +1444,7 @@ int mclbm_batch_create(const mclbm_config* cfgs, int32_t n, const double* const*
   }
   rc = batch_reset_all(b);
   if (rc) {
-    hipStreamDestroy(b->cap_stream);
+    (void)hipStreamDestroy(b->cap_stream);
     delete b;
     return rc;
   }
@@ -1414,9 +1572,9 @@ int mclbm_batch_autotune(mclbm_batch* b, int32_t steps) {
       if (rc) break;
       for (int w = 0; w < 2 && !rc; ++w) rc = batch_direct_step(b);
       if (rc) break;
-      hipEventRecord(e0, b->stream);
+      HIP_TRY(hipEventRecord(e0, b->stream));
       for (int q = 0; q < steps && !rc; ++q) rc = batch_direct_step(b);
-      hipEventRecord(e1, b->stream);
+      HIP_TRY(hipEventRecord(e1, b->stream));
       if (rc) break;
       hipError_t he = hipEventSynchronize(e1);
       if (he != hipSuccess) {
@@ -1424,7 +1582,7 @@ int mclbm_batch_autotune(mclbm_batch* b, int32_t steps) {
         break;
       }
       float ms = 0.0f;
-      hipEventElapsedTime(&ms, e0, e1);
+      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
       if (ms < best) {
         best = ms;
         best_s = si;
@@ -1439,8 +1597,8 @@ int mclbm_batch_autotune(mclbm_batch* b, int32_t steps) {
       }
     }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   b->graph_steps = saved_graph;
   drop_graph(b);
   (void)saved_active;
@@ -1476,7 +1634,7 @@ int mclbm_batch_destroy(mclbm_batch* b) {
   if (!b) return MCLBM_OK;
   hipError_t e = hipStreamSynchronize(b->stream);
   drop_graph(b);
-  if (b->cap_stream) hipStreamDestroy(b->cap_stream);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
   delete b;
   if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
   return MCLBM_OK;

@@ -1,0 +1,256 @@
+"""Warm-start surrogate: a Fourier neural operator mapping the cavity
+parameters (Ra, phi0, d_p) and a coordinate grid to near-steady fields
+(u, v, theta, phi).  The lattice Boltzmann solver starts from its prediction
+(``Cavity.load_fields``) and still runs to its own convergence criterion, so
+the surrogate changes the time to steady state, never the converged answer.
+
+Every operation runs in the library's kernels (``include/mclbm_nn.h``): the
+matrix products (the Fourier transforms are written as products with cosine
+and sine matrices) on BF16 matrix cores with FP32 accumulation, and the bias,
+activation, loss and optimiser steps as elementwise kernels.  PyTorch only
+owns the device buffers.
+
+Network on an S x S grid, channel-last activations (B, S, S, C):
+  h_0 = a W_lift + b_lift                         (a: 5 input features)
+  s_l = spectral_l(h_l) + h_l W_l + b_l,  h_l+1 = GELU(s_l) (identity last)
+  out = GELU(h_L P1 + c1) P2 + c2                 (4 output fields)
+spectral(h) = (1/S^2) sum_{ky in K_y, kx < m} alpha(kx)
+              Re{ (H R)(ky, kx) e^{+2 pi i (ky y + kx x)/S} },
+H(ky, kx) = sum_{y,x} h e^{-2 pi i (ky y + kx x)/S}, K_y = {0..m-1} u
+{S-m..S-1}, alpha(0) = 1, alpha(kx > 0) = 2, R complex per mode.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+
+import numpy as np
+
+from . import _check, lib
+
+GELU, IDENT = 1, 0
+
+
+def _p(t, off=0):
+    return ctypes.c_void_p(t.data_ptr() + 4 * int(off))
+
+
+class _Ops:
+    """Kernel calls on one stream."""
+
+    def __init__(self, torch, stream):
+        self.torch = torch
+        self.s = ctypes.c_void_p(stream.cuda_stream)
+
+    def gemm(self, ta, tb, M, N, K, alpha, A, aoff, lda, sa1, sa2, B, boff, ldb, sb1, sb2,
+             beta, C, coff, ldc, sc1, sc2, nb1=1, nb2=1):
+        _check(lib().mclbm_nn_gemm(ta, tb, M, N, K, alpha, _p(A, aoff), lda, sa1, sa2,
+                                   _p(B, boff), ldb, sb1, sb2, beta, _p(C, coff), ldc, sc1, sc2,
+                                   nb1, nb2, self.s))
+
+    def bias_act(self, y, bias, rows, cols, act, pre=None):
+        _check(lib().mclbm_nn_bias_act(_p(y), None if bias is None else _p(bias), rows, cols, act,
+                                       None if pre is None else _p(pre), self.s))
+
+    def act_backward(self, dy, pre, act):
+        _check(lib().mclbm_nn_act_backward(_p(dy), _p(pre), dy.numel(), act, self.s))
+
+    def colsum(self, dy, db, rows, cols, scratch, beta=0.0):
+        _check(lib().mclbm_nn_colsum(_p(dy), _p(db), rows, cols, beta, _p(scratch), self.s))
+
+    def mse(self, y, t, dy, scratch, loss):
+        _check(lib().mclbm_nn_mse(_p(y), _p(t), _p(dy), y.numel(), _p(scratch), _p(loss), self.s))
+
+    def adamw(self, w, g, m, v, lr, b1, b2, eps, wd, t):
+        _check(lib().mclbm_nn_adamw(_p(w), _p(g), _p(m), _p(v), w.numel(), lr, b1, b2, eps, wd, t, self.s))
+
+
+def dft_matrices(S: int, m: int) -> dict:
+    """Real matrices of the truncated transforms (float32)."""
+    x = np.arange(S)
+    kx = np.arange(m)
+    ky = np.array(list(range(m)) + list(range(S - m, S)))
+    tx = 2 * np.pi * np.outer(kx, x) / S            # (m, S)
+    ty = 2 * np.pi * np.outer(ky, x) / S            # (2m, S)
+    Gc, Gs = np.cos(ty), np.sin(ty)
+    G = np.block([[Gc, Gs], [-Gs, Gc]])            # (4m, 2S): forward along y
+    Hm = np.block([[Gc.T, -Gs.T], [Gs.T, Gc.T]])   # (2S, 4m): inverse along y
+    alpha = np.where(kx == 0, 1.0, 2.0)
+    Ec = (np.cos(tx) * alpha[:, None]).T / (S * S)  # (S, m): inverse along x, real part
+    Es = (-np.sin(tx) * alpha[:, None]).T / (S * S)
+    return {"Fc": np.cos(tx), "Fs": -np.sin(tx), "G": G, "Hm": Hm, "Ec": Ec, "Es": Es}
+
+
+class FNO:
+    """Fourier neural operator on the GPU (training and inference)."""
+
+    def __init__(self, S=64, C=32, m=12, L=4, Q=64, B=16, seed=0, device="cuda", stream=None):
+        import torch
+        self.torch = torch
+        self.S, self.C, self.m, self.L, self.Q, self.B = S, C, m, L, Q, B
+        self.M2 = 2 * m
+        self.nq = self.M2 * m
+        self.dev = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.dev)
+        self.ops = _Ops(torch, self.stream)
+        rng = np.random.default_rng(seed)
+        f32 = lambda a: torch.tensor(np.asarray(a, dtype=np.float32), device=self.dev)
+        self.mats = {k: f32(v) for k, v in dft_matrices(S, m).items()}
+        p = {"W_lift": rng.normal(0, 1 / math.sqrt(5), (5, C)), "b_lift": np.zeros(C)}
+        for l in range(L):
+            sc = 1.0 / (C * C)
+            p[f"R_re_{l}"] = sc * rng.uniform(0, 1, (self.M2, m, C, C))
+            p[f"R_im_{l}"] = sc * rng.uniform(0, 1, (self.M2, m, C, C))
+            p[f"W_{l}"] = rng.normal(0, 1 / math.sqrt(C), (C, C))
+            p[f"b_{l}"] = np.zeros(C)
+        p["P1"] = rng.normal(0, 1 / math.sqrt(C), (C, Q))
+        p["c1"] = np.zeros(Q)
+        p["P2"] = rng.normal(0, 1 / math.sqrt(Q), (Q, 4))
+        p["c2"] = np.zeros(4)
+        self.params = {k: f32(v) for k, v in p.items()}
+        self.grads = {k: torch.zeros_like(v) for k, v in self.params.items()}
+        self.adam_m = {k: torch.zeros_like(v) for k, v in self.params.items()}
+        self.adam_v = {k: torch.zeros_like(v) for k, v in self.params.items()}
+        self.adam_t = 0
+        self._alloc(B)
+
+    # ---- buffers --------------------------------------------------------
+    def _alloc(self, B):
+        torch, S, C, m, Q = self.torch, self.S, self.C, self.m, self.Q
+        z = lambda *shape: torch.zeros(*shape, dtype=torch.float32, device=self.dev)
+        self.B = B
+        rows = B * S * S
+        self.h = [z(rows, C) for _ in range(self.L + 1)]        # layer inputs / outputs
+        self.pre = [z(rows, C) for _ in range(self.L)]          # pre-activations
+        self.Y = [z(B, 2, self.nq, C) for _ in range(self.L)]    # spectra after the y-transform
+        self.X = z(B, 2, S, m, C)
+        self.Z = z(B, 2, self.nq, C)
+        self.W = z(B, 2, S, m, C)
+        self.qpre, self.q = z(rows, Q), z(rows, Q)
+        self.out = z(rows, 4)
+        self.dout, self.dq = z(rows, 4), z(rows, Q)
+        self.dh, self.dh2 = z(rows, C), z(rows, C)
+        self.dX, self.dZ, self.dW, self.dY = z(B, 2, S, m, C), z(B, 2, self.nq, C), z(B, 2, S, m, C), z(B, 2, self.nq, C)
+        ncol = max(C, Q, 4)
+        self.cs_scratch = z(int(lib().mclbm_nn_colsum_scratch(rows, ncol)))
+        self.mse_scratch = torch.zeros(int(lib().mclbm_nn_mse_scratch(rows * 4)), dtype=torch.float64, device=self.dev)
+        self.loss_dev = torch.zeros(1, dtype=torch.float64, device=self.dev)
+
+    # ---- spectral layer -------------------------------------------------
+    def _spectral_forward(self, h, l, out):
+        o, S, C, m, nq, B = self.ops, self.S, self.C, self.m, self.nq, self.B
+        M, SmC, mC = self.mats, S * m * C, m * C
+        # x-transform, per (b, y): X_re = Fc h[b, y], X_im = Fs h[b, y]
+        for ri, F in ((0, M["Fc"]), (1, M["Fs"])):
+            o.gemm(0, 0, m, C, S, 1.0, F, 0, S, 0, 0, h, 0, C, S * S * C, S * C,
+                   0.0, self.X, ri * SmC, C, 2 * SmC, mC, B, S)
+        # y-transform, per b: [Y_re; Y_im] = G [X_re; X_im]
+        Y = self.Y[l]
+        o.gemm(0, 0, 2 * self.M2, mC, 2 * S, 1.0, M["G"], 0, 2 * S, 0, 0, self.X, 0, mC, 2 * SmC, 0,
+               0.0, Y, 0, mC, 2 * nq * C, 0, B, 1)
+        # complex mode mixing, per mode q: Z = Y R
+        Rr, Ri = self.params[f"R_re_{l}"], self.params[f"R_im_{l}"]
+        ld = 2 * nq * C
+        for (yi, Rt, zi, alpha, beta) in ((0, Rr, 0, 1.0, 0.0), (1, Ri, 0, -1.0, 1.0),
+                                          (0, Ri, 1, 1.0, 0.0), (1, Rr, 1, 1.0, 1.0)):
+            o.gemm(0, 0, B, C, C, alpha, Y, yi * nq * C, ld, C, 0, Rt, 0, C, C * C, 0,
+                   beta, self.Z, zi * nq * C, ld, C, 0, nq, 1)
+        # inverse y-transform, per b: [W_re; W_im] = Hm [Z_re; Z_im]
+        o.gemm(0, 0, 2 * S, mC, 2 * self.M2, 1.0, M["Hm"], 0, 2 * self.M2, 0, 0, self.Z, 0, mC, 2 * nq * C, 0,
+               0.0, self.W, 0, mC, 2 * SmC, 0, B, 1)
+        # inverse x-transform (real part), per (b, y): out = Ec W_re + Es W_im
+        for ri, E, beta in ((0, M["Ec"], 0.0), (1, M["Es"], 1.0)):
+            o.gemm(0, 0, S, C, m, 1.0, E, 0, m, 0, 0, self.W, ri * SmC, C, 2 * SmC, mC,
+                   beta, out, 0, C, S * S * C, S * C, B, S)
+
+    def _spectral_backward(self, l, dout, dh):
+        """dh += spectral_l^T(dout); accumulates dR_re, dR_im."""
+        o, S, C, m, nq, B = self.ops, self.S, self.C, self.m, self.nq, self.B
+        M, SmC, mC = self.mats, S * m * C, m * C
+        for ri, E in ((0, M["Ec"]), (1, M["Es"])):
+            o.gemm(1, 0, m, C, S, 1.0, E, 0, m, 0, 0, dout, 0, C, S * S * C, S * C,
+                   0.0, self.dW, ri * SmC, C, 2 * SmC, mC, B, S)
+        o.gemm(1, 0, 2 * self.M2, mC, 2 * S, 1.0, M["Hm"], 0, 2 * self.M2, 0, 0, self.dW, 0, mC, 2 * SmC, 0,
+               0.0, self.dZ, 0, mC, 2 * nq * C, 0, B, 1)
+        Y = self.Y[l]
+        Rr, Ri = self.params[f"R_re_{l}"], self.params[f"R_im_{l}"]
+        gRr, gRi = self.grads[f"R_re_{l}"], self.grads[f"R_im_{l}"]
+        ld = 2 * nq * C
+        # dY_re = dZ_re Rr^T + dZ_im Ri^T ; dY_im = -dZ_re Ri^T + dZ_im Rr^T
+        for (zi, Rt, yi, alpha, beta) in ((0, Rr, 0, 1.0, 0.0), (1, Ri, 0, 1.0, 1.0),
+                                          (0, Ri, 1, -1.0, 0.0), (1, Rr, 1, 1.0, 1.0)):
+            o.gemm(0, 1, B, C, C, alpha, self.dZ, zi * nq * C, ld, C, 0, Rt, 0, C, C * C, 0,
+                   beta, self.dY, yi * nq * C, ld, C, 0, nq, 1)
+        # dRr = Y_re^T dZ_re + Y_im^T dZ_im ; dRi = -Y_im^T dZ_re + Y_re^T dZ_im
+        for (yi, zi, G_, alpha, beta) in ((0, 0, gRr, 1.0, 0.0), (1, 1, gRr, 1.0, 1.0),
+                                          (1, 0, gRi, -1.0, 0.0), (0, 1, gRi, 1.0, 1.0)):
+            o.gemm(1, 0, C, C, B, alpha, Y, yi * nq * C, ld, C, 0, self.dZ, zi * nq * C, ld, C, 0,
+                   beta, G_, 0, C, C * C, 0, nq, 1)
+        o.gemm(1, 0, 2 * S, mC, 2 * self.M2, 1.0, M["G"], 0, 2 * S, 0, 0, self.dY, 0, mC, 2 * nq * C, 0,
+               0.0, self.dX, 0, mC, 2 * SmC, 0, B, 1)
+        for ri, F in ((0, M["Fc"]), (1, M["Fs"])):
+            o.gemm(1, 0, S, C, m, 1.0, F, 0, S, 0, 0, self.dX, ri * SmC, C, 2 * SmC, mC,
+                   1.0, dh, 0, C, S * S * C, S * C, B, S)
+
+    # ---- whole network ----------------------------------------------------
+    def forward(self, a):
+        """a: (B, S, S, 5) float32 device tensor.  Returns (B, S, S, 4)."""
+        o, C, Q = self.ops, self.C, self.Q
+        rows = self.B * self.S * self.S
+        a = a.reshape(rows, 5)
+        self._a = a
+        P = self.params
+        o.gemm(0, 0, rows, C, 5, 1.0, a, 0, 5, 0, 0, P["W_lift"], 0, C, 0, 0, 0.0, self.h[0], 0, C, 0, 0)
+        o.bias_act(self.h[0], P["b_lift"], rows, C, IDENT)
+        for l in range(self.L):
+            s = self.h[l + 1]
+            self._spectral_forward(self.h[l], l, s)
+            o.gemm(0, 0, rows, C, C, 1.0, self.h[l], 0, C, 0, 0, P[f"W_{l}"], 0, C, 0, 0, 1.0, s, 0, C, 0, 0)
+            o.bias_act(s, P[f"b_{l}"], rows, C, GELU if l < self.L - 1 else IDENT, self.pre[l])
+        o.gemm(0, 0, rows, Q, C, 1.0, self.h[self.L], 0, C, 0, 0, P["P1"], 0, Q, 0, 0, 0.0, self.q, 0, Q, 0, 0)
+        o.bias_act(self.q, P["c1"], rows, Q, GELU, self.qpre)
+        o.gemm(0, 0, rows, 4, Q, 1.0, self.q, 0, Q, 0, 0, P["P2"], 0, 4, 0, 0, 0.0, self.out, 0, 4, 0, 0)
+        o.bias_act(self.out, P["c2"], rows, 4, IDENT)
+        return self.out.reshape(self.B, self.S, self.S, 4)
+
+    def backward(self, target):
+        """MSE against target (B, S, S, 4): fills self.grads, returns the loss
+        (device tensor, FP64)."""
+        o, C, Q = self.ops, self.C, self.Q
+        rows = self.B * self.S * self.S
+        P, G = self.params, self.grads
+        o.mse(self.out, target.reshape(rows, 4), self.dout, self.mse_scratch, self.loss_dev)
+        o.colsum(self.dout, G["c2"], rows, 4, self.cs_scratch)
+        o.gemm(1, 0, Q, 4, rows, 1.0, self.q, 0, Q, 0, 0, self.dout, 0, 4, 0, 0, 0.0, G["P2"], 0, 4, 0, 0)
+        o.gemm(0, 1, rows, Q, 4, 1.0, self.dout, 0, 4, 0, 0, P["P2"], 0, 4, 0, 0, 0.0, self.dq, 0, Q, 0, 0)
+        o.act_backward(self.dq, self.qpre, GELU)
+        o.colsum(self.dq, G["c1"], rows, Q, self.cs_scratch)
+        o.gemm(1, 0, C, Q, rows, 1.0, self.h[self.L], 0, C, 0, 0, self.dq, 0, Q, 0, 0, 0.0, G["P1"], 0, Q, 0, 0)
+        dh = self.dh
+        o.gemm(0, 1, rows, C, Q, 1.0, self.dq, 0, Q, 0, 0, P["P1"], 0, Q, 0, 0, 0.0, dh, 0, C, 0, 0)
+        for l in reversed(range(self.L)):
+            if l < self.L - 1:
+                o.act_backward(dh, self.pre[l], GELU)
+            o.colsum(dh, G[f"b_{l}"], rows, C, self.cs_scratch)
+            o.gemm(1, 0, C, C, rows, 1.0, self.h[l], 0, C, 0, 0, dh, 0, C, 0, 0, 0.0, G[f"W_{l}"], 0, C, 0, 0)
+            dprev = self.dh2
+            o.gemm(0, 1, rows, C, C, 1.0, dh, 0, C, 0, 0, P[f"W_{l}"], 0, C, 0, 0, 0.0, dprev, 0, C, 0, 0)
+            self._spectral_backward(l, dh, dprev)
+            self.dh, self.dh2 = dprev, dh
+            dh = self.dh
+        o.colsum(dh, G["b_lift"], rows, C, self.cs_scratch)
+        o.gemm(1, 0, 5, C, rows, 1.0, self._a, 0, 5, 0, 0, dh, 0, C, 0, 0, 0.0, G["W_lift"], 0, C, 0, 0)
+        return self.loss_dev
+
+    def step(self, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, wd=1e-4):
+        self.adam_t += 1
+        for k, w in self.params.items():
+            self.ops.adamw(w, self.grads[k], self.adam_m[k], self.adam_v[k], lr, b1, b2, eps, wd, self.adam_t)
+
+    # ---- persistence -----------------------------------------------------
+    def state(self) -> dict:
+        return {k: v.detach().cpu().numpy() for k, v in self.params.items()}
+
+    def load_state(self, st: dict) -> None:
+        for k, v in st.items():
+            self.params[k].copy_(self.torch.tensor(v, dtype=self.torch.float32))

@@ -1,0 +1,110 @@
+"""Warm start (mclbm_load_fields) against the oracle: field resampling,
+particle-inventory rescaling, equilibrium populations, and the time steps
+that follow."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import oracle  # noqa: E402
+from oracle import warmstart  # noqa: E402
+import paper_1511_04552_amd as mc  # noqa: E402
+from paper_1511_04552_amd import inputs  # noqa: E402
+
+DEV = torch.device("cuda")
+
+
+def _fields(seed, sx, sy):
+    """Smooth synthetic fields in standardised units (u, v ~ 1, theta in
+    [-1/2, 1/2], phi deviation ~ 1) on an sx x sy grid."""
+    rng = np.random.default_rng(seed)
+    xs = (np.arange(sx) + 0.5) / sx
+    ys = (np.arange(sy) + 0.5) / sy
+    X, Y = np.meshgrid(xs, ys)
+    F = np.zeros((sy, sx, 4), np.float32)
+    F[..., 0] = np.sin(np.pi * X) * np.sin(2 * np.pi * Y) * rng.uniform(0.5, 1.5)
+    F[..., 1] = -np.sin(2 * np.pi * X) * np.sin(np.pi * Y) * rng.uniform(0.5, 1.5)
+    F[..., 2] = 0.5 - X + 0.1 * np.sin(np.pi * Y)
+    F[..., 3] = rng.normal(size=(sy, sx)) * 0.3 + (Y - 0.5)
+    return F
+
+
+def _case(cfg, xi, F, affine, steps):
+    nx, ny = cfg["nx"], cfg["ny"]
+    g = mc.Cavity(xi=xi, **cfg)
+    g.step(7)  # the load must not depend on the prior state
+    g.load_fields(torch.tensor(F, device=DEV), affine=affine)
+    assert g.time == 0
+    o = oracle.Oracle(xi=xi, **cfg)
+    fx = warmstart.resample(F, nx, ny, scale=affine[:4], offset=affine[4:])
+    inv = warmstart.cold_inventory(cfg["phi0"], o.cfg.phi_perturb_amp, xi, nx * ny)
+    phi = warmstart.renormalize(fx[3], inv)
+    o.load_fields(fx[0], fx[1], fx[2], phi)
+    return g, o
+
+
+def _compare(g, o, tol=1e-5):
+    mg, mo = g.moments(), o.moments()
+    for f in mo:
+        scale = np.abs(mo[f]).max()
+        if scale > 0:
+            err = np.abs(mg[f] - mo[f]).max() / scale
+            assert err <= tol, (f, err)
+
+
+@pytest.mark.parametrize("cfg,src", [
+    (dict(nx=37, ny=29, Ra=1e4, phi0=0.02, dp_nm=40.0), (13, 9)),
+    (dict(nx=64, ny=64, Ra=1e5, phi0=0.03, dp_nm=50.0, tau_f=-1.0), (16, 16)),
+    (dict(nx=70, ny=45, Ra=3e4, phi0=0.01, dp_nm=100.0), (70, 45)),
+    (dict(nx=16, ny=16, Ra=1e3, phi0=0.04, dp_nm=30.0), (1, 1)),
+])
+def test_load_fields_matches_oracle(cfg, src):
+    sx, sy = src
+    xi = inputs.phi_perturbation(31, cfg["nx"], cfg["ny"])
+    F = _fields(sx * 100 + sy, sx, sy)
+    U = 0.02
+    affine = [U, U, 1.0, 0.005, 0.0, 0.0, 0.0, cfg["phi0"]]
+    g, o = _case(cfg, xi, F, affine, 0)
+    _compare(g, o)
+    # the lag field and the residual snapshot are those of the loaded state
+    res_g, res_o = g.residual(), o.residual()
+    assert res_g[0] == 0.0 and res_o[0] == 0.0
+    for steps in (1, 300):
+        g.step(steps)
+        o.step(steps)
+        _compare(g, o)
+    nu_g, nu_o = g.nusselt(), o.nusselt()
+    assert abs(nu_g[0] - nu_o[0]) <= 1e-4 * abs(nu_o[0])
+
+
+def test_particle_inventory_equals_cold_start():
+    cfg = dict(nx=48, ny=40, Ra=1e4, phi0=0.02, dp_nm=60.0, phi_perturb_amp=0.01)
+    xi = inputs.phi_perturbation(8, 48, 40)
+    cold = mc.Cavity(xi=xi, **cfg)
+    F = _fields(3, 12, 10)
+    F[..., 3] = np.abs(F[..., 3]) * 5.0  # a very different particle field
+    warm = mc.Cavity(xi=xi, **cfg)
+    warm.load_fields(torch.tensor(F, device=DEV), affine=[0.01, 0.01, 1, 0.01, 0, 0, 0, 0])
+    pc, pw = cold.moments("phi")["phi"].sum(), warm.moments("phi")["phi"].sum()
+    assert abs(pw - pc) <= 1e-6 * pc
+    assert abs(pc - np.maximum(0.02 + 0.01 * xi, 0).sum()) <= 1e-6 * pc
+
+
+def test_load_fields_rejects_bad_arguments():
+    c = mc.Cavity(nx=16, ny=16, Ra=1e4)
+    L = mc.lib()
+    F = torch.zeros(4, 4, 4, device=DEV)
+    import ctypes
+    p = ctypes.c_void_p(F.data_ptr())
+    assert L.mclbm_load_fields(c._h, p, 0, 4, None) == mc.EINVAL
+    assert L.mclbm_load_fields(c._h, None, 4, 4, None) == mc.EINVAL
+    bad = np.array([1, 1, 1, np.nan, 0, 0, 0, 0], dtype=np.float64)
+    assert L.mclbm_load_fields(c._h, p, 4, 4, bad.ctypes.data_as(ctypes.POINTER(ctypes.c_double))) == mc.EINVAL
+    b = mc.Batch([dict(nx=16, ny=16, Ra=1e4)] * 2)
+    assert L.mclbm_load_fields(b.members[0]._h, p, 4, 4, None) == mc.ESTATE
+    with pytest.raises(ValueError):
+        c.load_fields(torch.zeros(4, 4, 3, device=DEV))
