@@ -165,8 +165,10 @@ int mclbm_reset(mclbm_cavity* c);
  * sum max(phi0 + A xi, 0) (the particle mass of the closed cavity is
  * conserved); if nothing is left it becomes uniform.  The fluid partial
  * density is that of the cold start, rho_f~ = 1 - phi0, rho_p~ = R phi, and
- * both phases move with u.  Synchronous on the cavity's stream.  Members of
- * a batch are rejected (MCLBM_ESTATE). */
+ * both phases move with u.  Synchronous on the cavity's stream.  A member
+ * of a batch (mclbm_batch_cavity) may be loaded while the batch is at an
+ * even step count (MCLBM_ESTATE otherwise): its time restarts at 0 and it
+ * keeps its active flag. */
 int mclbm_load_fields(mclbm_cavity* c, const float* dev_fields, int32_t sx,
                       int32_t sy, const double* affine);
 

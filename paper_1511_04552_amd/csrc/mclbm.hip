@@ -705,6 +705,7 @@ struct mclbm_cavity {
   bool nt;             // non-temporal population traffic
   bool idx32;          // 32-bit element offsets
   bool in_batch;       // owned by a batch: stepped only through it
+  const int64_t* batch_clock;  // the owning batch's step count (members only)
   std::vector<double> host_dev_p;  // initial phi deviations (source of an async copy)
 
   void* pop() { return base + L.off_pop; }
@@ -1003,7 +1004,10 @@ int mclbm_reset(mclbm_cavity* c) {
 int mclbm_load_fields(mclbm_cavity* c, const float* dev_fields, int32_t sx, int32_t sy,
                       const double* affine) {
   if (!c || !dev_fields) return fail(MCLBM_EINVAL, "load_fields: NULL cavity or fields");
-  if (c->in_batch) return fail(MCLBM_ESTATE, "load_fields: cavity belongs to a batch");
+  // A batch steps all members with one parity; a loaded state is in the
+  // even-step layout, so a member may be loaded only at an even batch step.
+  if (c->in_batch && (!c->batch_clock || (*c->batch_clock & 1)))
+    return fail(MCLBM_ESTATE, "load_fields: the batch is at an odd step; step it once more first");
   if (sx < 1 || sy < 1 || (long long)sx * sy > (1LL << 30))
     return fail(MCLBM_EINVAL, "load_fields: source grid must be at least 1 x 1 and at most 2^30 cells");
   if (affine)
@@ -1408,6 +1412,7 @@ int mclbm_batch_create(const mclbm_config* cfgs, int32_t n, const double* const*
     c->base = b->base + B.off_cav[k];
     c->bytes = make_layout(cfgs[k]).total;
     c->in_batch = true;
+    c->batch_clock = &b->t;
     setup_cavity(c);
     // the batched kernel runs 256-thread workgroups: every tile shape must
     // cover exactly 256 nodes (bx * by == 256)

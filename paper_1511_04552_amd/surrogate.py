@@ -32,7 +32,9 @@ GELU, IDENT = 1, 0
 
 
 def _p(t, off=0):
-    return ctypes.c_void_p(t.data_ptr() + 4 * int(off))
+    if not t.is_contiguous():
+        raise ValueError("kernel operands must be contiguous")
+    return ctypes.c_void_p(t.data_ptr() + t.element_size() * int(off))
 
 
 class _Ops:
@@ -78,7 +80,8 @@ def dft_matrices(S: int, m: int) -> dict:
     alpha = np.where(kx == 0, 1.0, 2.0)
     Ec = (np.cos(tx) * alpha[:, None]).T / (S * S)  # (S, m): inverse along x, real part
     Es = (-np.sin(tx) * alpha[:, None]).T / (S * S)
-    return {"Fc": np.cos(tx), "Fs": -np.sin(tx), "G": G, "Hm": Hm, "Ec": Ec, "Es": Es}
+    mats = {"Fc": np.cos(tx), "Fs": -np.sin(tx), "G": G, "Hm": Hm, "Ec": Ec, "Es": Es}
+    return {k: np.ascontiguousarray(v, dtype=np.float32) for k, v in mats.items()}
 
 
 class FNO:
@@ -94,7 +97,7 @@ class FNO:
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.dev)
         self.ops = _Ops(torch, self.stream)
         rng = np.random.default_rng(seed)
-        f32 = lambda a: torch.tensor(np.asarray(a, dtype=np.float32), device=self.dev)
+        f32 = lambda a: torch.tensor(np.ascontiguousarray(a, dtype=np.float32), device=self.dev)
         self.mats = {k: f32(v) for k, v in dft_matrices(S, m).items()}
         p = {"W_lift": rng.normal(0, 1 / math.sqrt(5), (5, C)), "b_lift": np.zeros(C)}
         for l in range(L):
@@ -254,3 +257,197 @@ class FNO:
     def load_state(self, st: dict) -> None:
         for k, v in st.items():
             self.params[k].copy_(self.torch.tensor(v, dtype=self.torch.float32))
+
+
+# ==========================================================================
+# Warm start: data, training, prediction, loading
+# ==========================================================================
+TARGETS = ("ux_ns", "uy_ns", "theta", "phi")
+
+
+def velocity_scale(cfg: dict) -> float:
+    """Convective velocity scale alpha sqrt(Ra) / H in lattice units: it
+    makes the steady velocities of the whole Ra range O(0.1 - 0.3)."""
+    from . import derive_constants
+    kw = {k: v for k, v in cfg.items() if k != "seed"}
+    d = derive_constants(**kw)
+    return d["alpha_L"] * math.sqrt(max(cfg["Ra"], 1.0)) / cfg["nx"]
+
+
+def features(cases, S: int) -> np.ndarray:
+    """Network input (n, S, S, 5): scaled log10 Ra, phi0, d_p and the cell
+    coordinates in [-1, 1]."""
+    n = len(cases)
+    a = np.zeros((n, S, S, 5), np.float32)
+    xs = 2.0 * (np.arange(S) + 0.5) / S - 1.0
+    for k, c in enumerate(cases):
+        a[k, :, :, 0] = (math.log10(max(c["Ra"], 1.0)) - 4.5) / 1.5
+        a[k, :, :, 1] = (c["phi0"] - 0.025) / 0.025
+        a[k, :, :, 2] = (c["dp_nm"] - 55.0) / 45.0
+        a[k, :, :, 3] = xs[None, :]
+        a[k, :, :, 4] = xs[:, None]
+    return a
+
+
+def nondimensional(moments: dict, cfg: dict) -> np.ndarray:
+    """(ny, nx, 4): u / U, v / U, theta, phi / phi0 - 1 (0 without
+    particles)."""
+    U = velocity_scale(cfg)
+    out = np.zeros(moments["theta"].shape + (4,), np.float32)
+    out[..., 0] = moments["ux_ns"] / U
+    out[..., 1] = moments["uy_ns"] / U
+    out[..., 2] = moments["theta"]
+    if cfg["phi0"] > 1e-4:
+        out[..., 3] = moments["phi"] / cfg["phi0"] - 1.0
+    return out
+
+
+def _cavity_kw(c: dict) -> dict:
+    return {k: v for k, v in c.items() if k != "seed"}
+
+
+def generate_dataset(cases, chunk: int = 2000, tol: float = 1e-6, max_steps: int = 2_000_000,
+                     log=None):
+    """Run the cases (square cavities of one side) to steady state as one
+    batch with drop-out: a cavity leaves the batch when the relative change
+    of u and theta over ``chunk`` steps is below ``tol``.  Returns the
+    nondimensional fields (n, S, S, 4), the step counts and a converged
+    mask."""
+    from . import Batch
+    b = Batch([_cavity_kw(c) for c in cases])
+    n = len(cases)
+    status = np.zeros(n, np.int32)
+    steps = np.zeros(n, np.int64)
+    b.residual(tol=0.0)
+    t = 0
+    while t < max_steps and (status == 0).any():
+        b.step(chunk)
+        t += chunk
+        _, st = b.residual(tol=tol)
+        newly = (status == 0) & (st != 0)
+        steps[newly] = t
+        status[newly] = st[newly]
+        if log:
+            log(f"  t={t} converged {(status == 1).sum()}/{n} diverged {(status == 2).sum()}")
+    fields = np.stack([nondimensional(b.members[k].moments(TARGETS), cases[k]) for k in range(n)])
+    return fields, steps, status == 1
+
+
+class WarmStart:
+    """Learned initial condition: the FNO plus the per-channel
+    standardisation of its targets."""
+
+    def __init__(self, S=64, C=32, m=12, L=4, Q=64, B=16, seed=0, device="cuda"):
+        self.S, self.B = S, B
+        self.net = FNO(S=S, C=C, m=m, L=L, Q=Q, B=B, seed=seed, device=device)
+        self.torch = self.net.torch
+        self.mean = np.zeros(4)
+        self.std = np.ones(4)
+        self.seed = seed
+
+    def fit(self, cases, fields, epochs=100, lr=2e-3, lr_min=1e-4, wd=1e-5, log=None):
+        """AdamW on the mean-squared error of the standardised fields, with a
+        cosine learning-rate schedule.  Returns the loss per epoch."""
+        torch = self.torch
+        n = len(cases)
+        if n < self.B:
+            raise ValueError("need at least one batch of training cases")
+        self.mean = fields.reshape(-1, 4).mean(0).astype(np.float64)
+        self.std = np.maximum(fields.reshape(-1, 4).std(0).astype(np.float64), 1e-6)
+        y = ((fields - self.mean) / self.std).astype(np.float32)
+        dev = self.net.dev
+        X = torch.tensor(features(cases, self.S), device=dev)
+        Y = torch.tensor(y, device=dev)
+        rng = np.random.default_rng(self.seed)
+        nb = n // self.B
+        total = epochs * nb
+        hist = []
+        it = 0
+        for ep in range(epochs):
+            perm = rng.permutation(n)
+            acc = torch.zeros(1, dtype=torch.float64, device=dev)
+            for j in range(nb):
+                idx = torch.tensor(perm[j * self.B:(j + 1) * self.B], device=dev)
+                xb = X.index_select(0, idx).contiguous()
+                yb = Y.index_select(0, idx).contiguous()
+                self.net.forward(xb)
+                acc += self.net.backward(yb)
+                cur = lr_min + 0.5 * (lr - lr_min) * (1.0 + math.cos(math.pi * it / total))
+                self.net.step(lr=cur, wd=wd)
+                it += 1
+            hist.append(float(acc) / nb)
+            if log and (ep % 10 == 0 or ep == epochs - 1):
+                log(f"  epoch {ep} loss {hist[-1]:.4e}")
+        return hist
+
+    def predict(self, cases):
+        """Standardised predictions (n, S, S, 4) as a float32 device tensor."""
+        torch = self.torch
+        n = len(cases)
+        X = features(cases, self.S)
+        out = torch.empty((n, self.S, self.S, 4), dtype=torch.float32, device=self.net.dev)
+        for j in range(0, n, self.B):
+            chunk = X[j:j + self.B]
+            k = chunk.shape[0]
+            if k < self.B:
+                chunk = np.concatenate([chunk, np.repeat(chunk[-1:], self.B - k, 0)])
+            res = self.net.forward(torch.tensor(chunk, device=self.net.dev))
+            out[j:j + k].copy_(res[:k])
+        return out
+
+    def affine(self, cfg: dict) -> list:
+        """Map of the standardised channels to the fields mclbm_load_fields
+        takes (u, v in lattice units, theta, phi)."""
+        U = velocity_scale(cfg)
+        p0 = cfg["phi0"]
+        s, m = self.std, self.mean
+        return [U * s[0], U * s[1], s[2], p0 * s[3], U * m[0], U * m[1], m[2], p0 * (1.0 + m[3])]
+
+    def load(self, cavity, cfg: dict, pred) -> None:
+        """Warm-start one cavity (or batch member) from its prediction."""
+        cavity.load_fields(pred.contiguous(), affine=self.affine(cfg))
+
+    def state(self) -> dict:
+        st = {f"p_{k}": v for k, v in self.net.state().items()}
+        st["mean"], st["std"] = self.mean, self.std
+        return st
+
+    def load_state(self, st: dict) -> None:
+        self.net.load_state({k[2:]: v for k, v in st.items() if k.startswith("p_")})
+        self.mean, self.std = np.asarray(st["mean"]), np.asarray(st["std"])
+
+
+def time_to_steady(cases, warm: WarmStart | None = None, chunk: int = 1000, tol: float = 1e-6,
+                   max_steps: int = 4_000_000):
+    """Steps until the relative change of u and theta over ``chunk`` steps
+    falls below ``tol`` for each case (cold start, or warm start from
+    ``warm``), run as one batch with drop-out.  Returns (steps, Nu at the
+    hot wall, converged mask, seconds spent on prediction and loading)."""
+    import time
+    from . import Batch
+    torch = warm.torch if warm is not None else __import__("torch")
+    b = Batch([_cavity_kw(c) for c in cases])
+    n = len(cases)
+    t_load = 0.0
+    if warm is not None:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pred = warm.predict(cases)
+        for k, c in enumerate(cases):
+            warm.load(b.members[k], c, pred[k])
+        torch.cuda.synchronize()
+        t_load = time.perf_counter() - t0
+    status = np.zeros(n, np.int32)
+    steps = np.zeros(n, np.int64)
+    b.residual(tol=0.0)
+    t = 0
+    while t < max_steps and (status == 0).any():
+        b.step(chunk)
+        t += chunk
+        _, st = b.residual(tol=tol)
+        newly = (status == 0) & (st != 0)
+        steps[newly] = t
+        status[newly] = st[newly]
+    nu = b.nusselt()[:, 0].copy()
+    fields = np.stack([nondimensional(b.members[k].moments(TARGETS), cases[k]) for k in range(n)])
+    return steps, nu, status == 1, t_load, fields

@@ -138,7 +138,8 @@ def test_elementwise_kernels_match_definitions():
     ms = torch.zeros(int(mc.lib().mclbm_nn_mse_scratch(n)), dtype=torch.float64, device=DEV)
     loss = torch.zeros(1, dtype=torch.float64, device=DEV)
     ops.mse(torch.tensor(a, device=DEV), torch.tensor(t, device=DEV), d, ms, loss)
-    diff = a.astype(np.float64) - t
+    # the residual y - t is formed in FP32, its square summed in FP64
+    diff = (a - t).astype(np.float64)
     assert abs(float(loss) - (diff ** 2).mean()) <= 1e-12 * (diff ** 2).mean()
     np.testing.assert_allclose(d.cpu().numpy(), 2 * diff / n, rtol=1e-6)
 

@@ -56,29 +56,42 @@ def _compare(g, o, tol=1e-5):
             assert err <= tol, (f, err)
 
 
+NO_ROT = mc.F_ALL & ~mc.F_MAGROT
+
+
 @pytest.mark.parametrize("cfg,src", [
-    (dict(nx=37, ny=29, Ra=1e4, phi0=0.02, dp_nm=40.0), (13, 9)),
-    (dict(nx=64, ny=64, Ra=1e5, phi0=0.03, dp_nm=50.0, tau_f=-1.0), (16, 16)),
+    (dict(nx=37, ny=29, Ra=1e4, phi0=0.02, dp_nm=40.0, force_mask=NO_ROT), (13, 9)),
+    (dict(nx=64, ny=64, Ra=1e5, phi0=0.03, dp_nm=50.0, tau_f=-1.0, force_mask=NO_ROT), (16, 16)),
     (dict(nx=70, ny=45, Ra=3e4, phi0=0.01, dp_nm=100.0), (70, 45)),
+    (dict(nx=37, ny=29, Ra=1e4, phi0=0.02, dp_nm=40.0), (13, 9)),
     (dict(nx=16, ny=16, Ra=1e3, phi0=0.04, dp_nm=30.0), (1, 1)),
 ])
 def test_load_fields_matches_oracle(cfg, src):
+    """The loaded state matches at t = 0 and the steps that follow stay
+    within 1e-5.  The particle-rotation term acts along the unit vector of
+    the slip; a warm start begins with both phases at one velocity, where
+    that direction is set by rounding on either side, so with that term on
+    the first steps are compared only after the drag has relaxed the slip
+    (a few steps); step-by-step parity from step 1 is checked without it."""
     sx, sy = src
     xi = inputs.phi_perturbation(31, cfg["nx"], cfg["ny"])
     F = _fields(sx * 100 + sy, sx, sy)
     U = 0.02
     affine = [U, U, 1.0, 0.005, 0.0, 0.0, 0.0, cfg["phi0"]]
     g, o = _case(cfg, xi, F, affine, 0)
-    _compare(g, o)
+    _compare(g, o, tol=1e-6)
     # the lag field and the residual snapshot are those of the loaded state
     res_g, res_o = g.residual(), o.residual()
     assert res_g[0] == 0.0 and res_o[0] == 0.0
-    for steps in (1, 300):
-        g.step(steps)
-        o.step(steps)
+    rot = cfg.get("force_mask", mc.F_ALL) & mc.F_MAGROT
+    t = 0
+    for target in ((100, 300) if rot else (1, 2, 300)):
+        g.step(target - t)
+        o.step(target - t)
+        t = target
         _compare(g, o)
     nu_g, nu_o = g.nusselt(), o.nusselt()
-    assert abs(nu_g[0] - nu_o[0]) <= 1e-4 * abs(nu_o[0])
+    assert abs(nu_g[0] - nu_o[0]) <= 1e-4 * max(abs(nu_o[0]), 1.0)
 
 
 def test_particle_inventory_equals_cold_start():
@@ -105,6 +118,28 @@ def test_load_fields_rejects_bad_arguments():
     bad = np.array([1, 1, 1, np.nan, 0, 0, 0, 0], dtype=np.float64)
     assert L.mclbm_load_fields(c._h, p, 4, 4, bad.ctypes.data_as(ctypes.POINTER(ctypes.c_double))) == mc.EINVAL
     b = mc.Batch([dict(nx=16, ny=16, Ra=1e4)] * 2)
+    b.step(1)
     assert L.mclbm_load_fields(b.members[0]._h, p, 4, 4, None) == mc.ESTATE
     with pytest.raises(ValueError):
         c.load_fields(torch.zeros(4, 4, 3, device=DEV))
+
+
+def test_batch_member_load_equals_single_cavity():
+    """A member loaded at an even batch step runs bitwise like a loaded
+    single cavity; the other members are unaffected."""
+    cfgs = [dict(nx=37, ny=29, Ra=1e4, phi0=0.02, dp_nm=40.0), dict(nx=64, ny=48, Ra=1e5, phi0=0.03, dp_nm=50.0)]
+    xis = [inputs.phi_perturbation(40 + k, c["nx"], c["ny"]) for k, c in enumerate(cfgs)]
+    F = torch.tensor(_fields(7, 16, 12), device=DEV)
+    aff = [0.02, 0.02, 1.0, 0.005, 0.0, 0.0, 0.0, 0.02]
+    b = mc.Batch(cfgs, xis=xis)
+    b.step(10)
+    b.members[0].load_fields(F, affine=aff)
+    assert b.time(0) == 0 and b.time(1) == 10
+    b.step(64)
+    single = mc.Cavity(xi=xis[0], **cfgs[0])
+    single.load_fields(F, affine=aff)
+    single.step(64)
+    assert np.array_equal(b.members[0].populations(), single.populations())
+    other = mc.Cavity(xi=xis[1], **cfgs[1])
+    other.step(74)
+    assert np.array_equal(b.members[1].populations(), other.populations())
