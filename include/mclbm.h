@@ -153,24 +153,26 @@ int mclbm_reset(mclbm_cavity* c);
  * here every node takes the equilibrium of the given fields instead, so a
  * prediction of the steady flow shortens the transient while the time
  * stepping, and so the steady state it converges to, are unchanged.
- *   dev_fields: device FP32, sy x sx x 4 channel-last (row y, column x):
+ *   dev_fields: device FP32, sy x sx x nc channel-last (row y, column x):
  *     mixture velocity u_x, u_y (lattice units), dimensionless temperature
- *     theta and particle volume fraction phi, sampled at the cell centres of
- *     an sx x sy grid over the cavity (sx, sy >= 1);
- *   affine: NULL (identity) or 8 host doubles: channel c is taken as
- *     affine[c] * v + affine[4 + c].
+ *     theta, particle volume fraction phi and, if nc == 5, the deviation of
+ *     the fluid partial density rho_f~ from its cold-start value 1 - phi0
+ *     (the pressure field), sampled at the cell centres of an sx x sy grid
+ *     over the cavity (sx, sy >= 1, nc = 4 or 5);
+ *   affine: NULL (identity) or 2 nc host doubles: channel c is taken as
+ *     affine[c] * v + affine[nc + c].
  * Lattice node (x, y) samples position s_x = (x + 1/2) sx / nx - 1/2
  * (clamped to [0, sx - 1]; likewise y) bilinearly in FP64.  phi is clipped
  * at 0 and rescaled so that its lattice sum equals that of the cold start,
  * sum max(phi0 + A xi, 0) (the particle mass of the closed cavity is
- * conserved); if nothing is left it becomes uniform.  The fluid partial
- * density is that of the cold start, rho_f~ = 1 - phi0, rho_p~ = R phi, and
- * both phases move with u.  Synchronous on the cavity's stream.  A member
- * of a batch (mclbm_batch_cavity) may be loaded while the batch is at an
- * even step count (MCLBM_ESTATE otherwise): its time restarts at 0 and it
- * keeps its active flag. */
+ * conserved); if nothing is left it becomes uniform.  rho_f~ = 1 - phi0
+ * plus the density deviation less its lattice mean (the fluid mass is
+ * conserved too), rho_p~ = R phi, and both phases move with u.  Synchronous
+ * on the cavity's stream.  A member of a batch (mclbm_batch_cavity) may be
+ * loaded while the batch is at an even step count (MCLBM_ESTATE otherwise):
+ * its time restarts at 0 and it keeps its active flag. */
 int mclbm_load_fields(mclbm_cavity* c, const float* dev_fields, int32_t sx,
-                      int32_t sy, const double* affine);
+                      int32_t sy, int32_t nc, const double* affine);
 
 /* Advance nsteps >= 0 time steps (Eqs 18-36: collision with the slip
  * forces, streaming, walls).  Each step is one fused kernel launch.  Async. */

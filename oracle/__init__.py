@@ -83,6 +83,7 @@ def lib():
         L.mclbm_oracle_time.restype = ctypes.c_int64
         L.mclbm_oracle_read_moments.argtypes = [P, ctypes.c_uint32, D, ctypes.c_size_t]
         L.mclbm_oracle_read_populations.argtypes = [P, D, ctypes.c_size_t]
+        L.mclbm_oracle_write_populations.argtypes = [P, D, ctypes.c_size_t]
         L.mclbm_oracle_nusselt.argtypes = [P, D, D, D]
         L.mclbm_oracle_residual.argtypes = [P, D, D]
         L.mclbm_oracle_derived.argtypes = [P, D, ctypes.c_int]
@@ -91,7 +92,7 @@ def lib():
         L.mclbm_oracle_forcing.argtypes = [ctypes.c_double] * 2 + [D]
         L.mclbm_oracle_forcing.restype = None
         L.mclbm_oracle_node_forces.argtypes = [P, D, D]
-        L.mclbm_oracle_load_fields.argtypes = [P, D, D, D, D]
+        L.mclbm_oracle_load_fields.argtypes = [P, D, D, D, D, D]
         L.mclbm_oracle_destroy.argtypes = [P]
         L.mclbm_oracle_destroy.restype = None
         L.mclbm_oracle_set_threads.argtypes = [ctypes.c_int]
@@ -181,13 +182,17 @@ class Oracle:
         if rc != 0:
             raise RuntimeError(f"oracle step failed: {rc}")
 
-    def load_fields(self, ux, uy, theta, phi) -> None:
+    def load_fields(self, ux, uy, theta, phi, rho_f=None) -> None:
         """Warm start: equilibrium populations of the given (ny, nx) fields
-        (mixture velocity, temperature, particle volume fraction); t = 0."""
+        (mixture velocity, temperature, particle volume fraction and,
+        optionally, the fluid partial density); t = 0."""
         arrs = [np.ascontiguousarray(a, dtype=np.float64).reshape(-1) for a in (ux, uy, theta, phi)]
+        if rho_f is not None:
+            arrs.append(np.ascontiguousarray(rho_f, dtype=np.float64).reshape(-1))
         if any(a.size != self.nx * self.ny for a in arrs):
             raise ValueError("fields must hold nx*ny values")
-        rc = lib().mclbm_oracle_load_fields(self._h, *[_dptr(a) for a in arrs])
+        ptrs = [_dptr(a) for a in arrs] + ([None] if rho_f is None else [])
+        rc = lib().mclbm_oracle_load_fields(self._h, *ptrs)
         if rc != 0:
             raise RuntimeError(f"load_fields failed: {rc}")
 
@@ -204,6 +209,12 @@ class Oracle:
             raise RuntimeError(f"read_moments failed: {rc}")
         out = out.reshape(len(order), self.ny, self.nx)
         return {n: out[k] for k, n in enumerate(order)}
+
+    def write_populations(self, pops: np.ndarray) -> None:
+        a = np.ascontiguousarray(pops, dtype=np.float64).reshape(-1)
+        rc = lib().mclbm_oracle_write_populations(self._h, _dptr(a), a.size)
+        if rc != 0:
+            raise RuntimeError(f"write_populations failed: {rc}")
 
     def populations(self) -> np.ndarray:
         out = np.zeros(27 * self.nx * self.ny)

@@ -510,20 +510,55 @@ int mclbm_oracle_create(const mo_config* cfg, const double* xi,
   return MO_OK;
 }
 
-/* Warm start: every node at the second-order equilibrium (Eqs 26-27) of
- * the given fields, with the fluid partial density of the cold start
- * (1 - phi0), rho_p~ = R phi and the mixture velocity for both phases;
- * time restarts at 0. */
+/* Difference of a node field along x (dx = 1) or y (dx = 0): central
+ * inside, one-sided at the first and last node. */
+static double field_diff(const double* a, int nx, int ny, int x, int y, int along_x) {
+  const int n = y * nx + x;
+  if (along_x) {
+    if (x == 0) return a[n + 1] - a[n];
+    if (x == nx - 1) return a[n] - a[n - 1];
+    return 0.5 * (a[n + 1] - a[n - 1]);
+  }
+  if (y == 0) return a[n + nx] - a[n];
+  if (y == ny - 1) return a[n] - a[n - nx];
+  return 0.5 * (a[n + nx] - a[n - nx]);
+}
+
+/* Warm start from given fields (fluid partial density rho_f, NULL: 1 - phi0
+ * of the cold start; rho_p~ = R phi; the mixture velocity for both phases):
+ * every node takes the second-order equilibria (Eqs 26-27) plus the
+ * first-order non-equilibrium parts of the Chapman-Enskog expansion of the
+ * BGK lattices (Eqs 18-19): -3 tau_f W_i rho_f (e_i e_i - I/3) : grad u on
+ * the fluid lattice and -tau_theta W_i e_i . grad theta on the temperature
+ * lattice (tau_theta of Eq 24 at the node's phi), with gradients by node
+ * differences; the particle lattice takes its equilibrium.  Time restarts
+ * at 0. */
 int mclbm_oracle_load_fields(mo_state* o, const double* ux, const double* uy,
-                             const double* theta, const double* phi) {
+                             const double* theta, const double* phi,
+                             const double* rho_f) {
   if (!o || !ux || !uy || !theta || !phi) return MO_EINVAL;
-  const size_t nn = o->nn;
-  for (size_t n = 0; n < nn; ++n) {
-    const double rf = o->s.rho_f0, rp = o->s.R * phi[n];
-    for (int i = 0; i < 9; ++i) {
-      o->f[i * nn + n] = equilibrium(i, rf, ux[n], uy[n]);
-      o->p[i * nn + n] = equilibrium(i, rp, ux[n], uy[n]);
-      o->g[i * nn + n] = equilibrium(i, theta[n], ux[n], uy[n]);
+  const int nx = o->nx, ny = o->ny;
+  const Setup* s = &o->s;
+  for (int y = 0; y < ny; ++y) {
+    for (int x = 0; x < nx; ++x) {
+      const size_t n = (size_t)y * nx + x, nn = o->nn;
+      const double rf = rho_f ? rho_f[n] : s->rho_f0, rp = s->R * phi[n];
+      const double dxux = field_diff(ux, nx, ny, x, y, 1), dyux = field_diff(ux, nx, ny, x, y, 0);
+      const double dxuy = field_diff(uy, nx, ny, x, y, 1), dyuy = field_diff(uy, nx, ny, x, y, 0);
+      const double dxth = field_diff(theta, nx, ny, x, y, 1), dyth = field_diff(theta, nx, ny, x, y, 0);
+      const double phic = phi[n] > 0.0 ? phi[n] : 0.0;
+      const double r_k = 1.0 + s->Ck * pow(phic, 0.764);
+      const double r_rhoc = 1.0 + phi[n] * (s->rhoc_ratio - 1.0);
+      const double tau_th = 3.0 * s->alpha_L * r_k / r_rhoc + 0.5;
+      for (int i = 0; i < 9; ++i) {
+        /* grad u contracted with e_i e_i - I/3 */
+        const double qgu = (EX[i] * EX[i] - 1.0 / 3.0) * dxux + (EY[i] * EY[i] - 1.0 / 3.0) * dyuy +
+                           EX[i] * EY[i] * (dxuy + dyux);
+        o->f[i * nn + n] = equilibrium(i, rf, ux[n], uy[n]) - 3.0 * s->tau_f * WGT[i] * rf * qgu;
+        o->p[i * nn + n] = equilibrium(i, rp, ux[n], uy[n]);
+        o->g[i * nn + n] = equilibrium(i, theta[n], ux[n], uy[n]) -
+                           tau_th * WGT[i] * (EX[i] * dxth + EY[i] * dyth);
+      }
     }
   }
   init_lag_and_snapshot(o);
@@ -680,6 +715,18 @@ int mclbm_oracle_read_populations(const mo_state* o, double* out,
   memcpy(out, o->f, 9 * o->nn * sizeof(double));
   memcpy(out + 9 * o->nn, o->p, 9 * o->nn * sizeof(double));
   memcpy(out + 18 * o->nn, o->g, 9 * o->nn * sizeof(double));
+  return MO_OK;
+}
+
+/* Test knob: replace the populations (layout of read_populations); the lag
+ * fields and the residual snapshot are taken from the new state. */
+int mclbm_oracle_write_populations(mo_state* o, const double* in,
+                                   size_t n_doubles) {
+  if (!o || !in || n_doubles < 27 * o->nn) return MO_EINVAL;
+  memcpy(o->f, in, 9 * o->nn * sizeof(double));
+  memcpy(o->p, in + 9 * o->nn, 9 * o->nn * sizeof(double));
+  memcpy(o->g, in + 18 * o->nn, 9 * o->nn * sizeof(double));
+  init_lag_and_snapshot(o);
   return MO_OK;
 }
 

@@ -97,9 +97,12 @@ int mclbm_oracle_create(const mo_config* cfg, const double* xi, mo_state** out);
 int mclbm_oracle_step(mo_state* o, int64_t nsteps);
 int64_t mclbm_oracle_time(const mo_state* o);
 int mclbm_oracle_load_fields(mo_state* o, const double* ux, const double* uy,
-                             const double* theta, const double* phi);
+                             const double* theta, const double* phi,
+                             const double* rho_f);
 int mclbm_oracle_read_moments(const mo_state* o, uint32_t mask, double* out,
                               size_t n_doubles);
+int mclbm_oracle_write_populations(mo_state* o, const double* in,
+                                   size_t n_doubles);
 int mclbm_oracle_read_populations(const mo_state* o, double* out,
                                   size_t n_doubles); /* [3][9][ny][nx] */
 int mclbm_oracle_nusselt(const mo_state* o, double* nu_hot, double* nu_cold,

@@ -5,14 +5,17 @@ start computes before it sets equilibrium populations, written as loops over
 nodes in float64.  Shares no code with the product path.
 
 Given fields on an sx x sy cell-centred grid covering the cavity
-(channel-last (u_x, u_y, theta, phi) after the affine map a_c v + b_c):
+(channel-last (u_x, u_y, theta, phi[, rho_f deviation]) after the affine map
+a_c v + b_c):
   * lattice node (x, y) samples the source at the cell-centred coordinate
     s_x = (x + 1/2) sx / nx - 1/2 (likewise y), clamped to [0, sx - 1], by
     bilinear interpolation;
   * phi is clipped at 0 and rescaled so that its sum over the lattice equals
     the particle inventory of the cold start, sum max(phi0 + A xi, 0) (the
     particle mass of a closed cavity is conserved, so the steady state
-    depends on it); a field with no particles left becomes uniform.
+    depends on it); a field with no particles left becomes uniform;
+  * the fluid partial density is 1 - phi0 plus the density deviation less
+    its lattice mean (the fluid mass is conserved as well).
 """
 from __future__ import annotations
 
@@ -29,9 +32,11 @@ def _axis(n_dst: int, n_src: int, i: int):
     return i0, i1, s - i0
 
 
-def resample(fields: np.ndarray, nx: int, ny: int, scale=(1, 1, 1, 1), offset=(0, 0, 0, 0)) -> np.ndarray:
-    """fields: (sy, sx, 4).  Returns (4, ny, nx) float64."""
+def resample(fields: np.ndarray, nx: int, ny: int, scale=None, offset=None) -> np.ndarray:
+    """fields: (sy, sx, nc).  Returns (nc, ny, nx) float64."""
     sy, sx, nc = fields.shape
+    scale = [1.0] * nc if scale is None else list(scale)
+    offset = [0.0] * nc if offset is None else list(offset)
     out = np.zeros((nc, ny, nx))
     for y in range(ny):
         y0, y1, wy = _axis(ny, sy, y)
@@ -56,3 +61,7 @@ def renormalize(phi: np.ndarray, inventory: float) -> np.ndarray:
     if total > 0.0:
         return p * (inventory / total)
     return np.full_like(p, inventory / p.size)
+
+
+def fluid_density(deviation: np.ndarray, phi0: float) -> np.ndarray:
+    return (1.0 - phi0) + (deviation - deviation.mean())

@@ -92,7 +92,7 @@ def lib(load_torch: bool = True):
     L.mclbm_create.argtypes = [CP, D, P, ctypes.c_size_t, P, ctypes.POINTER(P)]
     L.mclbm_set_properties.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_double]
     L.mclbm_reset.argtypes = [P]
-    L.mclbm_load_fields.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32, D]
+    L.mclbm_load_fields.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, D]
     L.mclbm_step.argtypes = [P, ctypes.c_int64]
     L.mclbm_time.argtypes = [P]
     L.mclbm_time.restype = ctypes.c_int64
@@ -252,21 +252,24 @@ class Cavity:
         _check(lib().mclbm_set_properties(self._h, float(Ra), float(phi0), float(dp_m)))
 
     def load_fields(self, fields, affine=None) -> None:
-        """Warm start from fields: a float32 device tensor (sy, sx, 4) holding
-        (u_x, u_y, theta, phi) per cell; affine: None or 8 floats mapping
-        channel c to affine[c] * v + affine[4 + c].  Restarts at t = 0."""
+        """Warm start from fields: a float32 device tensor (sy, sx, nc), nc = 4
+        (u_x, u_y, theta, phi) or 5 (plus the deviation of rho_f~ from
+        1 - phi0); affine: None or 2 nc floats mapping channel c to
+        affine[c] * v + affine[nc + c].  Restarts at t = 0."""
         import torch
-        if fields.dtype != torch.float32 or not fields.is_cuda or fields.dim() != 3 or fields.shape[2] != 4:
-            raise ValueError("fields must be a float32 device tensor of shape (sy, sx, 4)")
+        if (fields.dtype != torch.float32 or not fields.is_cuda or fields.dim() != 3
+                or fields.shape[2] not in (4, 5)):
+            raise ValueError("fields must be a float32 device tensor of shape (sy, sx, 4 or 5)")
         f = fields.contiguous()
+        nc = int(f.shape[2])
         aff = None
         if affine is not None:
             self._affine = np.ascontiguousarray(affine, dtype=np.float64)
-            if self._affine.size != 8:
-                raise ValueError("affine must hold 8 values")
+            if self._affine.size != 2 * nc:
+                raise ValueError(f"affine must hold {2 * nc} values")
             aff = _dptr(self._affine)
         _check(lib().mclbm_load_fields(self._h, ctypes.c_void_p(f.data_ptr()), int(f.shape[1]),
-                                       int(f.shape[0]), aff))
+                                       int(f.shape[0]), nc, aff))
 
     # ---- outputs ------------------------------------------------------------
     @staticmethod

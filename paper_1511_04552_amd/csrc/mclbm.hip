@@ -272,12 +272,12 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__
   }
 }
 
-// Warm start: bilinear samples of channel-last fields (sy x sx x 4) at the
-// lattice nodes, cell-centred on both grids, in FP64.
+// Warm start: bilinear samples of channel-last fields (sy x sx x nc) at
+// the lattice nodes, cell-centred on both grids, in FP64.
 struct FieldMap {
   const float* F;
-  int sx, sy;
-  double a[4], b[4];
+  int sx, sy, nc;
+  double a[5], b[5];
 };
 
 __device__ __forceinline__ void field_axis(int i, int n_dst, int n_src, int& i0, int& i1, double& w) {
@@ -288,73 +288,125 @@ __device__ __forceinline__ void field_axis(int i, int n_dst, int n_src, int& i0,
   w = s - (double)i0;
 }
 
-__device__ __forceinline__ double field_sample(const FieldMap& M, int c, int x0, int x1, double wx, int y0,
-                                               int y1, double wy) {
-  auto v = [&](int yy, int xx) {
-    return M.a[c] * (double)M.F[((long long)yy * M.sx + xx) * 4 + c] + M.b[c];
-  };
-  return (1.0 - wy) * ((1.0 - wx) * v(y0, x0) + wx * v(y0, x1)) +
-         wy * ((1.0 - wx) * v(y1, x0) + wx * v(y1, x1));
+struct FieldPoint {
+  int x0, x1, y0, y1;
+  double wx, wy;
+};
+
+__device__ __forceinline__ FieldPoint field_point(const FieldMap& M, int x, int y, int nx, int ny) {
+  FieldPoint q;
+  field_axis(x, nx, M.sx, q.x0, q.x1, q.wx);
+  field_axis(y, ny, M.sy, q.y0, q.y1, q.wy);
+  return q;
 }
 
-// Per-block sums of the clipped phi samples (slot 0 of 5 per block).
-__global__ __launch_bounds__(256) void k_load_phi_sum(FieldMap M, int nx, int ny,
-                                                      double* __restrict__ partial) {
+__device__ __forceinline__ double field_sample(const FieldMap& M, int c, const FieldPoint& q) {
+  auto v = [&](int yy, int xx) {
+    return M.a[c] * (double)M.F[((long long)yy * M.sx + xx) * M.nc + c] + M.b[c];
+  };
+  return (1.0 - q.wy) * ((1.0 - q.wx) * v(q.y0, q.x0) + q.wx * v(q.y0, q.x1)) +
+         q.wy * ((1.0 - q.wx) * v(q.y1, q.x0) + q.wx * v(q.y1, q.x1));
+}
+
+// Per-block sums of the clipped phi samples (slot 0 of 5 per block) and of
+// the fluid-density deviation samples (slot 1; 0 without that channel).
+__global__ __launch_bounds__(256) void k_load_sums(FieldMap M, int nx, int ny, double* __restrict__ partial) {
   __shared__ double lds[4];
   const long long nn = (long long)nx * ny;
   const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  double s = 0.0;
+  double s = 0.0, r = 0.0;
   if (k < nn) {
-    const int x = (int)(k % nx), y = (int)(k / nx);
-    int x0, x1, y0, y1;
-    double wx, wy;
-    field_axis(x, nx, M.sx, x0, x1, wx);
-    field_axis(y, ny, M.sy, y0, y1, wy);
-    s = fmax(field_sample(M, 3, x0, x1, wx, y0, y1, wy), 0.0);
+    const FieldPoint q = field_point(M, (int)(k % nx), (int)(k / nx), nx, ny);
+    s = fmax(field_sample(M, 3, q), 0.0);
+    if (M.nc > 4) r = field_sample(M, 4, q);
   }
   s = block_sum(s, lds);
+  r = block_sum(r, lds);
   if (threadIdx.x == 0) {
     double* o = partial + 5 * (long long)blockIdx.x;
-    o[0] = s; o[1] = 0.0; o[2] = 0.0; o[3] = 0.0; o[4] = 0.0;
+    o[0] = s; o[1] = r; o[2] = 0.0; o[3] = 0.0; o[4] = 0.0;
   }
 }
 
-// Equilibrium populations (Eqs 26-27) of the sampled fields, with phi
-// rescaled to the cold-start inventory; then the lag field of the first
-// step from the stored state, as at a cold start.
+// Constants of the warm start in FP64.
+struct LoadConst {
+  double inventory, rho_f0, R, tau_f, alpha3, Ck, crc_m1;
+};
+
+// Gradient along one axis of sampled values at lattice nodes: central
+// differences inside, one-sided at the first and last node (so fields
+// without gradients give none at the walls either).
+__device__ __forceinline__ double node_diff(double lo, double mid, double hi, bool first, bool last) {
+  if (first) return hi - mid;
+  if (last) return mid - lo;
+  return 0.5 * (hi - lo);
+}
+
+// Populations of the sampled fields: the equilibria (Eqs 26-27) plus the
+// first-order non-equilibrium parts of the Chapman-Enskog expansion of the
+// BGK lattices (Eqs 18-19), the viscous stress of the fluid lattice,
+// -3 tau_f W_i rho_f (e_i e_i - I/3) : grad u, and the conducted heat flux of
+// the temperature lattice, -tau_theta W_i e_i . grad theta (tau_theta of
+// Eq 24 at the node's phi); the particle lattice takes its equilibrium.
+// phi is rescaled to the cold-start inventory, the fluid partial density
+// is that of the cold start plus the sampled deviation less its lattice
+// mean (so both phases keep their cold-start mass).  Then the lag field of
+// the first step from the stored state, as at a cold start.
 template <class S>
-__global__ __launch_bounds__(256) void k_load_fields(StepParams P, FieldMap M,
+__global__ __launch_bounds__(256) void k_load_fields(StepParams P, FieldMap M, LoadConst K,
                                                      typename S::T* __restrict__ pop,
-                                                     const double* __restrict__ phi_sum,
-                                                     double inventory, double rho_f0, double R,
+                                                     const double* __restrict__ sums,
                                                      float2* __restrict__ d2prev) {
   const long long nn = (long long)P.nx * P.ny;
   const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nn) return;
   const int x = (int)(k % P.nx), y = (int)(k / P.nx);
-  int x0, x1, y0, y1;
-  double wx, wy;
-  field_axis(x, P.nx, M.sx, x0, x1, wx);
-  field_axis(y, P.ny, M.sy, y0, y1, wy);
-  const double ux = field_sample(M, 0, x0, x1, wx, y0, y1, wy);
-  const double uy = field_sample(M, 1, x0, x1, wx, y0, y1, wy);
-  const double th = field_sample(M, 2, x0, x1, wx, y0, y1, wy);
-  const double total = phi_sum[0];
-  double phi = fmax(field_sample(M, 3, x0, x1, wx, y0, y1, wy), 0.0);
-  phi = total > 0.0 ? phi * (inventory / total) : inventory / (double)nn;
-  const double rf = rho_f0, rp = R * phi;
+  const FieldPoint q = field_point(M, x, y, P.nx, P.ny);
+  const double ux = field_sample(M, 0, q);
+  const double uy = field_sample(M, 1, q);
+  const double th = field_sample(M, 2, q);
+  // the u and theta samples at the four neighbours
+  const bool xf = x == 0, xl = x == P.nx - 1, yf = y == 0, yl = y == P.ny - 1;
+  double nb[4][3];  // E, W, N, S
+  const int nxs[4] = {xl ? x : x + 1, xf ? x : x - 1, x, x};
+  const int nys[4] = {y, y, yl ? y : y + 1, yf ? y : y - 1};
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    const FieldPoint r = field_point(M, nxs[d], nys[d], P.nx, P.ny);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) nb[d][c] = field_sample(M, c, r);
+  }
+  const double dxux = node_diff(nb[1][0], ux, nb[0][0], xf, xl);
+  const double dxuy = node_diff(nb[1][1], uy, nb[0][1], xf, xl);
+  const double dxth = node_diff(nb[1][2], th, nb[0][2], xf, xl);
+  const double dyux = node_diff(nb[3][0], ux, nb[2][0], yf, yl);
+  const double dyuy = node_diff(nb[3][1], uy, nb[2][1], yf, yl);
+  const double dyth = node_diff(nb[3][2], th, nb[2][2], yf, yl);
+
+  const double total = sums[0];
+  double phi = fmax(field_sample(M, 3, q), 0.0);
+  phi = total > 0.0 ? phi * (K.inventory / total) : K.inventory / (double)nn;
+  double rf = K.rho_f0;
+  if (M.nc > 4) rf += field_sample(M, 4, q) - sums[1] / (double)nn;
+  const double rp = K.R * phi;
+  const double tau_th = K.alpha3 * (1.0 + K.Ck * pow(phi, 0.764)) / (1.0 + phi * K.crc_m1) + 0.5;
   const double rf_ref = (double)P.rho_f_ref, rp_ref = (double)P.rho_p_ref;
   const double uu = ux * ux + uy * uy;
+  const double shear = dxuy + dyux;
   const long long n = (long long)y * P.px + x;
   float f[9], p[9], g[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
-    const double eu = (double)ex(i) * ux + (double)ey(i) * uy;
+    const double exi = (double)ex(i), eyi = (double)ey(i);
+    const double eu = exi * ux + eyi * uy;
     const double shape = 3.0 * eu + 4.5 * eu * eu - 1.5 * uu;
     const double w = wgt_d(i);
-    S::st(pop + P.plane * i + n, (float)(w * ((rf - rf_ref) + rf * shape)), P.scale[0]);
+    const double qgu = (exi * exi - 1.0 / 3.0) * dxux + (eyi * eyi - 1.0 / 3.0) * dyuy + exi * eyi * shear;
+    const double fneq = -3.0 * K.tau_f * w * rf * qgu;
+    const double gneq = -tau_th * w * (exi * dxth + eyi * dyth);
+    S::st(pop + P.plane * i + n, (float)(w * ((rf - rf_ref) + rf * shape) + fneq), P.scale[0]);
     S::st(pop + P.plane * (9 + i) + n, (float)(w * ((rp - rp_ref) + rp * shape)), P.scale[1]);
-    S::st(pop + P.plane * (18 + i) + n, (float)(w * th * (1.0 + shape)), P.scale[2]);
+    S::st(pop + P.plane * (18 + i) + n, (float)(w * th * (1.0 + shape) + gneq), P.scale[2]);
   }
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
@@ -366,7 +418,6 @@ __global__ __launch_bounds__(256) void k_load_fields(StepParams P, FieldMap M,
   d2prev[n] = make_float2(m.drp * P.invR, m.th);
 }
 
-// Snapshot of the initial state for the first residual call.
 template <bool ODD, class S, class I>
 __global__ __launch_bounds__(256) void k_export(StepParams P,
                                                 const typename S::T* __restrict__ pop,
@@ -863,16 +914,17 @@ int export_pops(mclbm_cavity* c, int q, double* dev_out) {
   });
 }
 
-int enqueue_load_fields(mclbm_cavity* c, const float* F, int sx, int sy, const double* affine) {
+int enqueue_load_fields(mclbm_cavity* c, const float* F, int sx, int sy, int nc, const double* affine) {
   const mclbm_config& cfg = c->cfg;
   const long long nn = (long long)cfg.nx * cfg.ny;
   FieldMap M{};
   M.F = F;
   M.sx = sx;
   M.sy = sy;
-  for (int q = 0; q < 4; ++q) {
+  M.nc = nc;
+  for (int q = 0; q < nc; ++q) {
     M.a[q] = affine ? affine[q] : 1.0;
-    M.b[q] = affine ? affine[4 + q] : 0.0;
+    M.b[q] = affine ? affine[nc + q] : 0.0;
   }
   // particle inventory of the cold start (the initial state of mclbm_create)
   double inventory = 0.0;
@@ -881,9 +933,17 @@ int enqueue_load_fields(mclbm_cavity* c, const float* F, int sx, int sy, const d
     if (!c->xi.empty()) phi += cfg.phi_perturb_amp * c->xi[(size_t)k];
     inventory += phi < 0.0 ? 0.0 : phi;
   }
+  LoadConst K{};
+  K.inventory = inventory;
+  K.rho_f0 = c->D.v[MCLBM_D_RHO_F0];
+  K.R = c->D.v[MCLBM_D_R];
+  K.tau_f = c->D.v[MCLBM_D_TAU_F];
+  K.alpha3 = 3.0 * c->D.v[MCLBM_D_ALPHA_L];
+  K.Ck = c->D.v[MCLBM_D_CK];
+  K.crc_m1 = c->D.v[MCLBM_D_RHOC_RATIO] - 1.0;
   HIP_TRY(hipMemsetAsync(c->d5(), 0, (size_t)6 * c->L.px * sizeof(float), c->stream));
-  k_load_phi_sum<<<c->L.red_blocks, 256, 0, c->stream>>>(M, cfg.nx, cfg.ny, c->part());
-  int rc = launch_check("k_load_phi_sum");
+  k_load_sums<<<c->L.red_blocks, 256, 0, c->stream>>>(M, cfg.nx, cfg.ny, c->part());
+  int rc = launch_check("k_load_sums");
   if (rc) return rc;
   k_sum_partials<<<1, 256, 0, c->stream>>>(c->part(), c->L.red_blocks, c->res());
   rc = launch_check("k_sum_partials");
@@ -892,9 +952,7 @@ int enqueue_load_fields(mclbm_cavity* c, const float* F, int sx, int sy, const d
     using S = typename decltype(k)::S;
     using I = typename decltype(k)::I;
     auto* pop = reinterpret_cast<typename S::T*>(c->pop());
-    k_load_fields<S><<<node_blocks(c), 256, 0, c->stream>>>(c->P, M, pop, c->res(), inventory,
-                                                            c->D.v[MCLBM_D_RHO_F0], c->D.v[MCLBM_D_R],
-                                                            c->d2(1));
+    k_load_fields<S><<<node_blocks(c), 256, 0, c->stream>>>(c->P, M, K, pop, c->res(), c->d2(1));
     int r = launch_check("k_load_fields");
     if (r) return r;
     k_residual<false, S, I><<<c->L.red_blocks, 256, 0, c->stream>>>(
@@ -1001,19 +1059,20 @@ int mclbm_reset(mclbm_cavity* c) {
   return enqueue_init(c);
 }
 
-int mclbm_load_fields(mclbm_cavity* c, const float* dev_fields, int32_t sx, int32_t sy,
+int mclbm_load_fields(mclbm_cavity* c, const float* dev_fields, int32_t sx, int32_t sy, int32_t nc,
                       const double* affine) {
   if (!c || !dev_fields) return fail(MCLBM_EINVAL, "load_fields: NULL cavity or fields");
   // A batch steps all members with one parity; a loaded state is in the
   // even-step layout, so a member may be loaded only at an even batch step.
   if (c->in_batch && (!c->batch_clock || (*c->batch_clock & 1)))
     return fail(MCLBM_ESTATE, "load_fields: the batch is at an odd step; step it once more first");
+  if (nc != 4 && nc != 5) return fail(MCLBM_EINVAL, "load_fields: nc must be 4 or 5");
   if (sx < 1 || sy < 1 || (long long)sx * sy > (1LL << 30))
     return fail(MCLBM_EINVAL, "load_fields: source grid must be at least 1 x 1 and at most 2^30 cells");
   if (affine)
-    for (int q = 0; q < 8; ++q)
+    for (int q = 0; q < 2 * nc; ++q)
       if (!std::isfinite(affine[q])) return fail(MCLBM_EINVAL, "load_fields: affine map not finite");
-  return enqueue_load_fields(c, dev_fields, sx, sy, affine);
+  return enqueue_load_fields(c, dev_fields, sx, sy, nc, affine);
 }
 
 int mclbm_step(mclbm_cavity* c, int64_t nsteps) {

@@ -13,7 +13,7 @@ owns the device buffers.
 Network on an S x S grid, channel-last activations (B, S, S, C):
   h_0 = a W_lift + b_lift                         (a: 5 input features)
   s_l = spectral_l(h_l) + h_l W_l + b_l,  h_l+1 = GELU(s_l) (identity last)
-  out = GELU(h_L P1 + c1) P2 + c2                 (4 output fields)
+  out = GELU(h_L P1 + c1) P2 + c2                 (nout output fields)
 spectral(h) = (1/S^2) sum_{ky in K_y, kx < m} alpha(kx)
               Re{ (H R)(ky, kx) e^{+2 pi i (ky y + kx x)/S} },
 H(ky, kx) = sum_{y,x} h e^{-2 pi i (ky y + kx x)/S}, K_y = {0..m-1} u
@@ -87,10 +87,11 @@ def dft_matrices(S: int, m: int) -> dict:
 class FNO:
     """Fourier neural operator on the GPU (training and inference)."""
 
-    def __init__(self, S=64, C=32, m=12, L=4, Q=64, B=16, seed=0, device="cuda", stream=None):
+    def __init__(self, S=64, C=32, m=12, L=4, Q=64, B=16, seed=0, device="cuda", stream=None, nout=5):
         import torch
         self.torch = torch
         self.S, self.C, self.m, self.L, self.Q, self.B = S, C, m, L, Q, B
+        self.nout = nout
         self.M2 = 2 * m
         self.nq = self.M2 * m
         self.dev = torch.device(device)
@@ -108,8 +109,8 @@ class FNO:
             p[f"b_{l}"] = np.zeros(C)
         p["P1"] = rng.normal(0, 1 / math.sqrt(C), (C, Q))
         p["c1"] = np.zeros(Q)
-        p["P2"] = rng.normal(0, 1 / math.sqrt(Q), (Q, 4))
-        p["c2"] = np.zeros(4)
+        p["P2"] = rng.normal(0, 1 / math.sqrt(Q), (Q, nout))
+        p["c2"] = np.zeros(nout)
         self.params = {k: f32(v) for k, v in p.items()}
         self.grads = {k: torch.zeros_like(v) for k, v in self.params.items()}
         self.adam_m = {k: torch.zeros_like(v) for k, v in self.params.items()}
@@ -130,13 +131,14 @@ class FNO:
         self.Z = z(B, 2, self.nq, C)
         self.W = z(B, 2, S, m, C)
         self.qpre, self.q = z(rows, Q), z(rows, Q)
-        self.out = z(rows, 4)
-        self.dout, self.dq = z(rows, 4), z(rows, Q)
+        self.out = z(rows, self.nout)
+        self.dout, self.dq = z(rows, self.nout), z(rows, Q)
         self.dh, self.dh2 = z(rows, C), z(rows, C)
         self.dX, self.dZ, self.dW, self.dY = z(B, 2, S, m, C), z(B, 2, self.nq, C), z(B, 2, S, m, C), z(B, 2, self.nq, C)
-        ncol = max(C, Q, 4)
+        ncol = max(C, Q, self.nout)
         self.cs_scratch = z(int(lib().mclbm_nn_colsum_scratch(rows, ncol)))
-        self.mse_scratch = torch.zeros(int(lib().mclbm_nn_mse_scratch(rows * 4)), dtype=torch.float64, device=self.dev)
+        self.mse_scratch = torch.zeros(int(lib().mclbm_nn_mse_scratch(rows * self.nout)), dtype=torch.float64,
+                                       device=self.dev)
         self.loss_dev = torch.zeros(1, dtype=torch.float64, device=self.dev)
 
     # ---- spectral layer -------------------------------------------------
@@ -197,7 +199,7 @@ class FNO:
 
     # ---- whole network ----------------------------------------------------
     def forward(self, a):
-        """a: (B, S, S, 5) float32 device tensor.  Returns (B, S, S, 4)."""
+        """a: (B, S, S, 5) float32 device tensor.  Returns (B, S, S, nout)."""
         o, C, Q = self.ops, self.C, self.Q
         rows = self.B * self.S * self.S
         a = a.reshape(rows, 5)
@@ -212,20 +214,22 @@ class FNO:
             o.bias_act(s, P[f"b_{l}"], rows, C, GELU if l < self.L - 1 else IDENT, self.pre[l])
         o.gemm(0, 0, rows, Q, C, 1.0, self.h[self.L], 0, C, 0, 0, P["P1"], 0, Q, 0, 0, 0.0, self.q, 0, Q, 0, 0)
         o.bias_act(self.q, P["c1"], rows, Q, GELU, self.qpre)
-        o.gemm(0, 0, rows, 4, Q, 1.0, self.q, 0, Q, 0, 0, P["P2"], 0, 4, 0, 0, 0.0, self.out, 0, 4, 0, 0)
-        o.bias_act(self.out, P["c2"], rows, 4, IDENT)
-        return self.out.reshape(self.B, self.S, self.S, 4)
+        no = self.nout
+        o.gemm(0, 0, rows, no, Q, 1.0, self.q, 0, Q, 0, 0, P["P2"], 0, no, 0, 0, 0.0, self.out, 0, no, 0, 0)
+        o.bias_act(self.out, P["c2"], rows, no, IDENT)
+        return self.out.reshape(self.B, self.S, self.S, no)
 
     def backward(self, target):
-        """MSE against target (B, S, S, 4): fills self.grads, returns the loss
+        """MSE against target (B, S, S, nout): fills self.grads, returns the loss
         (device tensor, FP64)."""
         o, C, Q = self.ops, self.C, self.Q
         rows = self.B * self.S * self.S
         P, G = self.params, self.grads
-        o.mse(self.out, target.reshape(rows, 4), self.dout, self.mse_scratch, self.loss_dev)
-        o.colsum(self.dout, G["c2"], rows, 4, self.cs_scratch)
-        o.gemm(1, 0, Q, 4, rows, 1.0, self.q, 0, Q, 0, 0, self.dout, 0, 4, 0, 0, 0.0, G["P2"], 0, 4, 0, 0)
-        o.gemm(0, 1, rows, Q, 4, 1.0, self.dout, 0, 4, 0, 0, P["P2"], 0, 4, 0, 0, 0.0, self.dq, 0, Q, 0, 0)
+        no = self.nout
+        o.mse(self.out, target.reshape(rows, no), self.dout, self.mse_scratch, self.loss_dev)
+        o.colsum(self.dout, G["c2"], rows, no, self.cs_scratch)
+        o.gemm(1, 0, Q, no, rows, 1.0, self.q, 0, Q, 0, 0, self.dout, 0, no, 0, 0, 0.0, G["P2"], 0, no, 0, 0)
+        o.gemm(0, 1, rows, Q, no, 1.0, self.dout, 0, no, 0, 0, P["P2"], 0, no, 0, 0, 0.0, self.dq, 0, Q, 0, 0)
         o.act_backward(self.dq, self.qpre, GELU)
         o.colsum(self.dq, G["c1"], rows, Q, self.cs_scratch)
         o.gemm(1, 0, C, Q, rows, 1.0, self.h[self.L], 0, C, 0, 0, self.dq, 0, Q, 0, 0, 0.0, G["P1"], 0, Q, 0, 0)
@@ -262,15 +266,15 @@ class FNO:
 # ==========================================================================
 # Warm start: data, training, prediction, loading
 # ==========================================================================
-TARGETS = ("ux_ns", "uy_ns", "theta", "phi")
+TARGETS = ("rho_f", "phi", "theta", "ux_ns", "uy_ns")
+NCH = 5  # u, v, theta, phi, fluid-density deviation
 
 
 def velocity_scale(cfg: dict) -> float:
     """Convective velocity scale alpha sqrt(Ra) / H in lattice units: it
     makes the steady velocities of the whole Ra range O(0.1 - 0.3)."""
     from . import derive_constants
-    kw = {k: v for k, v in cfg.items() if k != "seed"}
-    d = derive_constants(**kw)
+    d = derive_constants(**_cavity_kw(cfg))
     return d["alpha_L"] * math.sqrt(max(cfg["Ra"], 1.0)) / cfg["nx"]
 
 
@@ -289,16 +293,26 @@ def features(cases, S: int) -> np.ndarray:
     return a
 
 
+def density_scale(cfg: dict) -> float:
+    """Hydrostatic density scale of the buoyancy: the lattice pressure
+    c_s^2 delta rho balances rho G_L theta over the height, so
+    delta rho ~ 3 G_L nx."""
+    from . import derive_constants
+    d = derive_constants(**_cavity_kw(cfg))
+    return max(3.0 * d["G_L"] * cfg["nx"], 1e-12)
+
+
 def nondimensional(moments: dict, cfg: dict) -> np.ndarray:
-    """(ny, nx, 4): u / U, v / U, theta, phi / phi0 - 1 (0 without
-    particles)."""
+    """(ny, nx, 5): u / U, v / U, theta, phi / phi0 - 1 (0 without
+    particles), (rho_f~ - (1 - phi0)) / (3 G_L nx)."""
     U = velocity_scale(cfg)
-    out = np.zeros(moments["theta"].shape + (4,), np.float32)
+    out = np.zeros(moments["theta"].shape + (NCH,), np.float32)
     out[..., 0] = moments["ux_ns"] / U
     out[..., 1] = moments["uy_ns"] / U
     out[..., 2] = moments["theta"]
     if cfg["phi0"] > 1e-4:
         out[..., 3] = moments["phi"] / cfg["phi0"] - 1.0
+    out[..., 4] = (moments["rho_f"] - (1.0 - cfg["phi0"])) / density_scale(cfg)
     return out
 
 
@@ -311,7 +325,7 @@ def generate_dataset(cases, chunk: int = 2000, tol: float = 1e-6, max_steps: int
     """Run the cases (square cavities of one side) to steady state as one
     batch with drop-out: a cavity leaves the batch when the relative change
     of u and theta over ``chunk`` steps is below ``tol``.  Returns the
-    nondimensional fields (n, S, S, 4), the step counts and a converged
+    nondimensional fields (n, S, S, 5), the step counts and a converged
     mask."""
     from . import Batch
     b = Batch([_cavity_kw(c) for c in cases])
@@ -339,10 +353,10 @@ class WarmStart:
 
     def __init__(self, S=64, C=32, m=12, L=4, Q=64, B=16, seed=0, device="cuda"):
         self.S, self.B = S, B
-        self.net = FNO(S=S, C=C, m=m, L=L, Q=Q, B=B, seed=seed, device=device)
+        self.net = FNO(S=S, C=C, m=m, L=L, Q=Q, B=B, seed=seed, device=device, nout=NCH)
         self.torch = self.net.torch
-        self.mean = np.zeros(4)
-        self.std = np.ones(4)
+        self.mean = np.zeros(NCH)
+        self.std = np.ones(NCH)
         self.seed = seed
 
     def fit(self, cases, fields, epochs=100, lr=2e-3, lr_min=1e-4, wd=1e-5, log=None):
@@ -352,8 +366,8 @@ class WarmStart:
         n = len(cases)
         if n < self.B:
             raise ValueError("need at least one batch of training cases")
-        self.mean = fields.reshape(-1, 4).mean(0).astype(np.float64)
-        self.std = np.maximum(fields.reshape(-1, 4).std(0).astype(np.float64), 1e-6)
+        self.mean = fields.reshape(-1, NCH).mean(0).astype(np.float64)
+        self.std = np.maximum(fields.reshape(-1, NCH).std(0).astype(np.float64), 1e-6)
         y = ((fields - self.mean) / self.std).astype(np.float32)
         dev = self.net.dev
         X = torch.tensor(features(cases, self.S), device=dev)
@@ -381,11 +395,11 @@ class WarmStart:
         return hist
 
     def predict(self, cases):
-        """Standardised predictions (n, S, S, 4) as a float32 device tensor."""
+        """Standardised predictions (n, S, S, 5) as a float32 device tensor."""
         torch = self.torch
         n = len(cases)
         X = features(cases, self.S)
-        out = torch.empty((n, self.S, self.S, 4), dtype=torch.float32, device=self.net.dev)
+        out = torch.empty((n, self.S, self.S, NCH), dtype=torch.float32, device=self.net.dev)
         for j in range(0, n, self.B):
             chunk = X[j:j + self.B]
             k = chunk.shape[0]
@@ -397,11 +411,12 @@ class WarmStart:
 
     def affine(self, cfg: dict) -> list:
         """Map of the standardised channels to the fields mclbm_load_fields
-        takes (u, v in lattice units, theta, phi)."""
-        U = velocity_scale(cfg)
+        takes (u, v in lattice units, theta, phi, rho_f~ deviation)."""
+        U, D = velocity_scale(cfg), density_scale(cfg)
         p0 = cfg["phi0"]
         s, m = self.std, self.mean
-        return [U * s[0], U * s[1], s[2], p0 * s[3], U * m[0], U * m[1], m[2], p0 * (1.0 + m[3])]
+        return [U * s[0], U * s[1], s[2], p0 * s[3], D * s[4],
+                U * m[0], U * m[1], m[2], p0 * (1.0 + m[3]), D * m[4]]
 
     def load(self, cavity, cfg: dict, pred) -> None:
         """Warm-start one cavity (or batch member) from its prediction."""

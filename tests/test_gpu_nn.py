@@ -185,7 +185,7 @@ def test_network_forward_and_gradients_match_fp64_oracle(S, C, m, L, Q, B):
     for k in ("b_lift", "c1", "c2") + tuple(f"b_{l}" for l in range(L)):
         net.params[k].copy_(torch.tensor(rng.normal(0, 0.1, net.params[k].shape).astype(np.float32)))
     a = rng.normal(size=(B, S, S, 5)).astype(np.float32)
-    t = rng.normal(size=(B, S, S, 4)).astype(np.float32)
+    t = rng.normal(size=(B, S, S, 5)).astype(np.float32)
     out = net.forward(torch.tensor(a, device=DEV))
     loss = net.backward(torch.tensor(t, device=DEV))
     torch.cuda.synchronize()
@@ -203,7 +203,7 @@ def test_training_reduces_loss():
     """Fitting a fixed smooth target: AdamW steps through the kernels reduce
     the loss by an order of magnitude."""
     S, B = 16, 4
-    net = surrogate.FNO(S=S, C=16, m=4, L=2, Q=32, B=B, seed=3)
+    net = surrogate.FNO(S=S, C=16, m=4, L=2, Q=32, B=B, seed=3, nout=4)
     rng = np.random.default_rng(5)
     xs = (np.arange(S) + 0.5) / S
     a = np.zeros((B, S, S, 5), np.float32)

@@ -18,14 +18,17 @@ from paper_1511_04552_amd import inputs  # noqa: E402
 DEV = torch.device("cuda")
 
 
-def _fields(seed, sx, sy):
+def _fields(seed, sx, sy, nc=4):
     """Smooth synthetic fields in standardised units (u, v ~ 1, theta in
-    [-1/2, 1/2], phi deviation ~ 1) on an sx x sy grid."""
+    [-1/2, 1/2], phi deviation ~ 1, density deviation ~ 1) on an sx x sy
+    grid."""
     rng = np.random.default_rng(seed)
     xs = (np.arange(sx) + 0.5) / sx
     ys = (np.arange(sy) + 0.5) / sy
     X, Y = np.meshgrid(xs, ys)
-    F = np.zeros((sy, sx, 4), np.float32)
+    F = np.zeros((sy, sx, nc), np.float32)
+    if nc > 4:
+        F[..., 4] = (0.5 - Y) + 0.2 * np.cos(np.pi * X) + 0.3
     F[..., 0] = np.sin(np.pi * X) * np.sin(2 * np.pi * Y) * rng.uniform(0.5, 1.5)
     F[..., 1] = -np.sin(2 * np.pi * X) * np.sin(np.pi * Y) * rng.uniform(0.5, 1.5)
     F[..., 2] = 0.5 - X + 0.1 * np.sin(np.pi * Y)
@@ -40,10 +43,12 @@ def _case(cfg, xi, F, affine, steps):
     g.load_fields(torch.tensor(F, device=DEV), affine=affine)
     assert g.time == 0
     o = oracle.Oracle(xi=xi, **cfg)
-    fx = warmstart.resample(F, nx, ny, scale=affine[:4], offset=affine[4:])
+    nc = F.shape[2]
+    fx = warmstart.resample(F, nx, ny, scale=affine[:nc], offset=affine[nc:])
     inv = warmstart.cold_inventory(cfg["phi0"], o.cfg.phi_perturb_amp, xi, nx * ny)
     phi = warmstart.renormalize(fx[3], inv)
-    o.load_fields(fx[0], fx[1], fx[2], phi)
+    rho_f = warmstart.fluid_density(fx[4], cfg["phi0"]) if F.shape[2] > 4 else None
+    o.load_fields(fx[0], fx[1], fx[2], phi, rho_f)
     return g, o
 
 
@@ -65,6 +70,8 @@ NO_ROT = mc.F_ALL & ~mc.F_MAGROT
     (dict(nx=70, ny=45, Ra=3e4, phi0=0.01, dp_nm=100.0), (70, 45)),
     (dict(nx=37, ny=29, Ra=1e4, phi0=0.02, dp_nm=40.0), (13, 9)),
     (dict(nx=16, ny=16, Ra=1e3, phi0=0.04, dp_nm=30.0), (1, 1)),
+    (dict(nx=41, ny=33, Ra=1e5, phi0=0.03, dp_nm=50.0, tau_f=-1.0, force_mask=NO_ROT), (16, 12, 5)),
+    (dict(nx=64, ny=64, Ra=1e5, phi0=0.03, dp_nm=50.0, tau_f=-1.0), (64, 64, 5)),
 ])
 def test_load_fields_matches_oracle(cfg, src):
     """The loaded state matches at t = 0 and the steps that follow stay
@@ -73,11 +80,14 @@ def test_load_fields_matches_oracle(cfg, src):
     that direction is set by rounding on either side, so with that term on
     the first steps are compared only after the drag has relaxed the slip
     (a few steps); step-by-step parity from step 1 is checked without it."""
-    sx, sy = src
+    sx, sy = src[:2]
+    nc = src[2] if len(src) > 2 else 4
     xi = inputs.phi_perturbation(31, cfg["nx"], cfg["ny"])
-    F = _fields(sx * 100 + sy, sx, sy)
+    F = _fields(sx * 100 + sy, sx, sy, nc)
     U = 0.02
     affine = [U, U, 1.0, 0.005, 0.0, 0.0, 0.0, cfg["phi0"]]
+    if nc > 4:
+        affine = affine[:4] + [1e-4] + affine[4:] + [0.0]
     g, o = _case(cfg, xi, F, affine, 0)
     _compare(g, o, tol=1e-6)
     # the lag field and the residual snapshot are those of the loaded state
@@ -94,7 +104,7 @@ def test_load_fields_matches_oracle(cfg, src):
     assert abs(nu_g[0] - nu_o[0]) <= 1e-4 * max(abs(nu_o[0]), 1.0)
 
 
-def test_particle_inventory_equals_cold_start():
+def test_particle_and_fluid_inventories_equal_cold_start():
     cfg = dict(nx=48, ny=40, Ra=1e4, phi0=0.02, dp_nm=60.0, phi_perturb_amp=0.01)
     xi = inputs.phi_perturbation(8, 48, 40)
     cold = mc.Cavity(xi=xi, **cfg)
@@ -105,6 +115,11 @@ def test_particle_inventory_equals_cold_start():
     pc, pw = cold.moments("phi")["phi"].sum(), warm.moments("phi")["phi"].sum()
     assert abs(pw - pc) <= 1e-6 * pc
     assert abs(pc - np.maximum(0.02 + 0.01 * xi, 0).sum()) <= 1e-6 * pc
+    F5 = _fields(4, 12, 10, nc=5)
+    warm.load_fields(torch.tensor(F5, device=DEV), affine=[0.01, 0.01, 1, 0.01, 0.05, 0, 0, 0, 0, 0.3])
+    rc, rw = cold.moments("rho_f")["rho_f"], warm.moments("rho_f")["rho_f"]
+    assert abs(rw.sum() - rc.sum()) <= 1e-6 * rc.sum()
+    assert rw.std() > 1e-3
 
 
 def test_load_fields_rejects_bad_arguments():
@@ -113,13 +128,14 @@ def test_load_fields_rejects_bad_arguments():
     F = torch.zeros(4, 4, 4, device=DEV)
     import ctypes
     p = ctypes.c_void_p(F.data_ptr())
-    assert L.mclbm_load_fields(c._h, p, 0, 4, None) == mc.EINVAL
-    assert L.mclbm_load_fields(c._h, None, 4, 4, None) == mc.EINVAL
+    assert L.mclbm_load_fields(c._h, p, 0, 4, 4, None) == mc.EINVAL
+    assert L.mclbm_load_fields(c._h, None, 4, 4, 4, None) == mc.EINVAL
+    assert L.mclbm_load_fields(c._h, p, 4, 4, 3, None) == mc.EINVAL
     bad = np.array([1, 1, 1, np.nan, 0, 0, 0, 0], dtype=np.float64)
-    assert L.mclbm_load_fields(c._h, p, 4, 4, bad.ctypes.data_as(ctypes.POINTER(ctypes.c_double))) == mc.EINVAL
+    assert L.mclbm_load_fields(c._h, p, 4, 4, 4, bad.ctypes.data_as(ctypes.POINTER(ctypes.c_double))) == mc.EINVAL
     b = mc.Batch([dict(nx=16, ny=16, Ra=1e4)] * 2)
     b.step(1)
-    assert L.mclbm_load_fields(b.members[0]._h, p, 4, 4, None) == mc.ESTATE
+    assert L.mclbm_load_fields(b.members[0]._h, p, 4, 4, 4, None) == mc.ESTATE
     with pytest.raises(ValueError):
         c.load_fields(torch.zeros(4, 4, 3, device=DEV))
 

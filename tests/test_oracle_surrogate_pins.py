@@ -90,6 +90,58 @@ def test_load_fields_moments_are_the_fields():
         np.testing.assert_allclose(m[k], ux, rtol=1e-12, atol=1e-18)
     for k in ("uy_f", "uy_p", "uy_ns"):
         np.testing.assert_allclose(m[k], uy, rtol=1e-12, atol=1e-18)
+    rf = 0.97 + 1e-3 * rng.normal(size=(ny, nx))
+    o.load_fields(ux, uy, th, phi, rf)
+    np.testing.assert_allclose(o.moments("rho_f")["rho_f"], rf, rtol=1e-14)
+
+
+def test_load_fields_non_equilibrium_parts_are_stress_and_heat_flux():
+    """Chapman-Enskog closed forms: with u_x = a y and theta = b x, the
+    second moment of f - f_eq at interior nodes is -(tau_f rho_f / 3) a in
+    xy (zero on the diagonal), and the first moment of g - g_eq is
+    -(tau_theta / 3) b along x, with tau_theta = 3 alpha (k/k_f) / (rho c_p
+    ratio) + 1/2 (Eqs 10, 8, 24)."""
+    nx, ny = 12, 10
+    a, b = 2e-4, 3e-3
+    Y, X = np.mgrid[0:ny, 0:nx].astype(float)
+    ux, uy = a * Y, np.zeros((ny, nx))
+    th = b * X - 0.01
+    phi = np.full((ny, nx), 0.02)
+    o = oracle.Oracle(nx=nx, ny=ny, Ra=1e5, phi0=0.02, dp_nm=40.0)
+    o.load_fields(ux, uy, th, phi)
+    d = o.derived()
+    e, _ = _d2q9_ew()
+    pops = o.populations().reshape(3, 9, ny, nx)
+    rf = d["rho_f0"]
+    k_ratio = 1.0 + d["Ck"] * 0.02 ** 0.764
+    rc_ratio = 1.0 + 0.02 * (d["rhoc_ratio"] - 1.0)
+    tau_th = 3.0 * d["alpha_L"] * k_ratio / rc_ratio + 0.5
+    for (y, x) in ((3, 4), (5, 7), (8, 1 + 1)):
+        feq = oracle.equilibrium(rf, ux[y, x], uy[y, x])
+        fneq = pops[0, :, y, x] - feq
+        Pi = np.einsum("i,ij,ik->jk", fneq, e, e)
+        np.testing.assert_allclose(Pi[0, 1], -d["tau_f"] * rf * a / 3.0, rtol=1e-9)
+        assert abs(Pi[0, 0]) < 1e-12 * abs(Pi[0, 1]) + 1e-20 and abs(Pi[1, 1]) < 1e-12 * abs(Pi[0, 1]) + 1e-20
+        geq = oracle.equilibrium(th[y, x], ux[y, x], uy[y, x])
+        gneq = pops[2, :, y, x] - geq
+        q = gneq @ e
+        np.testing.assert_allclose(q[0], -tau_th * b / 3.0, rtol=1e-9)
+        assert abs(q[1]) < 1e-15
+        assert abs(gneq.sum()) < 1e-15 and abs(fneq.sum()) < 1e-15
+        np.testing.assert_allclose(pops[1, :, y, x], oracle.equilibrium(d["R"] * 0.02, ux[y, x], uy[y, x]), rtol=1e-14)
+
+
+def test_fluid_density_conserves_the_fluid_mass():
+    dev = np.array([[0.1, -0.3], [0.5, 0.2]])
+    r = warmstart.fluid_density(dev, 0.02)
+    assert abs(r.sum() - 4 * 0.98) < 1e-15
+    np.testing.assert_allclose(np.diff(r.ravel()), np.diff(dev.ravel()), atol=1e-15)
+
+
+def _d2q9_ew():
+    import os
+    rows = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "d2q9.txt"))
+    return rows[:, 1:3], rows[:, 3] / rows[:, 4]
 
 
 # ------------------------------------------------------- network oracle ---
