@@ -359,15 +359,19 @@ class WarmStart:
         self.std = np.ones(NCH)
         self.seed = seed
 
-    def fit(self, cases, fields, epochs=100, lr=2e-3, lr_min=1e-4, wd=1e-5, log=None):
+    def fit(self, cases, fields, epochs=100, lr=2e-3, lr_min=1e-4, wd=1e-5, weights=None, log=None):
         """AdamW on the mean-squared error of the standardised fields, with a
-        cosine learning-rate schedule.  Returns the loss per epoch."""
+        cosine learning-rate schedule.  ``weights`` (one per channel) scale
+        the standardised targets, i.e. weight the squared error of channel c
+        by weights[c]^2: the temperature field decays slowest after a warm
+        start, so its accuracy matters most.  Returns the loss per epoch."""
         torch = self.torch
         n = len(cases)
         if n < self.B:
             raise ValueError("need at least one batch of training cases")
+        w = np.ones(NCH) if weights is None else np.asarray(weights, dtype=np.float64)
         self.mean = fields.reshape(-1, NCH).mean(0).astype(np.float64)
-        self.std = np.maximum(fields.reshape(-1, NCH).std(0).astype(np.float64), 1e-6)
+        self.std = np.maximum(fields.reshape(-1, NCH).std(0).astype(np.float64), 1e-6) / w
         y = ((fields - self.mean) / self.std).astype(np.float32)
         dev = self.net.dev
         X = torch.tensor(features(cases, self.S), device=dev)
@@ -432,12 +436,15 @@ class WarmStart:
         self.mean, self.std = np.asarray(st["mean"]), np.asarray(st["std"])
 
 
-def time_to_steady(cases, warm: WarmStart | None = None, chunk: int = 1000, tol: float = 1e-6,
-                   max_steps: int = 4_000_000):
-    """Steps until the relative change of u and theta over ``chunk`` steps
-    falls below ``tol`` for each case (cold start, or warm start from
-    ``warm``), run as one batch with drop-out.  Returns (steps, Nu at the
-    hot wall, converged mask, seconds spent on prediction and loading)."""
+def run_to_steady(cases, warm: WarmStart | None = None, chunk: int = 500, tol: float = 1e-6,
+                  max_steps: int = 4_000_000):
+    """Run the cases as one batch from a cold start, or from the warm start
+    ``warm``, each to its own criterion: the relative change of u and theta
+    over ``chunk`` steps below ``tol`` (then the cavity drops out).  Records
+    the hot-wall Nu of every cavity after every chunk.  Returns a dict:
+    steps (at convergence, 0 if not reached), converged, nu (final),
+    times, nu_hist (len(times) x n), t_load (seconds of prediction and
+    loading), fields (final nondimensional fields)."""
     import time
     from . import Batch
     torch = warm.torch if warm is not None else __import__("torch")
@@ -454,6 +461,7 @@ def time_to_steady(cases, warm: WarmStart | None = None, chunk: int = 1000, tol:
         t_load = time.perf_counter() - t0
     status = np.zeros(n, np.int32)
     steps = np.zeros(n, np.int64)
+    times, hist = [], []
     b.residual(tol=0.0)
     t = 0
     while t < max_steps and (status == 0).any():
@@ -463,6 +471,23 @@ def time_to_steady(cases, warm: WarmStart | None = None, chunk: int = 1000, tol:
         newly = (status == 0) & (st != 0)
         steps[newly] = t
         status[newly] = st[newly]
-    nu = b.nusselt()[:, 0].copy()
+        times.append(t)
+        hist.append(b.nusselt()[:, 0].copy())
     fields = np.stack([nondimensional(b.members[k].moments(TARGETS), cases[k]) for k in range(n)])
-    return steps, nu, status == 1, t_load, fields
+    return dict(steps=steps, converged=status == 1, nu=hist[-1] if hist else b.nusselt()[:, 0],
+                times=np.array(times), nu_hist=np.array(hist), t_load=t_load, fields=fields)
+
+
+def settle_steps(times, nu_hist, nu_ref, rtol: float = 1e-3) -> np.ndarray:
+    """Per cavity, the first recorded time from which on |Nu - Nu_ref| stays
+    below rtol |Nu_ref| (the run's end if it never settles)."""
+    out = np.zeros(nu_hist.shape[1], np.int64)
+    for k in range(nu_hist.shape[1]):
+        bad = np.nonzero(np.abs(nu_hist[:, k] - nu_ref[k]) > rtol * abs(nu_ref[k]))[0]
+        if bad.size == 0:
+            out[k] = times[0]
+        elif bad[-1] + 1 < len(times):
+            out[k] = times[bad[-1] + 1]
+        else:
+            out[k] = times[-1]
+    return out
