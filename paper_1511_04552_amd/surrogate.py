@@ -136,10 +136,30 @@ class FNO:
         self.dh, self.dh2 = z(rows, C), z(rows, C)
         self.dX, self.dZ, self.dW, self.dY = z(B, 2, S, m, C), z(B, 2, self.nq, C), z(B, 2, S, m, C), z(B, 2, self.nq, C)
         ncol = max(C, Q, self.nout)
-        self.cs_scratch = z(int(lib().mclbm_nn_colsum_scratch(rows, ncol)))
+        # K split of the weight gradients: slices of at least 256 rows
+        self.ksplit = 1
+        while self.ksplit < 256 and rows % (2 * self.ksplit) == 0 and rows // (2 * self.ksplit) >= 256:
+            self.ksplit *= 2
+        wmax = max(C * C, C * Q, Q * self.nout, 5 * C)
+        self.ws = z(self.ksplit * wmax)
+        self.cs_scratch = z(max(int(lib().mclbm_nn_colsum_scratch(rows, ncol)),
+                                int(lib().mclbm_nn_colsum_scratch(self.ksplit, wmax))))
         self.mse_scratch = torch.zeros(int(lib().mclbm_nn_mse_scratch(rows * self.nout)), dtype=torch.float64,
                                        device=self.dev)
         self.loss_dev = torch.zeros(1, dtype=torch.float64, device=self.dev)
+
+    # ---- weight gradients: G = op(X)^T Y over all rows, split over K ----
+    def _wgrad(self, X, ldx, Y, ldy, M, N, G):
+        """G (M x N) = X^T Y for X (rows x M, row stride ldx) and Y (rows x N):
+        the rows (the long K dimension) are split into ``ksplit`` slices
+        computed as one batched GEMM into a workspace, whose slices are then
+        summed in a fixed order by the column-sum kernel."""
+        rows = self.B * self.S * self.S
+        ks = self.ksplit
+        o = self.ops
+        o.gemm(1, 0, M, N, rows // ks, 1.0, X, 0, ldx, (rows // ks) * ldx, 0, Y, 0, ldy, (rows // ks) * ldy, 0,
+               0.0, self.ws, 0, N, M * N, 0, ks, 1)
+        o.colsum(self.ws, G, ks, M * N, self.cs_scratch)
 
     # ---- spectral layer -------------------------------------------------
     def _spectral_forward(self, h, l, out):
@@ -228,25 +248,25 @@ class FNO:
         no = self.nout
         o.mse(self.out, target.reshape(rows, no), self.dout, self.mse_scratch, self.loss_dev)
         o.colsum(self.dout, G["c2"], rows, no, self.cs_scratch)
-        o.gemm(1, 0, Q, no, rows, 1.0, self.q, 0, Q, 0, 0, self.dout, 0, no, 0, 0, 0.0, G["P2"], 0, no, 0, 0)
+        self._wgrad(self.q, Q, self.dout, no, Q, no, G["P2"])
         o.gemm(0, 1, rows, Q, no, 1.0, self.dout, 0, no, 0, 0, P["P2"], 0, no, 0, 0, 0.0, self.dq, 0, Q, 0, 0)
         o.act_backward(self.dq, self.qpre, GELU)
         o.colsum(self.dq, G["c1"], rows, Q, self.cs_scratch)
-        o.gemm(1, 0, C, Q, rows, 1.0, self.h[self.L], 0, C, 0, 0, self.dq, 0, Q, 0, 0, 0.0, G["P1"], 0, Q, 0, 0)
+        self._wgrad(self.h[self.L], C, self.dq, Q, C, Q, G["P1"])
         dh = self.dh
         o.gemm(0, 1, rows, C, Q, 1.0, self.dq, 0, Q, 0, 0, P["P1"], 0, Q, 0, 0, 0.0, dh, 0, C, 0, 0)
         for l in reversed(range(self.L)):
             if l < self.L - 1:
                 o.act_backward(dh, self.pre[l], GELU)
             o.colsum(dh, G[f"b_{l}"], rows, C, self.cs_scratch)
-            o.gemm(1, 0, C, C, rows, 1.0, self.h[l], 0, C, 0, 0, dh, 0, C, 0, 0, 0.0, G[f"W_{l}"], 0, C, 0, 0)
+            self._wgrad(self.h[l], C, dh, C, C, C, G[f"W_{l}"])
             dprev = self.dh2
             o.gemm(0, 1, rows, C, C, 1.0, dh, 0, C, 0, 0, P[f"W_{l}"], 0, C, 0, 0, 0.0, dprev, 0, C, 0, 0)
             self._spectral_backward(l, dh, dprev)
             self.dh, self.dh2 = dprev, dh
             dh = self.dh
         o.colsum(dh, G["b_lift"], rows, C, self.cs_scratch)
-        o.gemm(1, 0, 5, C, rows, 1.0, self._a, 0, 5, 0, 0, dh, 0, C, 0, 0, 0.0, G["W_lift"], 0, C, 0, 0)
+        self._wgrad(self._a, 5, dh, C, 5, C, G["W_lift"])
         return self.loss_dev
 
     def step(self, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, wd=1e-4):
@@ -341,7 +361,7 @@ def generate_dataset(cases, chunk: int = 2000, tol: float = 1e-6, max_steps: int
         newly = (status == 0) & (st != 0)
         steps[newly] = t
         status[newly] = st[newly]
-        if log:
+        if log and (t // chunk) % 50 == 0:
             log(f"  t={t} converged {(status == 1).sum()}/{n} diverged {(status == 2).sum()}")
     fields = np.stack([nondimensional(b.members[k].moments(TARGETS), cases[k]) for k in range(n)])
     return fields, steps, status == 1
@@ -437,7 +457,7 @@ class WarmStart:
 
 
 def run_to_steady(cases, warm: WarmStart | None = None, chunk: int = 500, tol: float = 1e-6,
-                  max_steps: int = 4_000_000):
+                  max_steps: int = 4_000_000, log=None):
     """Run the cases as one batch from a cold start, or from the warm start
     ``warm``, each to its own criterion: the relative change of u and theta
     over ``chunk`` steps below ``tol`` (then the cavity drops out).  Records
@@ -473,6 +493,8 @@ def run_to_steady(cases, warm: WarmStart | None = None, chunk: int = 500, tol: f
         status[newly] = st[newly]
         times.append(t)
         hist.append(b.nusselt()[:, 0].copy())
+        if log and (t // chunk) % 200 == 0:
+            log(f"  t={t} converged {(status == 1).sum()}/{n}")
     fields = np.stack([nondimensional(b.members[k].moments(TARGETS), cases[k]) for k in range(n)])
     return dict(steps=steps, converged=status == 1, nu=hist[-1] if hist else b.nusselt()[:, 0],
                 times=np.array(times), nu_hist=np.array(hist), t_load=t_load, fields=fields)
@@ -491,3 +513,89 @@ def settle_steps(times, nu_hist, nu_ref, rtol: float = 1e-3) -> np.ndarray:
         else:
             out[k] = times[-1]
     return out
+
+
+def main(argv=None) -> int:
+    """Train a warm-start surrogate on solver steady states and compare the
+    time to a steady hot-wall Nu (within 1e-3) from cold and warm starts on
+    held-out cavities, possibly at a finer grid than the training one."""
+    import argparse
+    import json
+    import time
+    from . import inputs
+    ap = argparse.ArgumentParser(description=main.__doc__)
+    ap.add_argument("--train-side", type=int, default=64)
+    ap.add_argument("--train-count", type=int, default=256)
+    ap.add_argument("--eval-side", type=int, default=128)
+    ap.add_argument("--eval-count", type=int, default=16)
+    ap.add_argument("--epochs", type=int, default=200)
+    ap.add_argument("--channels", type=int, default=32)
+    ap.add_argument("--modes", type=int, default=12)
+    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--lr", type=float, default=3e-3)
+    ap.add_argument("--theta-weight", type=float, default=4.0)
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--seed", type=int, default=5)
+    ap.add_argument("--out", default=None)
+    a = ap.parse_args(argv)
+    import torch
+    log = lambda s: print(s, flush=True)
+
+    def cases(seed, n, side):
+        return [dict(c, tau_f=-1.0) for c in inputs.sweep_parameters(seed, n, sides=(side,))]
+
+    S = a.train_side
+    train = cases(a.seed * 1000 + 1, a.train_count, S)
+    t0 = time.perf_counter()
+    F, steps, ok = generate_dataset(train, chunk=2000, tol=a.tol, max_steps=2_000_000, log=log)
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    log(f"training data: {ok.sum()}/{len(train)} cavities of {S}^2 converged in {t_gen:.1f} s")
+    ws = WarmStart(S=S, C=a.channels, m=min(a.modes, S // 4), L=4, Q=64, B=a.batch, seed=a.seed)
+    t0 = time.perf_counter()
+    hist = ws.fit([c for c, o in zip(train, ok) if o], F[ok], epochs=a.epochs, lr=a.lr,
+                  weights=(1, 1, a.theta_weight, 1, 1),
+                  log=lambda s: log(s) if s.strip().startswith("epoch") else None)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    log(f"trained {a.epochs} epochs in {t_train:.1f} s, loss {hist[0]:.3e} -> {hist[-1]:.3e}")
+    test = cases(a.seed * 1000 + 2, a.eval_count, a.eval_side)
+    t0 = time.perf_counter()
+    cold = run_to_steady(test, None, chunk=500, tol=a.tol, max_steps=4_000_000, log=log)
+    t_cold = time.perf_counter() - t0
+    log(f"cold start: {cold['converged'].sum()}/{len(test)} converged, {t_cold:.1f} s")
+    t0 = time.perf_counter()
+    warm = run_to_steady(test, ws, chunk=500, tol=a.tol, max_steps=4_000_000, log=log)
+    t_warm = time.perf_counter() - t0
+    log(f"warm start: {warm['converged'].sum()}/{len(test)} converged, {t_warm:.1f} s "
+        f"(prediction and loading {warm['t_load'] * 1e3:.1f} ms)")
+    done = cold["converged"] & warm["converged"]
+    sc = settle_steps(cold["times"], cold["nu_hist"], cold["nu"])
+    sw = settle_steps(warm["times"], warm["nu_hist"], cold["nu"])
+    dnu = np.abs(warm["nu"] - cold["nu"]) / np.abs(cold["nu"])
+    rep = {
+        "train": {"side": S, "count": int(ok.sum()), "epochs": a.epochs, "channels": a.channels,
+                  "modes": min(a.modes, S // 4), "seconds_data": t_gen, "seconds_train": t_train,
+                  "loss_first": hist[0], "loss_last": hist[-1]},
+        "eval": {"side": a.eval_side, "count": len(test), "tol": a.tol,
+                 "cold_settle_steps": sc.tolist(), "warm_settle_steps": sw.tolist(),
+                 "settle_ratio_total": float(sc.sum() / max(sw.sum(), 1)),
+                 "settle_ratio_median": float(np.median(sc / np.maximum(sw, 1))),
+                 "cold_converge_steps": cold["steps"].tolist(), "warm_converge_steps": warm["steps"].tolist(),
+                 "converged_both": int(done.sum()),
+                 "max_final_nu_rel_diff": float(dnu[done].max()) if done.any() else None,
+                 "seconds_cold": t_cold, "seconds_warm": t_warm, "seconds_load": warm["t_load"]},
+    }
+    if a.eval_side == S:
+        pred = ws.predict(test).cpu().numpy() * ws.std + ws.mean
+        err = np.sqrt(((pred - cold["fields"]) ** 2).reshape(-1, NCH).mean(0)) / cold["fields"].reshape(-1, NCH).std(0)
+        rep["eval"]["rel_rms_error"] = dict(zip(("u", "v", "theta", "phi", "rho_f"), err.tolist()))
+    log(json.dumps(rep["eval"]))
+    if a.out:
+        with open(a.out, "w") as fh:
+            json.dump(rep, fh, indent=1)
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())
