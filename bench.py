@@ -36,6 +36,8 @@ def parse():
                     help="HBM bytes per launch measured by rocprofv3 counters")
     ap.add_argument("--batch", type=int, default=256,
                     help="cavities in the batched-sweep measurement (0 skips it)")
+    ap.add_argument("--no-warm-start", action="store_true",
+                    help="skip the time-to-steady comparison of cold and learned warm starts")
     ap.add_argument("--no-secondary", action="store_true",
                     help="skip the 2048^2 (larger than the last-level cache) measurement")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -139,6 +141,50 @@ def batch_measure(torch, mc, inputs, n, steps=64):
     return out
 
 
+def warm_start_measure():
+    """Time to a steady hot-wall Nu (within 1e-3 of Nu_inf), cold start vs
+    the learned warm start: a surrogate trained on 128 steady states of 32^2
+    cavities predicts 16 held-out 64^2 cavities (up-sampled); both starts run
+    one fixed horizon as a batch, Nu_inf is the cold start's final Nu."""
+    import numpy as np
+    import torch
+    from paper_1511_04552_amd import inputs, surrogate as sg
+
+    def cases(seed, n, side):
+        return [dict(c, tau_f=-1.0) for c in inputs.sweep_parameters(seed, n, sides=(side,))]
+
+    t0 = time.perf_counter()
+    train = cases(9001, 128, 32)
+    F, _, ok = sg.generate_dataset(train, chunk=2000, tol=1e-6, max_steps=800_000)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    print(f"# warm start: {int(ok.sum())} training states in {t_data:.1f} s", file=sys.stderr, flush=True)
+    ws = sg.WarmStart(S=32, C=32, m=8, L=4, Q=64, B=16, seed=0)
+    t0 = time.perf_counter()
+    ws.fit([c for c, o in zip(train, ok) if o], F[ok], epochs=150, lr=3e-3, weights=(1, 1, 4, 1, 1))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    test = cases(9002, 16, 64)
+    cold = sg.run_to_steady(test, None, chunk=500, tol=1e-6, max_steps=1_000_000, drop=False)
+    print(f"# warm start: cold runs {cold['seconds']:.1f} s", file=sys.stderr, flush=True)
+    warm = sg.run_to_steady(test, ws, chunk=500, tol=1e-6, max_steps=1_000_000, drop=False)
+    sc = sg.settle_steps(cold["times"], cold["nu_hist"], cold["nu"])
+    sw = sg.settle_steps(warm["times"], warm["nu_hist"], cold["nu"])
+    both = cold["converged"] & warm["converged"]
+    per_step = cold["seconds"] / cold["times"][-1]
+    return {"workload": "16 held-out 64^2 cavities (Ra 1e3-1e6, phi0 0-0.05, d_p 10-100 nm) warm-started "
+                        "from an FNO trained on 128 steady states of 32^2",
+            "criterion": "steps until Nu stays within 1e-3 of Nu_inf", "horizon_steps": 1_000_000,
+            "cold_settle_steps_sum": int(sc.sum()), "warm_settle_steps_sum": int(sw.sum()),
+            "settle_ratio": round(float(sc.sum() / max(sw.sum(), 1)), 2),
+            "settle_ratio_median": round(float(np.median(sc / np.maximum(sw, 1))), 2),
+            "own_criterion_ratio": round(float(cold["steps"][both].sum() / max(warm["steps"][both].sum(), 1)), 2),
+            "final_nu_rel_diff_max": float(np.max(np.abs(warm["nu"] - cold["nu"]) / np.abs(cold["nu"]))),
+            "seconds_to_settle_cold": round(float(sc.max() * per_step), 3),
+            "seconds_to_settle_warm": round(float(sw.max() * per_step + warm["t_load"]), 3),
+            "seconds_training_data": round(t_data, 1), "seconds_training": round(t_train, 1)}
+
+
 def cpu_baseline(w, xi, seconds):
     """The FP64 oracle as it stands, on this host's cores, on a bounded
     sample of the same workload (same cavity, first steps)."""
@@ -231,6 +277,9 @@ def main():
     batched = None
     if a.batch > 0 and not a.no_secondary:
         batched = batch_measure(torch, mc, inputs, a.batch)
+    warm = None
+    if not a.no_warm_start and not a.no_secondary:
+        warm = warm_start_measure()
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
             "kernel": "k_step (even and odd A-A parities)",
@@ -248,6 +297,7 @@ def main():
         "nu_hot": nu_hot,
         "larger_than_llc": secondary,
         "batched_sweep": batched,
+        "time_to_steady": warm,
     }
     if not a.no_cpu_baseline:
         print("# cpu baseline (FP64 oracle) ...", file=sys.stderr, flush=True)
