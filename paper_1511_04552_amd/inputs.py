@@ -68,3 +68,27 @@ def sweep_parameters(seed: int, count: int,
                         phi0=float(0.05 * u[k, 2]), dp_nm=float(10.0 + 90.0 * u[k, 3]),
                         seed=seed * 1000003 + k))
     return out
+
+
+# Section 3.e: aspect ratio = height / width of the cavity (ny / nx); Ra and
+# Nu are based on the width between the isothermal walls.
+def aspect_ratio_configs(base: dict, width: int, ratios=(0.5, 1.0, 2.0)) -> list:
+    """One cavity per aspect ratio: width nx = ``width``, height ny =
+    round(ratio * width), the rest of ``base`` unchanged."""
+    return [dict(base, nx=int(width), ny=max(4, int(round(r * width)))) for r in ratios]
+
+
+# Slip-force ablation (Sections 3.a-3.b): every force on, each slip force
+# off in turn, and all slip forces off (buoyancy only).  Force bits as in
+# include/mclbm.h.
+FORCE_BITS = {"drag": 1, "brownian": 2, "thermophoresis": 4, "saffman": 8, "magnus_rotation": 16, "gravity": 32}
+
+
+def ablation_configs(base: dict) -> list:
+    """(label, config) pairs of the ablation study."""
+    full = sum(FORCE_BITS.values())
+    out = [("all", dict(base, force_mask=full))]
+    for name, bit in FORCE_BITS.items():
+        out.append((f"no_{name}", dict(base, force_mask=full & ~bit)))
+    out.append(("none", dict(base, force_mask=0)))
+    return out

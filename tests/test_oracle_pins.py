@@ -73,15 +73,17 @@ def test_mass_conserved_per_component_all_forces():
     assert 1e-6 < np.abs(m1["ux_ns"]).max() < 1e-2
 
 
-@pytest.mark.parametrize("phi0", [0.0, 0.02])
-def test_conduction_limit_is_linear_with_unit_nusselt(phi0):
+@pytest.mark.parametrize("phi0,nx,ny", [(0.0, 12, 12), (0.02, 12, 12), (0.02, 12, 24), (0.0, 16, 8)])
+def test_conduction_limit_is_linear_with_unit_nusselt(phi0, nx, ny):
     """Ra = 0 without slip forces: steady conduction between the isothermal
     walls (Eq 35) with adiabatic top and bottom (Eq 36) is the linear profile
-    theta = 1/2 - (x + 1/2)/N, so Nu = 1 and the conductivity-weighted
-    Nu_k = k_ns/k_f.  k_ns/k_f at phi0 = 0.02 comes from Eq 10a with the
-    constants below (water/alumina at 300 K, d_p = 100 nm, Pr = 0.71)."""
-    N = 12
-    o = oracle.Oracle(nx=N, ny=N, Ra=0.0, phi0=phi0, Pr=0.71, force_mask=0, phi_perturb_amp=0.0)
+    theta = 1/2 - (x + 1/2)/nx, so Nu = 1 and the conductivity-weighted
+    Nu_k = k_ns/k_f, for any aspect ratio ny/nx (Section 3.e; Nu on the
+    width between the isothermal walls).  k_ns/k_f at phi0 = 0.02 comes from
+    Eq 10a with the constants below (water/alumina at 300 K, d_p = 100 nm,
+    Pr = 0.71)."""
+    N = nx
+    o = oracle.Oracle(nx=nx, ny=ny, Ra=0.0, phi0=phi0, Pr=0.71, force_mask=0, phi_perturb_amp=0.0)
     o.step(6000)
     th = o.moments("theta")["theta"]
     x = np.arange(N)
@@ -156,14 +158,17 @@ def _centro(a):
     return a[::-1, ::-1]
 
 
-@pytest.mark.parametrize("phi0,mask", [(0.0, 0), (0.02, oracle.F_DRAG | oracle.F_SAFF | oracle.F_MAGROT)])
-def test_centro_symmetry(phi0, mask):
+@pytest.mark.parametrize("phi0,mask,nx,ny", [(0.0, 0, 24, 24),
+                                             (0.02, oracle.F_DRAG | oracle.F_SAFF | oracle.F_MAGROT, 24, 24),
+                                             (0.0, 0, 16, 32), (0.02, oracle.F_DRAG, 32, 16)])
+def test_centro_symmetry(phi0, mask, nx, ny):
     """With zero-mean theta, the cavity problem is invariant under the point
-    reflection (x, y) -> (N-1-x, N-1-y), theta -> -theta, u -> -u, phi -> phi,
-    as long as no force singles out a direction of gravity or absolute
-    temperature (thermophoresis and settling do).  Hot and cold Nu agree."""
-    N = 24
-    o = oracle.Oracle(nx=N, ny=N, Ra=2e4, phi0=phi0, force_mask=mask, phi_perturb_amp=0.0)
+    reflection (x, y) -> (nx-1-x, ny-1-y), theta -> -theta, u -> -u, phi ->
+    phi, as long as no force singles out a direction of gravity or absolute
+    temperature (thermophoresis and settling do); also for rectangular
+    cavities (aspect ratios 2 and 0.5, Section 3.e).  Hot and cold Nu
+    agree."""
+    o = oracle.Oracle(nx=nx, ny=ny, Ra=2e4, phi0=phi0, force_mask=mask, phi_perturb_amp=0.0)
     o.step(1500)
     m = o.moments()
     for k in ("theta", "ux_f", "uy_f", "ux_p", "uy_p", "ux_ns", "uy_ns"):
