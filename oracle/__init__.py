@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mclbm_oracle.c")
 _SO = os.path.join(_HERE, "libmclbm_oracle.so")
 
-FIELDS = ("rho_f", "ux_f", "uy_f", "phi", "ux_p", "uy_p", "theta", "ux_ns", "uy_ns")
+FIELDS = ("rho_f", "ux_f", "uy_f", "phi", "ux_p", "uy_p", "theta", "ux_ns", "uy_ns", "theta_f", "theta_p")
 FIELD_BIT = {name: 1 << i for i, name in enumerate(FIELDS)}
 
 F_DRAG, F_BROWN, F_THERMO, F_SAFF, F_MAGROT, F_GRAV = 1, 2, 4, 8, 16, 32
@@ -61,6 +61,7 @@ class Config(ctypes.Structure):
         ("boundary", ctypes.c_int32),
         ("body_force", ctypes.c_double * 2),
         ("u_f_init", ctypes.c_double * 2), ("u_p_init", ctypes.c_double * 2),
+        ("thermal_lattices", ctypes.c_int32),
     ]
 
 
@@ -217,11 +218,12 @@ class Oracle:
             raise RuntimeError(f"write_populations failed: {rc}")
 
     def populations(self) -> np.ndarray:
-        out = np.zeros(27 * self.nx * self.ny)
+        nl = 4 if self.cfg.thermal_lattices == 2 else 3
+        out = np.zeros(9 * nl * self.nx * self.ny)
         rc = lib().mclbm_oracle_read_populations(self._h, _dptr(out), out.size)
         if rc != 0:
             raise RuntimeError(f"read_populations failed: {rc}")
-        return out.reshape(3, 9, self.ny, self.nx)
+        return out.reshape(nl, 9, self.ny, self.nx)
 
     def nusselt(self) -> tuple:
         a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()

@@ -70,6 +70,8 @@ struct mo_state {
   int64_t t;
   double *f, *p, *g;    /* [9][nn], populations after streaming */
   double *fs, *ps, *gs; /* [9][nn], populations after collision */
+  double *g2, *g2s;     /* particle thermal lattice (two thermal lattices) */
+  int two_t;            /* two thermal lattices */
   double *phi_prev, *th_prev, *phi_cur, *th_cur;
   double *snap_ux, *snap_uy, *snap_th;
 };
@@ -118,6 +120,7 @@ void mclbm_oracle_config_defaults(mo_config* c) {
   c->particle.mu = 0.0;
   c->particle.d_mol = 0.0;
   c->boundary = MO_CAVITY;
+  c->thermal_lattices = 1;
 }
 
 /* ---- setup: lattice units from Ra, Pr, tau_f (Eqs 16, 22) -------------- */
@@ -419,6 +422,7 @@ static void free_state(mo_state* o) {
   if (!o) return;
   free(o->f); free(o->p); free(o->g);
   free(o->fs); free(o->ps); free(o->gs);
+  free(o->g2); free(o->g2s);
   free(o->phi_prev); free(o->th_prev); free(o->phi_cur); free(o->th_cur);
   free(o->snap_ux); free(o->snap_uy); free(o->snap_th);
   free(o);
@@ -426,18 +430,46 @@ static void free_state(mo_state* o) {
 
 void mclbm_oracle_destroy(mo_state* o) { free_state(o); }
 
+/* Temperatures at node n: the fluid's (first thermal lattice), the
+ * particles' (second thermal lattice, or the same one) and the
+ * suspension's, by Eq 33 over the two lattices.  Reading of Eq 33: the
+ * denominator carries the heat capacities as the numerator does (printed
+ * without them, the expression is not a temperature), so theta_ns is the
+ * average weighted by heat capacity per volume, (rho c_p)_f (1 - phi) and
+ * (rho c_p)_p phi. */
+static void node_temps(const mo_state* o, size_t n, double rho_p, double* th_f,
+                       double* th_p, double* th_ns) {
+  const size_t nn = o->nn;
+  double tf = 0.0;
+  for (int i = 0; i < 9; ++i) tf += o->g[i * nn + n];
+  *th_f = tf;
+  if (!o->two_t) {
+    *th_p = tf;
+    *th_ns = tf;
+    return;
+  }
+  double tp = 0.0;
+  for (int i = 0; i < 9; ++i) tp += o->g2[i * nn + n];
+  double phi = rho_p / o->s.R;
+  if (phi < 0.0) phi = 0.0;
+  const double cf = 1.0 - phi, cp = o->s.rhoc_ratio * phi;
+  *th_p = tp;
+  *th_ns = (cf * tf + cp * tp) / (cf + cp);
+}
+
 static void node_moments(const mo_state* o, size_t n, double* rho_f,
                          double* jxf, double* jyf, double* rho_p, double* jxp,
                          double* jyp, double* th) {
   const size_t nn = o->nn;
-  double a = 0, bx = 0, by = 0, c = 0, cx = 0, cy = 0, t = 0;
+  double a = 0, bx = 0, by = 0, c = 0, cx = 0, cy = 0;
   for (int i = 0; i < 9; ++i) {
     const double fi = o->f[i * nn + n], pi = o->p[i * nn + n];
     a += fi; bx += fi * EX[i]; by += fi * EY[i];
     c += pi; cx += pi * EX[i]; cy += pi * EY[i];
-    t += o->g[i * nn + n];
   }
-  *rho_f = a; *jxf = bx; *jyf = by; *rho_p = c; *jxp = cx; *jyp = cy; *th = t;
+  double tf, tp;
+  node_temps(o, n, c, &tf, &tp, th);
+  *rho_f = a; *jxf = bx; *jyf = by; *rho_p = c; *jxp = cx; *jyp = cy;
 }
 
 /* Lag fields of the first step and the residual snapshot, from the
@@ -464,6 +496,7 @@ int mclbm_oracle_create(const mo_config* cfg, const double* xi,
       !(cfg->phi0 <= 0.1) || !(cfg->dp > 0.0))
     return MO_EINVAL;
   if (cfg->tau_f > 0.0 && !(cfg->tau_f > 0.5)) return MO_EINVAL;
+  if (cfg->thermal_lattices < 0 || cfg->thermal_lattices > 2) return MO_EINVAL;
   mo_state* o = (mo_state*)calloc(1, sizeof(mo_state));
   if (!o) return MO_ENOMEM;
   o->cfg = *cfg;
@@ -475,6 +508,11 @@ int mclbm_oracle_create(const mo_config* cfg, const double* xi,
   o->f = malloc(9 * nn * sizeof(double));
   o->p = malloc(9 * nn * sizeof(double));
   o->g = malloc(9 * nn * sizeof(double));
+  o->two_t = cfg->thermal_lattices == 2;
+  if (o->two_t) {
+    o->g2 = malloc(9 * nn * sizeof(double));
+    o->g2s = malloc(9 * nn * sizeof(double));
+  }
   o->fs = malloc(9 * nn * sizeof(double));
   o->ps = malloc(9 * nn * sizeof(double));
   o->gs = malloc(9 * nn * sizeof(double));
@@ -487,7 +525,7 @@ int mclbm_oracle_create(const mo_config* cfg, const double* xi,
   o->snap_th = malloc(nn * sizeof(double));
   if (!o->f || !o->p || !o->g || !o->fs || !o->ps || !o->gs || !o->phi_prev ||
       !o->th_prev || !o->phi_cur || !o->th_cur || !o->snap_ux ||
-      !o->snap_uy || !o->snap_th) {
+      !o->snap_uy || !o->snap_th || (o->two_t && (!o->g2 || !o->g2s))) {
     free_state(o);
     return MO_ENOMEM;
   }
@@ -502,6 +540,7 @@ int mclbm_oracle_create(const mo_config* cfg, const double* xi,
       o->f[i * nn + n] = equilibrium(i, rf, cfg->u_f_init[0], cfg->u_f_init[1]);
       o->p[i * nn + n] = equilibrium(i, rp, cfg->u_p_init[0], cfg->u_p_init[1]);
       o->g[i * nn + n] = 0.0;
+      if (o->two_t) o->g2[i * nn + n] = 0.0;
     }
   }
   init_lag_and_snapshot(o);
@@ -536,7 +575,7 @@ static double field_diff(const double* a, int nx, int ny, int x, int y, int alon
 int mclbm_oracle_load_fields(mo_state* o, const double* ux, const double* uy,
                              const double* theta, const double* phi,
                              const double* rho_f) {
-  if (!o || !ux || !uy || !theta || !phi) return MO_EINVAL;
+  if (!o || !ux || !uy || !theta || !phi || o->two_t) return MO_EINVAL;
   const int nx = o->nx, ny = o->ny;
   const Setup* s = &o->s;
   for (int y = 0; y < ny; ++y) {
@@ -595,12 +634,41 @@ static void collide_all(mo_state* o) {
        * velocity of Eq 32. */
       for (int i = 0; i < 9; ++i) {
         const size_t k = i * nn + n;
-        const double fi = o->f[k], pi = o->p[k], gi = o->g[k];
+        const double fi = o->f[k], pi = o->p[k];
         o->fs[k] = fi - (fi - equilibrium(i, in.rho_f, r.ux_f, r.uy_f)) / tau_f +
                    forcing(i, r.Ffx, r.Ffy);
         o->ps[k] = pi - (pi - equilibrium(i, in.rho_p, r.ux_p, r.uy_p)) / r.tau_p +
                    forcing(i, r.Fpx, r.Fpy);
-        o->gs[k] = gi - (gi - equilibrium(i, in.theta, r.ux_ns, r.uy_ns)) / r.tau_th;
+      }
+      if (!o->two_t) {
+        for (int i = 0; i < 9; ++i) {
+          const size_t k = i * nn + n;
+          const double gi = o->g[k];
+          o->gs[k] = gi - (gi - equilibrium(i, in.theta, r.ux_ns, r.uy_ns)) / r.tau_th;
+        }
+      } else {
+        /* Eq 19 for each phase (reading of Eqs 18-19, "two equations"
+         * each): the fluid's thermal lattice relaxes to the fluid velocity
+         * with the base-fluid diffusivity (Eq 22 form), the particles' to
+         * the particle velocity with the relaxation time that makes the
+         * mass-weighted sum of Eq 24 equal tau_theta of the suspension
+         * (clamped as tau_p), or the fluid's where there are no particles. */
+        double th_f, th_p, th_ns;
+        node_temps(o, n, in.rho_p, &th_f, &th_p, &th_ns);
+        const double tau_tf = 3.0 * o->s.alpha_L + 0.5;
+        double tau_tp = tau_tf;
+        if (in.rho_p > 1e-12) {
+          const double rbar_p = in.rho_p / (in.rho_f + in.rho_p);
+          tau_tp = (r.tau_th - (1.0 - rbar_p) * tau_tf) / rbar_p;
+          if (tau_tp < 0.505) tau_tp = 0.505;
+          if (tau_tp > 5.0) tau_tp = 5.0;
+        }
+        for (int i = 0; i < 9; ++i) {
+          const size_t k = i * nn + n;
+          const double gi = o->g[k], hi = o->g2[k];
+          o->gs[k] = gi - (gi - equilibrium(i, th_f, r.ux_f, r.uy_f)) / tau_tf;
+          o->g2s[k] = hi - (hi - equilibrium(i, th_p, r.ux_p, r.uy_p)) / tau_tp;
+        }
       }
       /* keep (phi, theta) of this step for the next step's gradients */
       o->phi_cur[n] = in.rho_p / o->s.R;
@@ -634,6 +702,7 @@ static void stream_all(mo_state* o) {
           o->f[k] = o->fs[src];
           o->p[k] = o->ps[src];
           o->g[k] = o->gs[src];
+          if (o->two_t) o->g2[k] = o->g2s[src];
         } else {
           const size_t own = OPP[i] * nn + n;
           o->f[k] = o->fs[own];
@@ -641,8 +710,10 @@ static void stream_all(mo_state* o) {
           if (!in_x) {
             const double thw = sx < 0 ? TH_HOT : TH_COLD;
             o->g[k] = -o->gs[own] + 2.0 * WGT[i] * thw;
+            if (o->two_t) o->g2[k] = -o->g2s[own] + 2.0 * WGT[i] * thw;
           } else {
             o->g[k] = NAN; /* crossing a y-wall only: set by the copy below */
+            if (o->two_t) o->g2[k] = NAN;
           }
         }
       }
@@ -653,11 +724,13 @@ static void stream_all(mo_state* o) {
    * (e_y = -1) copied from rows 1 and ny-2 */
   for (int x = 0; x < nx; ++x) {
     for (int i = 0; i < 9; ++i) {
-      if (EY[i] == 1)
-        o->g[i * nn + x] = o->g[i * nn + (size_t)nx + x];
-      else if (EY[i] == -1)
-        o->g[i * nn + (size_t)(ny - 1) * nx + x] =
-            o->g[i * nn + (size_t)(ny - 2) * nx + x];
+      for (int l = 0; l < 1 + o->two_t; ++l) {
+        double* h = l == 0 ? o->g : o->g2;
+        if (EY[i] == 1)
+          h[i * nn + x] = h[i * nn + (size_t)nx + x];
+        else if (EY[i] == -1)
+          h[i * nn + (size_t)(ny - 1) * nx + x] = h[i * nn + (size_t)(ny - 2) * nx + x];
+      }
     }
   }
 }
@@ -680,26 +753,29 @@ int mclbm_oracle_read_moments(const mo_state* o, uint32_t mask, double* out,
                               size_t n_doubles) {
   if (!o || !out) return MO_EINVAL;
   int nf = 0;
-  for (int b = 0; b < 9; ++b) nf += (mask >> b) & 1u;
-  if (mask >> 9) return MO_EINVAL;
+  for (int b = 0; b < 11; ++b) nf += (mask >> b) & 1u;
+  if (mask >> 11) return MO_EINVAL;
   const size_t nn = o->nn;
   if (n_doubles < (size_t)nf * nn) return MO_EINVAL;
   for (size_t n = 0; n < nn; ++n) {
-    double rf, jxf, jyf, rp, jxp, jyp, th;
+    double rf, jxf, jyf, rp, jxp, jyp, th, th_f, th_p, th_ns;
     node_moments(o, n, &rf, &jxf, &jyf, &rp, &jxp, &jyp, &th);
+    node_temps(o, n, rp, &th_f, &th_p, &th_ns);
     const double uxf = jxf / rf, uyf = jyf / rf;
     const int empty = !(rp > 1e-12);
-    const double v[9] = {rf,
-                         uxf,
-                         uyf,
-                         rp / o->s.R,
-                         empty ? uxf : jxp / rp,
-                         empty ? uyf : jyp / rp,
-                         th,
-                         (jxf + jxp) / (rf + rp),
-                         (jyf + jyp) / (rf + rp)};
+    const double v[11] = {rf,
+                          uxf,
+                          uyf,
+                          rp / o->s.R,
+                          empty ? uxf : jxp / rp,
+                          empty ? uyf : jyp / rp,
+                          th,
+                          (jxf + jxp) / (rf + rp),
+                          (jyf + jyp) / (rf + rp),
+                          th_f,
+                          th_p};
     int slot = 0;
-    for (int b = 0; b < 9; ++b) {
+    for (int b = 0; b < 11; ++b) {
       if ((mask >> b) & 1u) {
         out[(size_t)slot * nn + n] = v[b];
         ++slot;
@@ -711,10 +787,11 @@ int mclbm_oracle_read_moments(const mo_state* o, uint32_t mask, double* out,
 
 int mclbm_oracle_read_populations(const mo_state* o, double* out,
                                   size_t n_doubles) {
-  if (!o || !out || n_doubles < 27 * o->nn) return MO_EINVAL;
+  if (!o || !out || n_doubles < (size_t)(27 + 9 * o->two_t) * o->nn) return MO_EINVAL;
   memcpy(out, o->f, 9 * o->nn * sizeof(double));
   memcpy(out + 9 * o->nn, o->p, 9 * o->nn * sizeof(double));
   memcpy(out + 18 * o->nn, o->g, 9 * o->nn * sizeof(double));
+  if (o->two_t) memcpy(out + 27 * o->nn, o->g2, 9 * o->nn * sizeof(double));
   return MO_OK;
 }
 
@@ -722,10 +799,11 @@ int mclbm_oracle_read_populations(const mo_state* o, double* out,
  * fields and the residual snapshot are taken from the new state. */
 int mclbm_oracle_write_populations(mo_state* o, const double* in,
                                    size_t n_doubles) {
-  if (!o || !in || n_doubles < 27 * o->nn) return MO_EINVAL;
+  if (!o || !in || n_doubles < (size_t)(27 + 9 * o->two_t) * o->nn) return MO_EINVAL;
   memcpy(o->f, in, 9 * o->nn * sizeof(double));
   memcpy(o->p, in + 9 * o->nn, 9 * o->nn * sizeof(double));
   memcpy(o->g, in + 18 * o->nn, 9 * o->nn * sizeof(double));
+  if (o->two_t) memcpy(o->g2, in + 27 * o->nn, 9 * o->nn * sizeof(double));
   init_lag_and_snapshot(o);
   return MO_OK;
 }
@@ -747,7 +825,9 @@ int mclbm_oracle_nusselt(const mo_state* o, double* nu_hot, double* nu_cold,
     const int xs[4] = {0, 1, nx - 2, nx - 1};
     for (int q = 0; q < 4; ++q) {
       const size_t n = (size_t)y * nx + xs[q];
-      for (int i = 0; i < 9; ++i) th[q] += o->g[i * nn + n];
+      double rq = 0.0, tf, tp;
+      for (int i = 0; i < 9; ++i) rq += o->p[i * nn + n];
+      node_temps(o, n, rq, &tf, &tp, &th[q]);
     }
     double rp = 0.0;
     for (int i = 0; i < 9; ++i) rp += o->p[i * nn + (size_t)y * nx];

@@ -43,7 +43,8 @@ enum {
 /* Moment field bits for mclbm_oracle_read_moments. */
 enum {
   MO_RHO_F = 1, MO_UX_F = 2, MO_UY_F = 4, MO_PHI = 8, MO_UX_P = 16,
-  MO_UY_P = 32, MO_THETA = 64, MO_UX_NS = 128, MO_UY_NS = 256
+  MO_UY_P = 32, MO_THETA = 64, MO_UX_NS = 128, MO_UY_NS = 256,
+  MO_THETA_F = 512, MO_THETA_P = 1024
 };
 
 typedef struct {
@@ -63,6 +64,9 @@ typedef struct {
   int32_t boundary;              /* MO_CAVITY / MO_CHANNEL / MO_PERIODIC */
   double body_force[2];          /* extra uniform force density on f */
   double u_f_init[2], u_p_init[2];
+  /* 1 (0 means 1): one thermal lattice for the suspension; 2: Eq 19 for
+   * each phase, the suspension temperature by Eq 33 */
+  int32_t thermal_lattices;
 } mo_config;
 
 /* Derived-constant slots returned by mclbm_oracle_derived. */
@@ -104,7 +108,7 @@ int mclbm_oracle_read_moments(const mo_state* o, uint32_t mask, double* out,
 int mclbm_oracle_write_populations(mo_state* o, const double* in,
                                    size_t n_doubles);
 int mclbm_oracle_read_populations(const mo_state* o, double* out,
-                                  size_t n_doubles); /* [3][9][ny][nx] */
+                                  size_t n_doubles); /* [3 or 4][9][ny][nx] */
 int mclbm_oracle_nusselt(const mo_state* o, double* nu_hot, double* nu_cold,
                          double* nu_hot_k);
 int mclbm_oracle_residual(mo_state* o, double* res_u, double* res_theta);
