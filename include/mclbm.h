@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define MCLBM_ABI_VERSION 1
+#define MCLBM_ABI_VERSION 2
 
 enum mclbm_status {
   MCLBM_OK = 0,
@@ -65,11 +65,15 @@ enum mclbm_force {
 /* Moment fields (Eqs 29-32) for mclbm_read_moments / mclbm_export_moments.
  * Fields are written in increasing bit order, each nx*ny doubles, row-major
  * with x fastest. RHO_F is the fluid partial density, PHI the particle
- * volume fraction, *_NS the mass-averaged mixture velocity of Eq 32. */
+ * volume fraction, *_NS the mass-averaged mixture velocity of Eq 32, THETA
+ * the suspension temperature; THETA_F and THETA_P the temperatures of the
+ * fluid and particle thermal lattices (equal to THETA with one thermal
+ * lattice). */
 enum mclbm_field {
   MCLBM_RHO_F = 1, MCLBM_UX_F = 2, MCLBM_UY_F = 4, MCLBM_PHI = 8,
   MCLBM_UX_P = 16, MCLBM_UY_P = 32, MCLBM_THETA = 64, MCLBM_UX_NS = 128,
-  MCLBM_UY_NS = 256, MCLBM_ALL_FIELDS = 511
+  MCLBM_UY_NS = 256, MCLBM_ALL_FIELDS = 511, MCLBM_THETA_F = 512,
+  MCLBM_THETA_P = 1024, MCLBM_FIELD_MASK = 2047, MCLBM_FIELD_COUNT = 11
 };
 
 /* Derived lattice constants (slots of mclbm_derived). */
@@ -108,6 +112,12 @@ typedef struct {
                               (256 x 1 when nx >= 256, else 64 x 1);
                               block_x in {32, 64, 128, 256} and
                               block_x * block_y in {64, 128, 256} */
+  int32_t thermal_lattices;/* 1 (default; 0 means 1): one thermal lattice
+                              for the suspension.  2: Eq 19 for each phase
+                              (fluid and particle temperatures), the
+                              suspension temperature by Eq 33; FP32 storage
+                              and single cavities only (MCLBM_EUNSUPPORTED
+                              otherwise, also for mclbm_load_fields) */
 } mclbm_config;
 
 typedef struct mclbm_cavity mclbm_cavity; /* opaque host-side handle */
@@ -191,13 +201,14 @@ int mclbm_read_moments(mclbm_cavity* c, uint32_t mask, double* host_out,
                        size_t n_doubles);
 
 /* Populations of the current state after streaming, as doubles in host
- * memory: [lattice f,p,g][direction][y][x], 27*nx*ny values, the shift of
- * the storage added back.  Sync.  For tests and checkpoints. */
+ * memory: [lattice f,p,g(,g2)][direction][y][x], 27*nx*ny values (36*nx*ny
+ * with two thermal lattices), the shift of the storage added back.  Sync.
+ * For tests and checkpoints. */
 int mclbm_read_populations(mclbm_cavity* c, double* host_out,
                            size_t n_doubles);
 
 /* As mclbm_read_populations, into device memory dev_out
- * (n_doubles >= 27*nx*ny).  Async. */
+ * (n_doubles >= 27*nx*ny, or 36*nx*ny).  Async. */
 int mclbm_export_populations(mclbm_cavity* c, double* dev_out,
                              size_t n_doubles);
 

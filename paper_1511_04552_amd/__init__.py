@@ -24,7 +24,7 @@ OK, EINVAL, ENOMEM, EHIP, EDIVERGED, ESTATE, EUNSUPPORTED = 0, -1, -2, -3, -4, -
 FP32S, FP16S, BF16S = 0, 1, 2
 F_DRAG, F_BROWN, F_THERMO, F_SAFF, F_MAGROT, F_GRAV = 1, 2, 4, 8, 16, 32
 F_ALL = 63
-FIELDS = ("rho_f", "ux_f", "uy_f", "phi", "ux_p", "uy_p", "theta", "ux_ns", "uy_ns")
+FIELDS = ("rho_f", "ux_f", "uy_f", "phi", "ux_p", "uy_p", "theta", "ux_ns", "uy_ns", "theta_f", "theta_p")
 FIELD_BIT = {name: 1 << i for i, name in enumerate(FIELDS)}
 DERIVED = ("nu_L", "alpha_L", "H", "dx", "dt", "G_L", "grav_L", "Ck", "R", "tau_f",
            "rhoc_ratio", "beta_ratio", "rho_f0", "rho_p0", "nu_f", "alpha_f")
@@ -66,6 +66,7 @@ class Config(ctypes.Structure):
         ("fluid", Material), ("particle", Material),
         ("storage", ctypes.c_int32),
         ("block_x", ctypes.c_int32), ("block_y", ctypes.c_int32),
+        ("thermal_lattices", ctypes.c_int32),
     ]
 
 
@@ -208,7 +209,10 @@ class Cavity:
         self.nx, self.ny = int(self.cfg.nx), int(self.cfg.ny)
         nbytes = L.mclbm_device_bytes(ctypes.byref(self.cfg))
         if nbytes == 0:
-            raise MclbmError(EINVAL, L.mclbm_last_error().decode())
+            msg = L.mclbm_last_error().decode()
+            # the validation's own code (EINVAL or EUNSUPPORTED)
+            rc = L.mclbm_derive_constants(ctypes.byref(self.cfg), None, 0)
+            raise MclbmError(rc if rc not in (OK, EINVAL) else EINVAL, msg)
         dev = torch.device("cuda" if device is None else device)
         self._buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
         base = self._buf.data_ptr()
@@ -297,9 +301,10 @@ class Cavity:
         return order, out
 
     def populations(self) -> np.ndarray:
-        out = np.zeros(27 * self.nx * self.ny)
+        nl = 4 if self.cfg.thermal_lattices == 2 else 3
+        out = np.zeros(9 * nl * self.nx * self.ny)
         _check(lib().mclbm_read_populations(self._h, _dptr(out), out.size))
-        return out.reshape(3, 9, self.ny, self.nx)
+        return out.reshape(nl, 9, self.ny, self.nx)
 
     def nusselt(self, check: bool = True) -> tuple:
         a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()

@@ -7,9 +7,12 @@
 //
 // Memory layout in HBM (one copy, updated in place):
 //   pop[(l*9 + i)*plane + y*px + x]  l = 0 fluid f, 1 particles p, 2 theta g
+//     (with two thermal lattices, Eq 19 for each phase: 2 fluid temperature
+//     g, 3 particle temperature g2)
 //   populations stored as deviations h = f - W_i rho_ref (rho_ref = 0 for g)
 //   d2[k][y*px + x] = (phi - phi_ref, theta) of the step before, k = t & 1
-//   d5[(wall*3 + slot)*px + x]  adiabatic-wall side buffer (see below)
+//   d5[(lat*6 + wall*3 + slot)*px + x]  adiabatic-wall side buffer (see
+//     below), one block of six rows per thermal lattice
 //
 // A-A pattern.  Even steps read the nine populations of a node from its own
 // slots i and write the post-collision value of direction i into its own slot
@@ -167,7 +170,7 @@ __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(
 
 // ---- kernel parameters (kernarg, by value) -------------------------------
 struct StepParams {
-  int nx, ny, px, pad0;
+  int nx, ny, px, nl;    // nl: lattices, 3 or 4 (two thermal lattices)
   long long plane;       // elements per population plane
   float scale[3];        // storage scale per lattice (1 for FP32)
   float inv_scale[3];
@@ -179,6 +182,7 @@ struct StepParams {
   float invR, Rm1, crc, crb, Ck, alpha3;
   float tp_a, tp_b;      // tau_p = tau_f + tp_a rho_m (tp_b + 222.4 phi)/r_rho
   float G_L;             // g beta dT in lattice units
+  float omega_thf, tau_thf;  // relaxation of the fluid thermal lattice (nl = 4)
   // slip forces (Table 1) in lattice units, switches and scales folded in
   float cB;              // Brownian
   float cT, kfp, A1, A2; // thermophoresis
@@ -202,7 +206,7 @@ struct StepParams {
 template <class T>
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t pop_rsrc(const T* pop, const StepParams& P) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(pop), 0,
-                                           (int)(27u * (uint32_t)P.plane * (uint32_t)sizeof(T)),
+                                           (int)(9u * (uint32_t)P.nl * (uint32_t)P.plane * (uint32_t)sizeof(T)),
                                            0x00020000);
 }
 // wave-uniform byte offset of plane q shifted by (dx, dy) nodes
@@ -212,12 +216,26 @@ __device__ __forceinline__ uint32_t soff(const StepParams& P, int q, int dx, int
 }
 
 // ---- read the nine populations of each lattice ------------------------------
-template <bool ODD, class S, class I>
+// Thermal lattice at planes tb (18 or 27), side-buffer block db (0 or 6 rows):
+// the same wall rules for either.
+template <bool ODD, class S>
+__device__ __forceinline__ float load_thermal32(const StepParams& P, __amdgpu_buffer_rsrc_t R, uint32_t vo,
+                                                const float* __restrict__ d5, int x, int i, int tb, int db,
+                                                bool xl, bool outx, bool outy) {
+  using T = typename S::T;
+  if (!ODD) return S::bld(R, vo, soff<T>(P, tb + i, 0, 0), P.inv_scale[2]);
+  if (!(outx || outy)) return S::bld(R, vo, soff<T>(P, tb + opp(i), -ex(i), -ey(i)), P.inv_scale[2]);
+  if (outy) return d5[(db + (ey(i) == 1 ? 0 : 3) + d5slot(i)) * P.px + x];
+  const float v = S::bld(R, vo, soff<T>(P, tb + i, 0, 0), P.inv_scale[2]);
+  return (xl ? wgt(i) : -wgt(i)) - v;
+}
+
+template <bool ODD, class S, class I, int NL = 3>
 __device__ __forceinline__ void load_node(const StepParams& P,
                                           const typename S::T* __restrict__ pop,
                                           const float* __restrict__ d5, int x,
                                           int y, float f[9], float p[9],
-                                          float g[9]) {
+                                          float g[9], float g2[9] = nullptr) {
   using T = typename S::T;
   const I px = (I)P.px, pl = (I)P.plane;
   const I n = (I)y * px + (I)x;
@@ -227,30 +245,23 @@ __device__ __forceinline__ void load_node(const StepParams& P,
     const uint32_t vo = (uint32_t)n * (uint32_t)sizeof(T);
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
+      const bool outx = ODD && ((ex(i) == 1 && xl) || (ex(i) == -1 && xr));
+      const bool outy = ODD && ((ey(i) == 1 && yb) || (ey(i) == -1 && yt));
       if (!ODD) {
         f[i] = S::bld(R, vo, soff<T>(P, i, 0, 0), P.inv_scale[0]);
         p[i] = S::bld(R, vo, soff<T>(P, 9 + i, 0, 0), P.inv_scale[1]);
-        g[i] = S::bld(R, vo, soff<T>(P, 18 + i, 0, 0), P.inv_scale[2]);
+      } else if (!(outx || outy)) {
+        // upstream node x - e_i, slot opp(i)
+        f[i] = S::bld(R, vo, soff<T>(P, opp(i), -ex(i), -ey(i)), P.inv_scale[0]);
+        p[i] = S::bld(R, vo, soff<T>(P, 9 + opp(i), -ex(i), -ey(i)), P.inv_scale[1]);
       } else {
-        const bool outx = (ex(i) == 1 && xl) || (ex(i) == -1 && xr);
-        const bool outy = (ey(i) == 1 && yb) || (ey(i) == -1 && yt);
-        if (!(outx || outy)) {
-          // upstream node x - e_i, slot opp(i)
-          f[i] = S::bld(R, vo, soff<T>(P, opp(i), -ex(i), -ey(i)), P.inv_scale[0]);
-          p[i] = S::bld(R, vo, soff<T>(P, 9 + opp(i), -ex(i), -ey(i)), P.inv_scale[1]);
-          g[i] = S::bld(R, vo, soff<T>(P, 18 + opp(i), -ex(i), -ey(i)), P.inv_scale[2]);
-        } else {
-          // wall link: own slot i (bounce-back); g by the wall rule
-          f[i] = S::bld(R, vo, soff<T>(P, i, 0, 0), P.inv_scale[0]);
-          p[i] = S::bld(R, vo, soff<T>(P, 9 + i, 0, 0), P.inv_scale[1]);
-          if (outy) {
-            g[i] = d5[((ey(i) == 1 ? 0 : 3) + d5slot(i)) * P.px + x];
-          } else {
-            const float v = S::bld(R, vo, soff<T>(P, 18 + i, 0, 0), P.inv_scale[2]);
-            g[i] = (xl ? wgt(i) : -wgt(i)) - v;
-          }
-        }
+        // wall link: own slot i (bounce-back); the thermal lattices by the
+        // wall rules
+        f[i] = S::bld(R, vo, soff<T>(P, i, 0, 0), P.inv_scale[0]);
+        p[i] = S::bld(R, vo, soff<T>(P, 9 + i, 0, 0), P.inv_scale[1]);
       }
+      g[i] = load_thermal32<ODD, S>(P, R, vo, d5, x, i, 18, 0, xl, outx, outy);
+      if constexpr (NL == 4) g2[i] = load_thermal32<ODD, S>(P, R, vo, d5, x, i, 27, 6, xl, outx, outy);
     }
     return;
   } else {
@@ -260,6 +271,7 @@ __device__ __forceinline__ void load_node(const StepParams& P,
         f[i] = S::ld(elem(pop, pl * (I)i + n), P.inv_scale[0]);
         p[i] = S::ld(elem(pop, pl * (I)(9 + i) + n), P.inv_scale[1]);
         g[i] = S::ld(elem(pop, pl * (I)(18 + i) + n), P.inv_scale[2]);
+        if constexpr (NL == 4) g2[i] = S::ld(elem(pop, pl * (I)(27 + i) + n), P.inv_scale[2]);
       } else {
         const bool outx = (ex(i) == 1 && xl) || (ex(i) == -1 && xr);
         const bool outy = (ey(i) == 1 && yb) || (ey(i) == -1 && yt);
@@ -269,13 +281,18 @@ __device__ __forceinline__ void load_node(const StepParams& P,
         const I a = out ? (pl * (I)i + n) : (pl * (I)opp(i) + up);
         f[i] = S::ld(elem(pop, a), P.inv_scale[0]);
         p[i] = S::ld(elem(pop, pl * (I)9 + a), P.inv_scale[1]);
-        if (i == 0) {
-          g[i] = S::ld(elem(pop, pl * (I)18 + a), P.inv_scale[2]);
-        } else if (outy) {
-          g[i] = d5[((ey(i) == 1 ? 0 : 3) + d5slot(i)) * P.px + x];
-        } else {
-          const float v = S::ld(elem(pop, pl * (I)18 + a), P.inv_scale[2]);
-          g[i] = outx ? (xl ? wgt(i) : -wgt(i)) - v : v;
+#pragma unroll
+        for (int l = 0; l < NL - 2; ++l) {
+          float* h = l == 0 ? g : g2;
+          const I tb = pl * (I)(18 + 9 * l);
+          if (i == 0) {
+            h[i] = S::ld(elem(pop, tb + a), P.inv_scale[2]);
+          } else if (outy) {
+            h[i] = d5[(6 * l + (ey(i) == 1 ? 0 : 3) + d5slot(i)) * P.px + x];
+          } else {
+            const float v = S::ld(elem(pop, tb + a), P.inv_scale[2]);
+            h[i] = outx ? (xl ? wgt(i) : -wgt(i)) - v : v;
+          }
         }
       }
     }
@@ -283,12 +300,61 @@ __device__ __forceinline__ void load_node(const StepParams& P,
 }
 
 // ---- write the post-collision populations -----------------------------------
-template <bool ODD, class S, class I>
+template <bool ODD, class S>
+__device__ __forceinline__ void store_thermal32(const StepParams& P, __amdgpu_buffer_rsrc_t R, uint32_t vo,
+                                                int i, int tb, float v, int y, bool yb, bool yt,
+                                                bool outx, bool outy) {
+  using T = typename S::T;
+  if (!ODD) {
+    S::bst(R, vo, soff<T>(P, tb + opp(i), 0, 0), v, P.scale[2]);
+  } else if (!(outx || outy)) {
+    // downstream node x + e_i, slot i
+    S::bst(R, vo, soff<T>(P, tb + i, ex(i), ey(i)), v, P.scale[2]);
+    // the wall row takes the same value (copy of the adiabatic wall)
+    if ((ey(i) == 1 && yb) || (ey(i) == -1 && yt)) S::bst(R, vo, soff<T>(P, tb + i, ex(i), 0), v, P.scale[2]);
+  } else if (!outy) {
+    // isothermal wall: anti-bounce-back into the own slot opp(i)
+    const float w = (ex(i) == -1 ? wgt(i) : -wgt(i)) - v;
+    S::bst(R, vo, soff<T>(P, tb + opp(i), 0, 0), w, P.scale[2]);
+    // corner: the wall row next to this one copies it
+    if (ey(opp(i)) == 1 && y == 1) S::bst(R, vo, soff<T>(P, tb + opp(i), 0, -1), w, P.scale[2]);
+    if (ey(opp(i)) == -1 && y == P.ny - 2) S::bst(R, vo, soff<T>(P, tb + opp(i), 0, 1), w, P.scale[2]);
+  }
+  // out through an adiabatic wall: the value leaves the domain
+}
+
+// side buffer for the adiabatic copy of the next (odd) step, block db
+__device__ __forceinline__ void store_side(const StepParams& P, float* __restrict__ d5, int db, int x, int y,
+                                           const float g[9]) {
+  const int px = P.px, nx = P.nx, ny = P.ny;
+  const bool xl = x == 0, xr = x == nx - 1, yb = y == 0, yt = y == ny - 1;
+  float* d = d5 + (size_t)db * px;
+  if (yb) {
+    d[0 * px + x] = g[2];
+    if (!xr) d[1 * px + x + 1] = g[5];
+    if (!xl) d[2 * px + x - 1] = g[6];
+  }
+  if (y == 1) {
+    if (xl) d[1 * px + 0] = wgt(5) - g[7];
+    if (xr) d[2 * px + nx - 1] = -wgt(6) - g[8];
+  }
+  if (yt) {
+    d[3 * px + x] = g[4];
+    if (!xr) d[4 * px + x + 1] = g[8];
+    if (!xl) d[5 * px + x - 1] = g[7];
+  }
+  if (y == ny - 2) {
+    if (xl) d[4 * px + 0] = wgt(8) - g[6];
+    if (xr) d[5 * px + nx - 1] = -wgt(7) - g[5];
+  }
+}
+
+template <bool ODD, class S, class I, int NL = 3>
 __device__ __forceinline__ void store_node(const StepParams& P,
                                            typename S::T* __restrict__ pop,
                                            float* __restrict__ d5, int x, int y,
                                            const float f[9], const float p[9],
-                                           const float g[9]) {
+                                           const float g[9], const float g2[9] = nullptr) {
   using T = typename S::T;
   const I px = (I)P.px, pl = (I)P.plane;
   const I n = (I)y * px + (I)x;
@@ -299,38 +365,19 @@ __device__ __forceinline__ void store_node(const StepParams& P,
     const uint32_t vo = (uint32_t)n * (uint32_t)sizeof(T);
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-      if (!ODD) {
+      const bool outx = ODD && ((ex(i) == 1 && xr) || (ex(i) == -1 && xl));
+      const bool outy = ODD && ((ey(i) == 1 && yt) || (ey(i) == -1 && yb));
+      if (!ODD || outx || outy) {
+        // even step, or wall link: own slot opp(i)
         S::bst(R, vo, soff<T>(P, opp(i), 0, 0), f[i], P.scale[0]);
         S::bst(R, vo, soff<T>(P, 9 + opp(i), 0, 0), p[i], P.scale[1]);
-        S::bst(R, vo, soff<T>(P, 18 + opp(i), 0, 0), g[i], P.scale[2]);
       } else {
-        const bool outx = (ex(i) == 1 && xr) || (ex(i) == -1 && xl);
-        const bool outy = (ey(i) == 1 && yt) || (ey(i) == -1 && yb);
-        if (!(outx || outy)) {
-          // downstream node x + e_i, slot i
-          S::bst(R, vo, soff<T>(P, i, ex(i), ey(i)), f[i], P.scale[0]);
-          S::bst(R, vo, soff<T>(P, 9 + i, ex(i), ey(i)), p[i], P.scale[1]);
-          S::bst(R, vo, soff<T>(P, 18 + i, ex(i), ey(i)), g[i], P.scale[2]);
-          // the wall row takes the same value (copy of the adiabatic wall)
-          if ((ey(i) == 1 && yb) || (ey(i) == -1 && yt))
-            S::bst(R, vo, soff<T>(P, 18 + i, ex(i), 0), g[i], P.scale[2]);
-        } else {
-          // wall link: own slot opp(i)
-          S::bst(R, vo, soff<T>(P, opp(i), 0, 0), f[i], P.scale[0]);
-          S::bst(R, vo, soff<T>(P, 9 + opp(i), 0, 0), p[i], P.scale[1]);
-          if (!outy) {
-            // isothermal wall: anti-bounce-back into the own slot opp(i)
-            const float v = (ex(i) == -1 ? wgt(i) : -wgt(i)) - g[i];
-            S::bst(R, vo, soff<T>(P, 18 + opp(i), 0, 0), v, P.scale[2]);
-            // corner: the wall row next to this one copies it
-            if (ey(opp(i)) == 1 && y == 1)
-              S::bst(R, vo, soff<T>(P, 18 + opp(i), 0, -1), v, P.scale[2]);
-            if (ey(opp(i)) == -1 && y == ny - 2)
-              S::bst(R, vo, soff<T>(P, 18 + opp(i), 0, 1), v, P.scale[2]);
-          }
-          // out through an adiabatic wall: the value leaves the domain
-        }
+        // downstream node x + e_i, slot i
+        S::bst(R, vo, soff<T>(P, i, ex(i), ey(i)), f[i], P.scale[0]);
+        S::bst(R, vo, soff<T>(P, 9 + i, ex(i), ey(i)), p[i], P.scale[1]);
       }
+      store_thermal32<ODD, S>(P, R, vo, i, 18, g[i], y, yb, yt, outx, outy);
+      if constexpr (NL == 4) store_thermal32<ODD, S>(P, R, vo, i, 27, g2[i], y, yb, yt, outx, outy);
     }
   } else {
 #pragma unroll
@@ -339,6 +386,7 @@ __device__ __forceinline__ void store_node(const StepParams& P,
         S::st(elem(pop, pl * (I)opp(i) + n), f[i], P.scale[0]);
         S::st(elem(pop, pl * (I)(9 + opp(i)) + n), p[i], P.scale[1]);
         S::st(elem(pop, pl * (I)(18 + opp(i)) + n), g[i], P.scale[2]);
+        if constexpr (NL == 4) S::st(elem(pop, pl * (I)(27 + opp(i)) + n), g2[i], P.scale[2]);
       } else {
         const bool outx = (ex(i) == 1 && xr) || (ex(i) == -1 && xl);
         const bool outy = (ey(i) == 1 && yt) || (ey(i) == -1 && yb);
@@ -347,42 +395,29 @@ __device__ __forceinline__ void store_node(const StepParams& P,
         const I a = out ? (pl * (I)opp(i) + n) : (pl * (I)i + down);
         S::st(elem(pop, a), f[i], P.scale[0]);
         S::st(elem(pop, pl * (I)9 + a), p[i], P.scale[1]);
-        if (i == 0) {
-          S::st(elem(pop, pl * (I)18 + a), g[i], P.scale[2]);
-        } else if (!out) {
-          S::st(elem(pop, pl * (I)18 + a), g[i], P.scale[2]);
-          if ((ey(i) == 1 && yb) || (ey(i) == -1 && yt))
-            S::st(elem(pop, pl * (I)(18 + i) + n + (I)ex(i)), g[i], P.scale[2]);
-        } else if (!outy) {
-          const float v = (ex(i) == -1 ? wgt(i) : -wgt(i)) - g[i];
-          S::st(elem(pop, pl * (I)18 + a), v, P.scale[2]);
-          if (ey(opp(i)) == 1 && y == 1) S::st(elem(pop, pl * (I)18 + a - px), v, P.scale[2]);
-          if (ey(opp(i)) == -1 && y == ny - 2) S::st(elem(pop, pl * (I)18 + a + px), v, P.scale[2]);
+#pragma unroll
+        for (int l = 0; l < NL - 2; ++l) {
+          const float gv = l == 0 ? g[i] : g2[i];
+          const I tb = pl * (I)(18 + 9 * l);
+          if (i == 0) {
+            S::st(elem(pop, tb + a), gv, P.scale[2]);
+          } else if (!out) {
+            S::st(elem(pop, tb + a), gv, P.scale[2]);
+            if ((ey(i) == 1 && yb) || (ey(i) == -1 && yt))
+              S::st(elem(pop, tb + pl * (I)i + n + (I)ex(i)), gv, P.scale[2]);
+          } else if (!outy) {
+            const float v = (ex(i) == -1 ? wgt(i) : -wgt(i)) - gv;
+            S::st(elem(pop, tb + a), v, P.scale[2]);
+            if (ey(opp(i)) == 1 && y == 1) S::st(elem(pop, tb + a - px), v, P.scale[2]);
+            if (ey(opp(i)) == -1 && y == ny - 2) S::st(elem(pop, tb + a + px), v, P.scale[2]);
+          }
         }
       }
     }
   }
   if (!ODD) {
-    // side buffer for the adiabatic copy of the next (odd) step
-    const int px = P.px;
-    if (yb) {
-      d5[0 * px + x] = g[2];
-      if (!xr) d5[1 * px + x + 1] = g[5];
-      if (!xl) d5[2 * px + x - 1] = g[6];
-    }
-    if (y == 1) {
-      if (xl) d5[1 * px + 0] = wgt(5) - g[7];
-      if (xr) d5[2 * px + nx - 1] = -wgt(6) - g[8];
-    }
-    if (yt) {
-      d5[3 * px + x] = g[4];
-      if (!xr) d5[4 * px + x + 1] = g[8];
-      if (!xl) d5[5 * px + x - 1] = g[7];
-    }
-    if (y == ny - 2) {
-      if (xl) d5[4 * px + 0] = wgt(8) - g[6];
-      if (xr) d5[5 * px + nx - 1] = -wgt(7) - g[5];
-    }
+    store_side(P, d5, 0, x, y, g);
+    if constexpr (NL == 4) store_side(P, d5, 6, x, y, g2);
   }
 }
 
@@ -452,10 +487,14 @@ __device__ __forceinline__ NodeMoments moments(const float f[9], const float p[9
 // ---- one node: moments, properties, slip forces, collision ---------------
 // gphi, gth: central-difference gradients of the previous step's fields.
 // Returns the fields this step stores for the next step's gradients.
+// NL = 4: two thermal lattices (Eq 19 for each phase), g for the fluid and
+// g2 for the particles; the suspension temperature is their heat-capacity
+// weighted mean (Eq 33) and drives buoyancy and thermophoresis.
+template <int NL = 3>
 __device__ __forceinline__ float2 node_update(const StepParams& P, float f[9],
                                               float p[9], float g[9],
                                               float gphix, float gphiy,
-                                              float gthx, float gthy) {
+                                              float gthx, float gthy, float g2[9] = nullptr) {
   const NodeMoments m = moments(f, p, g);
   // S1/S2: Eqs 29-32 (partial densities; mass-averaged mixture velocity)
   const float rho_f = P.rho_f_ref + m.drf;
@@ -469,7 +508,6 @@ __device__ __forceinline__ float2 node_update(const StepParams& P, float f[9],
   const float rho_m = rho_f + rho_p;
   const float irm = frcp(rho_m);
   const float uxn = (m.jxf + m.jxp) * irm, uyn = (m.jyf + m.jyp) * irm;
-  const float th = m.th;
 
   // S3: Eqs 7-11 as ratios to the base fluid; Eq 23 for tau_p; Eq 24
   const float phi = rho_p * P.invR;
@@ -484,6 +522,14 @@ __device__ __forceinline__ float2 node_update(const StepParams& P, float f[9],
   tau_p = fminf(fmaxf(tau_p, 0.505f), 5.0f);
   if (empty) tau_p = P.tau_f;
   const float tau_th = fmaf(P.alpha3 * r_k, frcp(r_rhoc), 0.5f);
+  // temperature of the suspension: the single thermal lattice, or Eq 33
+  // over the two (volume fractions 1 - phi and phi, heat capacities per
+  // volume in the ratio 1 : 1 + crc)
+  float th = m.th, thp = 0.0f;
+  if constexpr (NL == 4) {
+    thp = ((g2[0] + g2[1]) + (g2[2] + g2[3])) + ((g2[4] + g2[5]) + (g2[6] + (g2[7] + g2[8])));
+    th = fmaf(phic, fmaf(P.crc + 1.0f, thp, -m.th), m.th) * frcp(fmaf(phic, P.crc, 1.0f));
+  }
 
   // S5: forces.  The fluid carries buoyancy (Eq 20) and the net weight of
   // the particles relative to the uniform suspension; every interaction
@@ -570,7 +616,19 @@ __device__ __forceinline__ float2 node_update(const StepParams& P, float f[9],
   collide(f, m.drf, rho_f, m.jxf, m.jyf, uxf, uyf, P.omega_f, Ffx, Ffy);
   collide(p, m.drp, rho_p, empty ? rho_p * uxf : m.jxp, empty ? rho_p * uyf : m.jyp, uxp, uyp,
           frcp(tau_p), Fpx, Fpy);
-  collide(g, th, th, th * uxn, th * uyn, uxn, uyn, frcp(tau_th), 0.0f, 0.0f);
+  if constexpr (NL == 4) {
+    // each phase's thermal lattice relaxes to its own velocity; the fluid's
+    // with the base-fluid diffusivity, the particles' with the relaxation
+    // time that makes the mass-weighted sum of Eq 24 equal tau_theta of the
+    // suspension
+    const float thf = m.th;
+    collide(g, thf, thf, thf * uxf, thf * uyf, uxf, uyf, P.omega_thf, 0.0f, 0.0f);
+    float tau_tp = P.tau_thf;
+    if (!empty) tau_tp = fminf(fmaxf(fmaf(tau_th - P.tau_thf, rho_m * irp, P.tau_thf), 0.505f), 5.0f);
+    collide(g2, thp, thp, thp * uxp, thp * uyp, uxp, uyp, frcp(tau_tp), 0.0f, 0.0f);
+  } else {
+    collide(g, th, th, th * uxn, th * uyn, uxn, uyn, frcp(tau_th), 0.0f, 0.0f);
+  }
   return make_float2(m.drp * P.invR, th);
 }
 

@@ -31,7 +31,7 @@ using namespace mclbm;
 // Kernels
 // ===========================================================================
 
-template <class S>
+template <class S, int NL>
 __global__ __launch_bounds__(256) void k_init(StepParams P,
                                               typename S::T* __restrict__ pop,
                                               const double* __restrict__ dev_p,
@@ -52,8 +52,10 @@ __global__ __launch_bounds__(256) void k_init(StepParams P,
     S::st(pop + P.plane * i + n, f[i], P.scale[0]);
     S::st(pop + P.plane * (9 + i) + n, p[i], P.scale[1]);
     S::st(pop + P.plane * (18 + i) + n, g[i], P.scale[2]);
+    if constexpr (NL == 4) S::st(pop + P.plane * (27 + i) + n, 0.0f, P.scale[2]);
   }
-  // the lag field holds what the first step would have stored
+  // the lag field holds what the first step would have stored (theta = 0
+  // on every thermal lattice, so the suspension temperature is 0 too)
   float fl[9], pl[9], gl[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
@@ -76,12 +78,12 @@ __device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned nb) {
 }
 
 // One node of one time step (the whole hot path for that node).
-template <bool ODD, class S, class I>
+template <bool ODD, class S, class I, int NL = 3>
 __device__ __forceinline__ void step_node(const StepParams& P, typename S::T* __restrict__ pop,
                                           const float2* __restrict__ d2p, float2* __restrict__ d2c,
                                           float* __restrict__ d5, int x, int y) {
-  float f[9], p[9], g[9];
-  load_node<ODD, S, I>(P, pop, d5, x, y, f, p, g);
+  float f[9], p[9], g[9], g2[NL == 4 ? 9 : 1];
+  load_node<ODD, S, I, NL>(P, pop, d5, x, y, f, p, g, g2);
 
   // S4: central differences of the previous step's (phi, theta); zero-flux
   // mirror ghosts for phi on all walls and for theta on the adiabatic walls,
@@ -99,12 +101,12 @@ __device__ __forceinline__ void step_node(const StepParams& P, typename S::T* __
   const float gphix = 0.5f * (vE.x - vW.x), gphiy = 0.5f * (vN.x - vS.x);
   const float gthx = 0.5f * (thE - thW), gthy = 0.5f * (vN.y - vS.y);
 
-  const float2 keep = node_update(P, f, p, g, gphix, gphiy, gthx, gthy);
-  store_node<ODD, S, I>(P, pop, d5, x, y, f, p, g);
+  const float2 keep = node_update<NL>(P, f, p, g, gphix, gphiy, gthx, gthy, g2);
+  store_node<ODD, S, I, NL>(P, pop, d5, x, y, f, p, g, g2);
   d2c[n] = keep;
 }
 
-template <bool ODD, class S, class I>
+template <bool ODD, class S, class I, int NL>
 __global__ __launch_bounds__(256) void k_step(StepParams P,
                                               typename S::T* __restrict__ pop,
                                               const float2* __restrict__ d2p,
@@ -115,7 +117,7 @@ __global__ __launch_bounds__(256) void k_step(StepParams P,
   const int x = (int)(t % (unsigned)tiles_x) * blockDim.x + threadIdx.x;
   const int y = (int)(t / (unsigned)tiles_x) * blockDim.y + threadIdx.y;
   if (x >= P.nx || y >= P.ny) return;
-  step_node<ODD, S, I>(P, pop, d2p, d2c, d5, x, y);
+  step_node<ODD, S, I, NL>(P, pop, d2p, d2c, d5, x, y);
 }
 
 // Batched sweep: one launch per time step updates every active cavity of a
@@ -167,7 +169,25 @@ __device__ double block_sum(double v, double* lds) {
   return r;
 }
 
-template <bool ODD, class S, class I>
+// Temperatures at a node in FP64: fluid (first thermal lattice), particles
+// (second thermal lattice, or the same one) and the suspension (Eq 33 over
+// the two lattices with volume fractions 1 - phi, phi and heat capacities
+// per volume in the ratio 1 : 1 + crc).
+template <int NL>
+__device__ __forceinline__ double3 node_thetas(const float g[9], const float g2[9], double phi, double crc) {
+  double tf = 0.0;
+  for (int i = 0; i < 9; ++i) tf += (double)g[i];
+  if constexpr (NL == 3) {
+    return make_double3(tf, tf, tf);
+  } else {
+    double tp = 0.0;
+    for (int i = 0; i < 9; ++i) tp += (double)g2[i];
+    const double pc = phi > 0.0 ? phi : 0.0;
+    return make_double3(tf, tp, (tf + pc * ((1.0 + crc) * tp - tf)) / (1.0 + crc * pc));
+  }
+}
+
+template <bool ODD, class S, class I, int NL>
 __global__ __launch_bounds__(256) void k_nusselt(StepParams P,
                                                  const typename S::T* __restrict__ pop,
                                                  const float* __restrict__ d5,
@@ -180,17 +200,16 @@ __global__ __launch_bounds__(256) void k_nusselt(StepParams P,
   for (int y = threadIdx.x; y < ny; y += blockDim.x) {
     const int xs[4] = {0, 1, nx - 2, nx - 1};
     double th[4];
-    double rp = rho_p_ref;
+    double rp0 = rho_p_ref;
     for (int q = 0; q < 4; ++q) {
-      float f[9], p[9], g[9];
-      load_node<ODD, S, I>(P, pop, d5, xs[q], y, f, p, g);
-      double t = 0.0;
-      for (int i = 0; i < 9; ++i) t += (double)g[i];
-      th[q] = t;
-      if (q == 0)
-        for (int i = 0; i < 9; ++i) rp += (double)p[i];
+      float f[9], p[9], g[9], g2[NL == 4 ? 9 : 1];
+      load_node<ODD, S, I, NL>(P, pop, d5, xs[q], y, f, p, g, g2);
+      double rp = rho_p_ref;
+      for (int i = 0; i < 9; ++i) rp += (double)p[i];
+      th[q] = node_thetas<NL>(g, g2, rp / R, (double)P.crc).z;
+      if (q == 0) rp0 = rp;
     }
-    double phi = rp / R;
+    double phi = rp0 / R;
     if (phi < 0.0) phi = 0.0;
     const double rk = 1.0 + Ck * pow(phi, 0.764);
     const double gh = -(double)nx * (9.0 * th[0] - th[1] - 4.0) / 3.0;
@@ -214,7 +233,7 @@ __global__ __launch_bounds__(256) void k_nusselt(StepParams P,
 
 // Per-block partial sums of |u - u_ref|^2, |u|^2, (theta - theta_ref)^2,
 // theta^2 and a non-finite count; the snapshot is replaced by the state.
-template <bool ODD, class S, class I>
+template <bool ODD, class S, class I, int NL>
 __global__ __launch_bounds__(256) void k_residual(StepParams P,
                                                   const typename S::T* __restrict__ pop,
                                                   const float* __restrict__ d5,
@@ -227,16 +246,16 @@ __global__ __launch_bounds__(256) void k_residual(StepParams P,
   double du = 0.0, un = 0.0, dt = 0.0, tn = 0.0, bad = 0.0;
   if (k < nn) {
     const int x = (int)(k % P.nx), y = (int)(k / P.nx);
-    float f[9], p[9], g[9];
-    load_node<ODD, S, I>(P, pop, d5, x, y, f, p, g);
-    double rf = rho_f_ref, rp = rho_p_ref, jx = 0.0, jy = 0.0, th = 0.0;
+    float f[9], p[9], g[9], g2[NL == 4 ? 9 : 1];
+    load_node<ODD, S, I, NL>(P, pop, d5, x, y, f, p, g, g2);
+    double rf = rho_f_ref, rp = rho_p_ref, jx = 0.0, jy = 0.0;
     for (int i = 0; i < 9; ++i) {
       rf += (double)f[i];
       rp += (double)p[i];
       jx += (double)ex(i) * ((double)f[i] + (double)p[i]);
       jy += (double)ey(i) * ((double)f[i] + (double)p[i]);
-      th += (double)g[i];
     }
+    const double th = node_thetas<NL>(g, g2, rp * (double)P.invR, (double)P.crc).z;
     const double ux = jx / (rf + rp), uy = jy / (rf + rp);
     const double ox = snap[k], oy = snap[nn + k], ot = snap[2 * nn + k];
     du = (ux - ox) * (ux - ox) + (uy - oy) * (uy - oy);
@@ -418,7 +437,7 @@ __global__ __launch_bounds__(256) void k_load_fields(StepParams P, FieldMap M, L
   d2prev[n] = make_float2(m.drp * P.invR, m.th);
 }
 
-template <bool ODD, class S, class I>
+template <bool ODD, class S, class I, int NL>
 __global__ __launch_bounds__(256) void k_export(StepParams P,
                                                 const typename S::T* __restrict__ pop,
                                                 const float* __restrict__ d5,
@@ -429,9 +448,9 @@ __global__ __launch_bounds__(256) void k_export(StepParams P,
   const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nn) return;
   const int x = (int)(k % P.nx), y = (int)(k / P.nx);
-  float f[9], p[9], g[9];
-  load_node<ODD, S, I>(P, pop, d5, x, y, f, p, g);
-  double rf = rho_f_ref, rp = rho_p_ref, jxf = 0, jyf = 0, jxp = 0, jyp = 0, th = 0;
+  float f[9], p[9], g[9], g2[NL == 4 ? 9 : 1];
+  load_node<ODD, S, I, NL>(P, pop, d5, x, y, f, p, g, g2);
+  double rf = rho_f_ref, rp = rho_p_ref, jxf = 0, jyf = 0, jxp = 0, jyp = 0;
   for (int i = 0; i < 9; ++i) {
     rf += (double)f[i];
     rp += (double)p[i];
@@ -439,15 +458,15 @@ __global__ __launch_bounds__(256) void k_export(StepParams P,
     jyf += (double)ey(i) * (double)f[i];
     jxp += (double)ex(i) * (double)p[i];
     jyp += (double)ey(i) * (double)p[i];
-    th += (double)g[i];
   }
+  const double3 th = node_thetas<NL>(g, g2, rp * invR, (double)P.crc);
   const double uxf = jxf / rf, uyf = jyf / rf;
   const bool empty = !(rp > 1e-12);
-  const double v[9] = {rf, uxf, uyf, rp * invR,
-                       empty ? uxf : jxp / rp, empty ? uyf : jyp / rp, th,
-                       (jxf + jxp) / (rf + rp), (jyf + jyp) / (rf + rp)};
+  const double v[MCLBM_FIELD_COUNT] = {rf, uxf, uyf, rp * invR,
+                                       empty ? uxf : jxp / rp, empty ? uyf : jyp / rp, th.z,
+                                       (jxf + jxp) / (rf + rp), (jyf + jyp) / (rf + rp), th.x, th.y};
   int slot = 0;
-  for (int b = 0; b < 9; ++b) {
+  for (int b = 0; b < MCLBM_FIELD_COUNT; ++b) {
     if ((mask >> b) & 1u) {
       out[(long long)slot * nn + k] = v[b];
       ++slot;
@@ -456,9 +475,9 @@ __global__ __launch_bounds__(256) void k_export(StepParams P,
 }
 
 // Populations after streaming with the storage shift added back; q < 0
-// writes all 27 planes, otherwise only plane q (lattice q / 9, direction
+// writes all 9 NL planes, otherwise only plane q (lattice q / 9, direction
 // q % 9) into out[0 .. nx*ny).
-template <bool ODD, class S, class I>
+template <bool ODD, class S, class I, int NL>
 __global__ __launch_bounds__(256) void k_export_pops(StepParams P,
                                                      const typename S::T* __restrict__ pop,
                                                      const float* __restrict__ d5,
@@ -468,23 +487,15 @@ __global__ __launch_bounds__(256) void k_export_pops(StepParams P,
   const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nn) return;
   const int x = (int)(k % P.nx), y = (int)(k / P.nx);
-  float f[9], p[9], g[9];
-  load_node<ODD, S, I>(P, pop, d5, x, y, f, p, g);
+  float f[9], p[9], g[9], g2[NL == 4 ? 9 : 1];
+  load_node<ODD, S, I, NL>(P, pop, d5, x, y, f, p, g, g2);
   for (int i = 0; i < 9; ++i) {
     const double w = wgt_d(i);
-    const double vf = (double)f[i] + w * rho_f_ref;
-    const double vp = (double)p[i] + w * rho_p_ref;
-    const double vg = (double)g[i];
-    if (q < 0) {
-      out[(long long)i * nn + k] = vf;
-      out[(long long)(9 + i) * nn + k] = vp;
-      out[(long long)(18 + i) * nn + k] = vg;
-    } else if (q == i) {
-      out[k] = vf;
-    } else if (q == 9 + i) {
-      out[k] = vp;
-    } else if (q == 18 + i) {
-      out[k] = vg;
+    const double v[4] = {(double)f[i] + w * rho_f_ref, (double)p[i] + w * rho_p_ref, (double)g[i],
+                         NL == 4 ? (double)g2[NL == 4 ? i : 0] : 0.0};
+    for (int l = 0; l < NL; ++l) {
+      if (q < 0) out[(long long)(9 * l + i) * nn + k] = v[l];
+      else if (q == 9 * l + i) out[k] = v[l];
     }
   }
 }
@@ -550,6 +561,8 @@ struct Layout {
 };
 
 int storage_bytes(int storage) { return storage == MCLBM_FP32S ? 4 : 2; }
+// lattices of a configuration: f, p and one or two thermal lattices
+int lattices(const mclbm_config& c) { return c.thermal_lattices == 2 ? 4 : 3; }
 
 Layout make_layout(const mclbm_config& c) {
   Layout L{};
@@ -558,11 +571,11 @@ Layout make_layout(const mclbm_config& c) {
   const long long nn = (long long)c.nx * c.ny;
   size_t off = 0;
   L.off_pop = off;
-  off = align_up(off + (size_t)27 * L.plane * storage_bytes(c.storage));
+  off = align_up(off + (size_t)9 * lattices(c) * L.plane * storage_bytes(c.storage));
   L.off_d2 = off;
   off = align_up(off + (size_t)2 * L.plane * sizeof(float2));
   L.off_d5 = off;
-  off = align_up(off + (size_t)6 * L.px * sizeof(float));
+  off = align_up(off + (size_t)6 * (lattices(c) - 2) * L.px * sizeof(float));
   L.off_snap = off;
   off = align_up(off + (size_t)3 * nn * sizeof(double));
   L.red_blocks = (int)((nn + 255) / 256);
@@ -599,6 +612,10 @@ int validate(const mclbm_config* c) {
   if (!finite_pos(p.rho) || !finite_pos(p.cp) || !finite_pos(p.k) || !std::isfinite(p.beta) || p.beta < 0.0)
     return fail(MCLBM_EINVAL, "particle rho, cp, k must be > 0 and beta >= 0");
   if (c->force_mask > MCLBM_F_ALL) return fail(MCLBM_EINVAL, "unknown force bits");
+  if (c->thermal_lattices < 0 || c->thermal_lattices > 2)
+    return fail(MCLBM_EINVAL, "thermal_lattices must be 0, 1 or 2");
+  if (c->thermal_lattices == 2 && c->storage != MCLBM_FP32S)
+    return fail(MCLBM_EUNSUPPORTED, "two thermal lattices need FP32 storage");
   for (int k = 0; k < 6; ++k)
     if (!std::isfinite(c->force_scale[k])) return fail(MCLBM_EINVAL, "force_scale must be finite");
   if (!std::isfinite(c->phi_perturb_amp) || c->phi_perturb_amp < 0.0)
@@ -688,6 +705,10 @@ StepParams make_params(const mclbm_config& c, const Derived& D, const Layout& L)
   P.rho_p0 = (float)v[MCLBM_D_RHO_P0];
   P.tau_f = (float)tau_f;
   P.omega_f = (float)(1.0 / tau_f);
+  P.nl = lattices(c);
+  // fluid thermal lattice (two thermal lattices): base-fluid diffusivity
+  P.tau_thf = (float)(3.0 * v[MCLBM_D_ALPHA_L] + 0.5);
+  P.omega_thf = (float)(1.0 / (3.0 * v[MCLBM_D_ALPHA_L] + 0.5));
   P.invR = (float)(1.0 / R);
   P.Rm1 = (float)(R - 1.0);
   P.crc = (float)(v[MCLBM_D_RHOC_RATIO] - 1.0);
@@ -783,25 +804,26 @@ int launch_check(const char* what) {
 // keeps its stores cached: they are shifted by one node, so the edge lines
 // of two neighbouring workgroups are each written half by either, and L2
 // merges the halves instead of sending two partial lines to HBM.
-template <class S_, class SE_, class SO_, class I_>
+template <class S_, class SE_, class SO_, class I_, int NL_ = 3>
 struct KTypes {
   using S = S_;
   using SE = SE_;
   using SO = SO_;
   using I = I_;
+  static constexpr int NL = NL_;  // lattices: 3, or 4 with two thermal lattices
 };
 
-template <template <bool, bool> class St, class Fn>
+template <template <bool, bool> class St, int NL = 3, class Fn>
 int dispatch_storage(bool idx32, bool nt, Fn&& fn) {
   using C = St<false, false>;
   using E = St<true, true>;
   using O = St<true, false>;
   if (idx32) {
-    if (nt) return fn(KTypes<C, E, O, uint32_t>{});
-    return fn(KTypes<C, C, C, uint32_t>{});
+    if (nt) return fn(KTypes<C, E, O, uint32_t, NL>{});
+    return fn(KTypes<C, C, C, uint32_t, NL>{});
   }
-  if (nt) return fn(KTypes<C, E, O, uint64_t>{});
-  return fn(KTypes<C, C, C, uint64_t>{});
+  if (nt) return fn(KTypes<C, E, O, uint64_t, NL>{});
+  return fn(KTypes<C, C, C, uint64_t, NL>{});
 }
 
 template <bool L, bool S>
@@ -823,6 +845,11 @@ int dispatch_kinds(int storage, bool idx32, bool nt, Fn&& fn) {
 
 template <class Fn>
 int dispatch(const mclbm_cavity* c, Fn&& fn) {
+  if (c->P.nl == 4) {
+    // two thermal lattices: FP32 storage only (checked at creation)
+    if (c->cfg.storage != MCLBM_FP32S) return fail(MCLBM_EUNSUPPORTED, "four lattices need FP32 storage");
+    return dispatch_storage<F32, 4>(c->idx32, c->nt, fn);
+  }
   return dispatch_kinds(c->cfg.storage, c->idx32, c->nt, fn);
 }
 
@@ -846,17 +873,17 @@ int enqueue_init(mclbm_cavity* c) {
   const double dev_f = c->D.v[MCLBM_D_RHO_F0] - (double)c->P.rho_f_ref;
   HIP_TRY(hipMemcpyAsync(c->stage(), c->host_dev_p.data(), (size_t)nn * sizeof(double),
                          hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(hipMemsetAsync(c->d5(), 0, (size_t)6 * c->L.px * sizeof(float), c->stream));
+  HIP_TRY(hipMemsetAsync(c->d5(), 0, (size_t)6 * (c->P.nl - 2) * c->L.px * sizeof(float), c->stream));
   int rc = dispatch(c, [&](auto k) {
     using S = typename decltype(k)::S;
     using I = typename decltype(k)::I;
     auto* pop = reinterpret_cast<typename S::T*>(c->pop());
     const dim3 b2(64, 4, 1), g2((cfg.nx + 63) / 64, (cfg.ny + 3) / 4, 1);
-    k_init<S><<<g2, b2, 0, c->stream>>>(c->P, pop, c->stage(), dev_f, c->d2(1));
+    k_init<S, decltype(k)::NL><<<g2, b2, 0, c->stream>>>(c->P, pop, c->stage(), dev_f, c->d2(1));
     int r = launch_check("k_init");
     if (r) return r;
     // snapshot of the initial state for the first residual call
-    k_residual<false, S, I><<<c->L.red_blocks, 256, 0, c->stream>>>(
+    k_residual<false, S, I, decltype(k)::NL><<<c->L.red_blocks, 256, 0, c->stream>>>(
         c->P, pop, c->d5(), (double)c->P.rho_f_ref, (double)c->P.rho_p_ref, c->snap(), c->part());
     return launch_check("k_residual");
   });
@@ -880,7 +907,7 @@ int setup_cavity(mclbm_cavity* c) {
   c->block = dim3(bx, by, 1);
   c->tiles_x = (c->cfg.nx + bx - 1) / bx;
   c->nblocks = (unsigned)c->tiles_x * (unsigned)((c->cfg.ny + by - 1) / by);
-  const size_t pop_bytes = (size_t)27 * c->L.plane * storage_bytes(c->cfg.storage);
+  const size_t pop_bytes = (size_t)9 * c->P.nl * c->L.plane * storage_bytes(c->cfg.storage);
   c->nt = pop_bytes + (size_t)2 * c->L.plane * sizeof(float2) > kStreamingBytes;
   c->idx32 = pop_bytes < ((size_t)1 << 31);
   return MCLBM_OK;
@@ -892,10 +919,10 @@ int launch_step(mclbm_cavity* c) {
   using T = typename K::S::T;
   auto* pop = reinterpret_cast<T*>(c->pop());
   if ((c->t & 1) == 0)
-    k_step<false, typename K::SE, I><<<c->nblocks, c->block, 0, c->stream>>>(c->P, pop, c->d2(1), c->d2(0),
+    k_step<false, typename K::SE, I, K::NL><<<c->nblocks, c->block, 0, c->stream>>>(c->P, pop, c->d2(1), c->d2(0),
                                                                            c->d5(), c->tiles_x);
   else
-    k_step<true, typename K::SO, I><<<c->nblocks, c->block, 0, c->stream>>>(c->P, pop, c->d2(0), c->d2(1),
+    k_step<true, typename K::SO, I, K::NL><<<c->nblocks, c->block, 0, c->stream>>>(c->P, pop, c->d2(0), c->d2(1),
                                                                           c->d5(), c->tiles_x);
   return launch_check("k_step");
 }
@@ -907,9 +934,9 @@ int export_pops(mclbm_cavity* c, int q, double* dev_out) {
     using I = typename decltype(k)::I;
     const auto* pop = reinterpret_cast<const typename S::T*>(c->pop());
     if (c->t & 1)
-      k_export_pops<true, S, I><<<node_blocks(c), 256, 0, c->stream>>>(c->P, pop, c->d5(), rf, rp, q, dev_out);
+      k_export_pops<true, S, I, decltype(k)::NL><<<node_blocks(c), 256, 0, c->stream>>>(c->P, pop, c->d5(), rf, rp, q, dev_out);
     else
-      k_export_pops<false, S, I><<<node_blocks(c), 256, 0, c->stream>>>(c->P, pop, c->d5(), rf, rp, q, dev_out);
+      k_export_pops<false, S, I, decltype(k)::NL><<<node_blocks(c), 256, 0, c->stream>>>(c->P, pop, c->d5(), rf, rp, q, dev_out);
     return launch_check("k_export_pops");
   });
 }
@@ -941,7 +968,7 @@ int enqueue_load_fields(mclbm_cavity* c, const float* F, int sx, int sy, int nc,
   K.alpha3 = 3.0 * c->D.v[MCLBM_D_ALPHA_L];
   K.Ck = c->D.v[MCLBM_D_CK];
   K.crc_m1 = c->D.v[MCLBM_D_RHOC_RATIO] - 1.0;
-  HIP_TRY(hipMemsetAsync(c->d5(), 0, (size_t)6 * c->L.px * sizeof(float), c->stream));
+  HIP_TRY(hipMemsetAsync(c->d5(), 0, (size_t)6 * (c->P.nl - 2) * c->L.px * sizeof(float), c->stream));
   k_load_sums<<<c->L.red_blocks, 256, 0, c->stream>>>(M, cfg.nx, cfg.ny, c->part());
   int rc = launch_check("k_load_sums");
   if (rc) return rc;
@@ -955,7 +982,7 @@ int enqueue_load_fields(mclbm_cavity* c, const float* F, int sx, int sy, int nc,
     k_load_fields<S><<<node_blocks(c), 256, 0, c->stream>>>(c->P, M, K, pop, c->res(), c->d2(1));
     int r = launch_check("k_load_fields");
     if (r) return r;
-    k_residual<false, S, I><<<c->L.red_blocks, 256, 0, c->stream>>>(
+    k_residual<false, S, I, decltype(k)::NL><<<c->L.red_blocks, 256, 0, c->stream>>>(
         c->P, pop, c->d5(), (double)c->P.rho_f_ref, (double)c->P.rho_p_ref, c->snap(), c->part());
     return launch_check("k_residual");
   });
@@ -993,6 +1020,7 @@ void mclbm_config_defaults(mclbm_config* c) {
   c->storage = MCLBM_FP32S;
   c->block_x = 0;
   c->block_y = 0;
+  c->thermal_lattices = 1;
 }
 
 size_t mclbm_device_bytes(const mclbm_config* cfg) {
@@ -1067,6 +1095,7 @@ int mclbm_load_fields(mclbm_cavity* c, const float* dev_fields, int32_t sx, int3
   if (c->in_batch && (!c->batch_clock || (*c->batch_clock & 1)))
     return fail(MCLBM_ESTATE, "load_fields: the batch is at an odd step; step it once more first");
   if (nc != 4 && nc != 5) return fail(MCLBM_EINVAL, "load_fields: nc must be 4 or 5");
+  if (c->P.nl != 3) return fail(MCLBM_EUNSUPPORTED, "load_fields: one thermal lattice only");
   if (sx < 1 || sy < 1 || (long long)sx * sy > (1LL << 30))
     return fail(MCLBM_EINVAL, "load_fields: source grid must be at least 1 x 1 and at most 2^30 cells");
   if (affine)
@@ -1093,7 +1122,7 @@ int64_t mclbm_time(const mclbm_cavity* c) { return c ? c->t : -1; }
 
 int mclbm_export_moments(mclbm_cavity* c, uint32_t mask, double* dev_out, size_t n_doubles) {
   if (!c || !dev_out) return fail(MCLBM_EINVAL, "NULL argument");
-  if (mask == 0 || mask > MCLBM_ALL_FIELDS) return fail(MCLBM_EINVAL, "bad field mask");
+  if (mask == 0 || mask > MCLBM_FIELD_MASK) return fail(MCLBM_EINVAL, "bad field mask");
   const long long nn = (long long)c->cfg.nx * c->cfg.ny;
   const int nf = __builtin_popcount(mask);
   if (n_doubles < (size_t)nf * nn) return fail(MCLBM_EINVAL, "output too small");
@@ -1104,16 +1133,16 @@ int mclbm_export_moments(mclbm_cavity* c, uint32_t mask, double* dev_out, size_t
     using I = typename decltype(k)::I;
     const auto* pop = reinterpret_cast<const typename S::T*>(c->pop());
     if (c->t & 1)
-      k_export<true, S, I><<<node_blocks(c), 256, 0, c->stream>>>(c->P, pop, c->d5(), rf, rp, invR, mask, dev_out);
+      k_export<true, S, I, decltype(k)::NL><<<node_blocks(c), 256, 0, c->stream>>>(c->P, pop, c->d5(), rf, rp, invR, mask, dev_out);
     else
-      k_export<false, S, I><<<node_blocks(c), 256, 0, c->stream>>>(c->P, pop, c->d5(), rf, rp, invR, mask, dev_out);
+      k_export<false, S, I, decltype(k)::NL><<<node_blocks(c), 256, 0, c->stream>>>(c->P, pop, c->d5(), rf, rp, invR, mask, dev_out);
     return launch_check("k_export");
   });
 }
 
 int mclbm_read_moments(mclbm_cavity* c, uint32_t mask, double* host_out, size_t n_doubles) {
   if (!c || !host_out) return fail(MCLBM_EINVAL, "NULL argument");
-  if (mask == 0 || mask > MCLBM_ALL_FIELDS) return fail(MCLBM_EINVAL, "bad field mask");
+  if (mask == 0 || mask > MCLBM_FIELD_MASK) return fail(MCLBM_EINVAL, "bad field mask");
   const long long nn = (long long)c->cfg.nx * c->cfg.ny;
   if (n_doubles < (size_t)__builtin_popcount(mask) * nn) return fail(MCLBM_EINVAL, "output too small");
   int slot = 0;
@@ -1133,15 +1162,15 @@ int mclbm_read_moments(mclbm_cavity* c, uint32_t mask, double* host_out, size_t 
 int mclbm_export_populations(mclbm_cavity* c, double* dev_out, size_t n_doubles) {
   if (!c || !dev_out) return fail(MCLBM_EINVAL, "NULL argument");
   const long long nn = (long long)c->cfg.nx * c->cfg.ny;
-  if (n_doubles < (size_t)27 * nn) return fail(MCLBM_EINVAL, "output too small");
+  if (n_doubles < (size_t)9 * c->P.nl * nn) return fail(MCLBM_EINVAL, "output too small");
   return export_pops(c, -1, dev_out);
 }
 
 int mclbm_read_populations(mclbm_cavity* c, double* host_out, size_t n_doubles) {
   if (!c || !host_out) return fail(MCLBM_EINVAL, "NULL argument");
   const long long nn = (long long)c->cfg.nx * c->cfg.ny;
-  if (n_doubles < (size_t)27 * nn) return fail(MCLBM_EINVAL, "output too small");
-  for (int q = 0; q < 27; ++q) {  // one plane at a time through the stage
+  if (n_doubles < (size_t)9 * c->P.nl * nn) return fail(MCLBM_EINVAL, "output too small");
+  for (int q = 0; q < 9 * c->P.nl; ++q) {  // one plane at a time through the stage
     int rc = export_pops(c, q, c->stage());
     if (rc) return rc;
     HIP_TRY(hipMemcpyAsync(host_out + (size_t)q * nn, c->stage(), (size_t)nn * sizeof(double),
@@ -1159,9 +1188,9 @@ int mclbm_nusselt(mclbm_cavity* c, double* nu_hot, double* nu_cold, double* nu_h
     using I = typename decltype(k)::I;
     const auto* pop = reinterpret_cast<const typename S::T*>(c->pop());
     if (c->t & 1)
-      k_nusselt<true, S, I><<<1, 256, 0, c->stream>>>(c->P, pop, c->d5(), rp, R, Ck, c->res());
+      k_nusselt<true, S, I, decltype(k)::NL><<<1, 256, 0, c->stream>>>(c->P, pop, c->d5(), rp, R, Ck, c->res());
     else
-      k_nusselt<false, S, I><<<1, 256, 0, c->stream>>>(c->P, pop, c->d5(), rp, R, Ck, c->res());
+      k_nusselt<false, S, I, decltype(k)::NL><<<1, 256, 0, c->stream>>>(c->P, pop, c->d5(), rp, R, Ck, c->res());
     return launch_check("k_nusselt");
   });
   if (rc) return rc;
@@ -1184,9 +1213,9 @@ int mclbm_residual(mclbm_cavity* c, double* res_u, double* res_theta) {
     using I = typename decltype(k)::I;
     const auto* pop = reinterpret_cast<const typename S::T*>(c->pop());
     if (c->t & 1)
-      k_residual<true, S, I><<<rb, 256, 0, c->stream>>>(c->P, pop, c->d5(), rf, rp, c->snap(), c->part());
+      k_residual<true, S, I, decltype(k)::NL><<<rb, 256, 0, c->stream>>>(c->P, pop, c->d5(), rf, rp, c->snap(), c->part());
     else
-      k_residual<false, S, I><<<rb, 256, 0, c->stream>>>(c->P, pop, c->d5(), rf, rp, c->snap(), c->part());
+      k_residual<false, S, I, decltype(k)::NL><<<rb, 256, 0, c->stream>>>(c->P, pop, c->d5(), rf, rp, c->snap(), c->part());
     return launch_check("k_residual");
   });
   if (rc) return rc;
@@ -1290,6 +1319,8 @@ int batch_layout(const mclbm_config* cfgs, int n, BatchLayout& B) {
     int rc = validate(&cfgs[k]);
     if (rc) return fail(rc, "cavity " + std::to_string(k) + ": " + g_err);
     if (cfgs[k].storage != cfgs[0].storage) return fail(MCLBM_EINVAL, "all cavities of a batch share the storage type");
+    if (cfgs[k].thermal_lattices == 2)
+      return fail(MCLBM_EUNSUPPORTED, "cavity " + std::to_string(k) + ": batches take one thermal lattice");
     int m = 0;
     for (const auto& sh : kShapes) m = std::max(m, tiles_of(cfgs[k].nx, cfgs[k].ny, sh[0], sh[1]));
     cap += m;

@@ -66,3 +66,59 @@ def test_ablation_sweep_batch_equals_single_runs_and_oracle():
     full = b.members[labels.index("all")].moments()["ux_p"]
     for lab in ("no_drag", "no_gravity", "no_thermophoresis"):
         assert not np.array_equal(b.members[labels.index(lab)].moments()["ux_p"], full), lab
+
+
+# ---- two thermal lattices (Eq 19 for each phase, Eq 33) -------------------
+
+@pytest.mark.parametrize("cfg,steps", [
+    (dict(nx=37, ny=29, Ra=5e4, phi0=0.03, dp_nm=40.0), 1001),
+    (dict(nx=70, ny=45, Ra=2e5, phi0=0.04, dp_nm=30.0, tau_f=-1.0), 1000),
+])
+def test_two_thermal_lattices_match_oracle(cfg, steps):
+    cfg = dict(cfg, thermal_lattices=2)
+    xi = inputs.phi_perturbation(90, cfg["nx"], cfg["ny"])
+    g, o = mc.Cavity(xi=xi, **cfg), oracle.Oracle(xi=xi, **cfg)
+    g.step(steps)
+    o.step(steps)
+    mg, mo = g.moments(), o.moments()
+    _close(mg, mo)
+    # the two phase temperatures differ (the reading is exercised)
+    assert np.abs(mo["theta_f"] - mo["theta_p"]).max() > 1e-4
+    ng, no = g.nusselt(), o.nusselt()
+    assert abs(ng[0] - no[0]) <= 1e-4 * abs(no[0])
+    res_g, res_o = g.residual(), o.residual()
+    assert abs(res_g[1] - res_o[1]) <= 1e-3 * res_o[1]
+
+
+@pytest.mark.parametrize("nsteps", [1, 2, 3])
+def test_two_thermal_lattices_first_steps_populations(nsteps):
+    """Every wall rule of both thermal lattices and both A-A parities, on
+    all 36 planes, to FP32 round-off of the largest deviation per lattice."""
+    cfg = dict(nx=16, ny=12, Ra=5e4, phi0=0.03, dp_nm=50.0, tau_f=0.7, thermal_lattices=2)
+    xi = inputs.phi_perturbation(3, 16, 12)
+    g, o = mc.Cavity(xi=xi, **cfg), oracle.Oracle(xi=xi, **cfg)
+    g.step(nsteps)
+    o.step(nsteps)
+    pg, po = g.populations(), o.populations()
+    assert pg.shape == po.shape == (4, 9, 12, 16)
+    d = o.derived()
+    w = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)[None, :, None, None]
+    rest = np.stack([w[0] * d["rho_f0"], w[0] * d["rho_p0"], w[0] * 0.0, w[0] * 0.0])
+    dev = np.abs(po - rest).reshape(4, -1).max(axis=1)[:, None, None, None]
+    err = (np.abs(pg - po) / dev).max(axis=(1, 2, 3))
+    assert (err < 1e-5).all(), err
+
+
+def test_two_thermal_lattices_unsupported_combinations():
+    L = mc.lib()
+    with pytest.raises(mc.MclbmError) as e:
+        mc.Cavity(nx=16, ny=16, thermal_lattices=2, storage=mc.FP16S)
+    assert e.value.code == mc.EUNSUPPORTED
+    with pytest.raises(mc.MclbmError, match="one thermal lattice"):
+        mc.Batch([dict(nx=16, ny=16), dict(nx=16, ny=16, thermal_lattices=2)])
+    c = mc.Cavity(nx=16, ny=16, thermal_lattices=2)
+    F = torch.zeros(4, 4, 4, device="cuda")
+    import ctypes
+    assert L.mclbm_load_fields(c._h, ctypes.c_void_p(F.data_ptr()), 4, 4, 4, None) == mc.EUNSUPPORTED
+    with pytest.raises(mc.MclbmError):
+        mc.Cavity(nx=16, ny=16, thermal_lattices=3)
