@@ -1146,7 +1146,7 @@ int mclbm_read_moments(mclbm_cavity* c, uint32_t mask, double* host_out, size_t 
   const long long nn = (long long)c->cfg.nx * c->cfg.ny;
   if (n_doubles < (size_t)__builtin_popcount(mask) * nn) return fail(MCLBM_EINVAL, "output too small");
   int slot = 0;
-  for (int b = 0; b < 9; ++b) {
+  for (int b = 0; b < MCLBM_FIELD_COUNT; ++b) {
     if (!((mask >> b) & 1u)) continue;
     int rc = mclbm_export_moments(c, 1u << b, c->stage(), (size_t)nn);
     if (rc) return rc;
