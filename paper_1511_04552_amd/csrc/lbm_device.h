@@ -216,20 +216,6 @@ __device__ __forceinline__ uint32_t soff(const StepParams& P, int q, int dx, int
 }
 
 // ---- read the nine populations of each lattice ------------------------------
-// Thermal lattice at planes tb (18 or 27), side-buffer block db (0 or 6 rows):
-// the same wall rules for either.
-template <bool ODD, class S>
-__device__ __forceinline__ float load_thermal32(const StepParams& P, __amdgpu_buffer_rsrc_t R, uint32_t vo,
-                                                const float* __restrict__ d5, int x, int i, int tb, int db,
-                                                bool xl, bool outx, bool outy) {
-  using T = typename S::T;
-  if (!ODD) return S::bld(R, vo, soff<T>(P, tb + i, 0, 0), P.inv_scale[2]);
-  if (!(outx || outy)) return S::bld(R, vo, soff<T>(P, tb + opp(i), -ex(i), -ey(i)), P.inv_scale[2]);
-  if (outy) return d5[(db + (ey(i) == 1 ? 0 : 3) + d5slot(i)) * P.px + x];
-  const float v = S::bld(R, vo, soff<T>(P, tb + i, 0, 0), P.inv_scale[2]);
-  return (xl ? wgt(i) : -wgt(i)) - v;
-}
-
 template <bool ODD, class S, class I, int NL = 3>
 __device__ __forceinline__ void load_node(const StepParams& P,
                                           const typename S::T* __restrict__ pop,
@@ -245,23 +231,37 @@ __device__ __forceinline__ void load_node(const StepParams& P,
     const uint32_t vo = (uint32_t)n * (uint32_t)sizeof(T);
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-      const bool outx = ODD && ((ex(i) == 1 && xl) || (ex(i) == -1 && xr));
-      const bool outy = ODD && ((ey(i) == 1 && yb) || (ey(i) == -1 && yt));
       if (!ODD) {
         f[i] = S::bld(R, vo, soff<T>(P, i, 0, 0), P.inv_scale[0]);
         p[i] = S::bld(R, vo, soff<T>(P, 9 + i, 0, 0), P.inv_scale[1]);
-      } else if (!(outx || outy)) {
-        // upstream node x - e_i, slot opp(i)
-        f[i] = S::bld(R, vo, soff<T>(P, opp(i), -ex(i), -ey(i)), P.inv_scale[0]);
-        p[i] = S::bld(R, vo, soff<T>(P, 9 + opp(i), -ex(i), -ey(i)), P.inv_scale[1]);
+        g[i] = S::bld(R, vo, soff<T>(P, 18 + i, 0, 0), P.inv_scale[2]);
+        if constexpr (NL == 4) g2[i] = S::bld(R, vo, soff<T>(P, 27 + i, 0, 0), P.inv_scale[2]);
       } else {
-        // wall link: own slot i (bounce-back); the thermal lattices by the
-        // wall rules
-        f[i] = S::bld(R, vo, soff<T>(P, i, 0, 0), P.inv_scale[0]);
-        p[i] = S::bld(R, vo, soff<T>(P, 9 + i, 0, 0), P.inv_scale[1]);
+        const bool outx = (ex(i) == 1 && xl) || (ex(i) == -1 && xr);
+        const bool outy = (ey(i) == 1 && yb) || (ey(i) == -1 && yt);
+        if (!(outx || outy)) {
+          // upstream node x - e_i, slot opp(i)
+          f[i] = S::bld(R, vo, soff<T>(P, opp(i), -ex(i), -ey(i)), P.inv_scale[0]);
+          p[i] = S::bld(R, vo, soff<T>(P, 9 + opp(i), -ex(i), -ey(i)), P.inv_scale[1]);
+          g[i] = S::bld(R, vo, soff<T>(P, 18 + opp(i), -ex(i), -ey(i)), P.inv_scale[2]);
+          if constexpr (NL == 4) g2[i] = S::bld(R, vo, soff<T>(P, 27 + opp(i), -ex(i), -ey(i)), P.inv_scale[2]);
+        } else {
+          // wall link: own slot i (bounce-back); the thermal lattices by
+          // the wall rules (side buffer block 6 l for thermal lattice l)
+          f[i] = S::bld(R, vo, soff<T>(P, i, 0, 0), P.inv_scale[0]);
+          p[i] = S::bld(R, vo, soff<T>(P, 9 + i, 0, 0), P.inv_scale[1]);
+#pragma unroll
+          for (int l = 0; l < NL - 2; ++l) {
+            float* h = l == 0 ? g : g2;
+            if (outy) {
+              h[i] = d5[(6 * l + (ey(i) == 1 ? 0 : 3) + d5slot(i)) * P.px + x];
+            } else {
+              const float v = S::bld(R, vo, soff<T>(P, 18 + 9 * l + i, 0, 0), P.inv_scale[2]);
+              h[i] = (xl ? wgt(i) : -wgt(i)) - v;
+            }
+          }
+        }
       }
-      g[i] = load_thermal32<ODD, S>(P, R, vo, d5, x, i, 18, 0, xl, outx, outy);
-      if constexpr (NL == 4) g2[i] = load_thermal32<ODD, S>(P, R, vo, d5, x, i, 27, 6, xl, outx, outy);
     }
     return;
   } else {
@@ -300,29 +300,6 @@ __device__ __forceinline__ void load_node(const StepParams& P,
 }
 
 // ---- write the post-collision populations -----------------------------------
-template <bool ODD, class S>
-__device__ __forceinline__ void store_thermal32(const StepParams& P, __amdgpu_buffer_rsrc_t R, uint32_t vo,
-                                                int i, int tb, float v, int y, bool yb, bool yt,
-                                                bool outx, bool outy) {
-  using T = typename S::T;
-  if (!ODD) {
-    S::bst(R, vo, soff<T>(P, tb + opp(i), 0, 0), v, P.scale[2]);
-  } else if (!(outx || outy)) {
-    // downstream node x + e_i, slot i
-    S::bst(R, vo, soff<T>(P, tb + i, ex(i), ey(i)), v, P.scale[2]);
-    // the wall row takes the same value (copy of the adiabatic wall)
-    if ((ey(i) == 1 && yb) || (ey(i) == -1 && yt)) S::bst(R, vo, soff<T>(P, tb + i, ex(i), 0), v, P.scale[2]);
-  } else if (!outy) {
-    // isothermal wall: anti-bounce-back into the own slot opp(i)
-    const float w = (ex(i) == -1 ? wgt(i) : -wgt(i)) - v;
-    S::bst(R, vo, soff<T>(P, tb + opp(i), 0, 0), w, P.scale[2]);
-    // corner: the wall row next to this one copies it
-    if (ey(opp(i)) == 1 && y == 1) S::bst(R, vo, soff<T>(P, tb + opp(i), 0, -1), w, P.scale[2]);
-    if (ey(opp(i)) == -1 && y == P.ny - 2) S::bst(R, vo, soff<T>(P, tb + opp(i), 0, 1), w, P.scale[2]);
-  }
-  // out through an adiabatic wall: the value leaves the domain
-}
-
 // side buffer for the adiabatic copy of the next (odd) step, block db
 __device__ __forceinline__ void store_side(const StepParams& P, float* __restrict__ d5, int db, int x, int y,
                                            const float g[9]) {
@@ -365,19 +342,45 @@ __device__ __forceinline__ void store_node(const StepParams& P,
     const uint32_t vo = (uint32_t)n * (uint32_t)sizeof(T);
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-      const bool outx = ODD && ((ex(i) == 1 && xr) || (ex(i) == -1 && xl));
-      const bool outy = ODD && ((ey(i) == 1 && yt) || (ey(i) == -1 && yb));
-      if (!ODD || outx || outy) {
-        // even step, or wall link: own slot opp(i)
+      if (!ODD) {
         S::bst(R, vo, soff<T>(P, opp(i), 0, 0), f[i], P.scale[0]);
         S::bst(R, vo, soff<T>(P, 9 + opp(i), 0, 0), p[i], P.scale[1]);
+        S::bst(R, vo, soff<T>(P, 18 + opp(i), 0, 0), g[i], P.scale[2]);
+        if constexpr (NL == 4) S::bst(R, vo, soff<T>(P, 27 + opp(i), 0, 0), g2[i], P.scale[2]);
       } else {
-        // downstream node x + e_i, slot i
-        S::bst(R, vo, soff<T>(P, i, ex(i), ey(i)), f[i], P.scale[0]);
-        S::bst(R, vo, soff<T>(P, 9 + i, ex(i), ey(i)), p[i], P.scale[1]);
+        const bool outx = (ex(i) == 1 && xr) || (ex(i) == -1 && xl);
+        const bool outy = (ey(i) == 1 && yt) || (ey(i) == -1 && yb);
+        if (!(outx || outy)) {
+          // downstream node x + e_i, slot i
+          S::bst(R, vo, soff<T>(P, i, ex(i), ey(i)), f[i], P.scale[0]);
+          S::bst(R, vo, soff<T>(P, 9 + i, ex(i), ey(i)), p[i], P.scale[1]);
+#pragma unroll
+          for (int l = 0; l < NL - 2; ++l) {
+            const float gv = l == 0 ? g[i] : g2[i];
+            S::bst(R, vo, soff<T>(P, 18 + 9 * l + i, ex(i), ey(i)), gv, P.scale[2]);
+            // the wall row takes the same value (copy of the adiabatic wall)
+            if ((ey(i) == 1 && yb) || (ey(i) == -1 && yt))
+              S::bst(R, vo, soff<T>(P, 18 + 9 * l + i, ex(i), 0), gv, P.scale[2]);
+          }
+        } else {
+          // wall link: own slot opp(i)
+          S::bst(R, vo, soff<T>(P, opp(i), 0, 0), f[i], P.scale[0]);
+          S::bst(R, vo, soff<T>(P, 9 + opp(i), 0, 0), p[i], P.scale[1]);
+          if (!outy) {
+#pragma unroll
+            for (int l = 0; l < NL - 2; ++l) {
+              // isothermal wall: anti-bounce-back into the own slot opp(i)
+              const float v = (ex(i) == -1 ? wgt(i) : -wgt(i)) - (l == 0 ? g[i] : g2[i]);
+              const int q = 18 + 9 * l + opp(i);
+              S::bst(R, vo, soff<T>(P, q, 0, 0), v, P.scale[2]);
+              // corner: the wall row next to this one copies it
+              if (ey(opp(i)) == 1 && y == 1) S::bst(R, vo, soff<T>(P, q, 0, -1), v, P.scale[2]);
+              if (ey(opp(i)) == -1 && y == ny - 2) S::bst(R, vo, soff<T>(P, q, 0, 1), v, P.scale[2]);
+            }
+          }
+          // out through an adiabatic wall: the value leaves the domain
+        }
       }
-      store_thermal32<ODD, S>(P, R, vo, i, 18, g[i], y, yb, yt, outx, outy);
-      if constexpr (NL == 4) store_thermal32<ODD, S>(P, R, vo, i, 27, g2[i], y, yb, yt, outx, outy);
     }
   } else {
 #pragma unroll
