@@ -398,6 +398,8 @@ class WarmStart:
         Y = torch.tensor(y, device=dev)
         rng = np.random.default_rng(self.seed)
         nb = n // self.B
+        xb = torch.empty((self.B,) + tuple(X.shape[1:]), dtype=torch.float32, device=dev)
+        yb = torch.empty((self.B,) + tuple(Y.shape[1:]), dtype=torch.float32, device=dev)
         total = epochs * nb
         hist = []
         it = 0
@@ -405,9 +407,10 @@ class WarmStart:
             perm = rng.permutation(n)
             acc = torch.zeros(1, dtype=torch.float64, device=dev)
             for j in range(nb):
-                idx = torch.tensor(perm[j * self.B:(j + 1) * self.B], device=dev)
-                xb = X.index_select(0, idx).contiguous()
-                yb = Y.index_select(0, idx).contiguous()
+                # the batch: device-to-device copies of whole samples
+                for q, k in enumerate(perm[j * self.B:(j + 1) * self.B]):
+                    xb[q].copy_(X[int(k)])
+                    yb[q].copy_(Y[int(k)])
                 self.net.forward(xb)
                 acc += self.net.backward(yb)
                 cur = lr_min + 0.5 * (lr - lr_min) * (1.0 + math.cos(math.pi * it / total))
