@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -893,6 +894,11 @@ int enqueue_init(mclbm_cavity* c) {
   return MCLBM_OK;
 }
 
+bool env_flag(const char* name) {
+  const char* v = std::getenv(name);
+  return v && v[0] == '1';
+}
+
 // Working sets above this size stream from HBM; below it they stay in the
 // 256 MB last-level (Infinity) cache, where non-temporal access hurts.
 constexpr size_t kStreamingBytes = 160u << 20;
@@ -910,6 +916,11 @@ int setup_cavity(mclbm_cavity* c) {
   const size_t pop_bytes = (size_t)9 * c->P.nl * c->L.plane * storage_bytes(c->cfg.storage);
   c->nt = pop_bytes + (size_t)2 * c->L.plane * sizeof(float2) > kStreamingBytes;
   c->idx32 = pop_bytes < ((size_t)1 << 31);
+  // Test knobs: the 64-bit index path and the streaming access policy are
+  // otherwise taken only by cavities above 2 GiB or 160 MiB; the results do
+  // not depend on either, which the tests check on small cavities.
+  if (env_flag("MCLBM_INDEX64")) c->idx32 = false;
+  if (env_flag("MCLBM_STREAMING")) c->nt = true;
   return MCLBM_OK;
 }
 

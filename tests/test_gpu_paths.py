@@ -1,0 +1,110 @@
+"""Code paths chosen by size: 64-bit element offsets (population arrays of
+2 GiB and more) and the streaming (non-temporal) access policy (working sets
+above the last-level cache).  Test knobs force either path on small
+cavities, where the results must be bitwise those of the default path; a
+cavity above 2 GiB is compared with the oracle directly."""
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import oracle  # noqa: E402
+import paper_1511_04552_amd as mc  # noqa: E402
+from paper_1511_04552_amd import inputs  # noqa: E402
+
+
+class _knobs:
+    def __init__(self, index64=False, streaming=False):
+        self.env = {"MCLBM_INDEX64": "1" if index64 else "0", "MCLBM_STREAMING": "1" if streaming else "0"}
+
+    def __enter__(self):
+        self.old = {k: os.environ.get(k) for k in self.env}
+        os.environ.update(self.env)
+
+    def __exit__(self, *a):
+        for k, v in self.old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+
+
+def _cavity(cfg, xi, steps, **knobs):
+    with _knobs(**knobs):
+        c = mc.Cavity(xi=xi, **cfg)
+    c.step(steps)
+    return c
+
+
+@pytest.mark.parametrize("cfg,tol", [
+    (dict(nx=37, ny=29, Ra=5e4, phi0=0.03, dp_nm=40.0), 1e-5),
+    (dict(nx=37, ny=29, Ra=5e4, phi0=0.03, dp_nm=40.0, thermal_lattices=2), 1e-5),
+    (dict(nx=40, ny=33, Ra=1e5, phi0=0.02, dp_nm=30.0, storage=mc.FP16S), 6e-3),
+])
+def test_index64_and_streaming_paths_match_oracle(cfg, tol):
+    """Each variant is its own kernel instantiation (the compiler may fuse
+    multiply-adds differently), so the bar is the parity bar against the
+    oracle (for FP16 storage its error bound), and the distance to the
+    default path is reported."""
+    xi = inputs.phi_perturbation(101, cfg["nx"], cfg["ny"])
+    o = oracle.Oracle(xi=xi, **{k: v for k, v in cfg.items() if k != "storage"})
+    o.step(1001)
+    mo = o.moments()
+    ref = _cavity(cfg, xi, 1001).moments()
+    for knobs in (dict(), dict(index64=True), dict(streaming=True), dict(index64=True, streaming=True)):
+        mg = _cavity(cfg, xi, 1001, **knobs).moments()
+        worst, to_default = 0.0, 0.0
+        for f in mo:
+            scale = np.abs(mo[f]).max()
+            if scale > 0:
+                worst = max(worst, np.abs(mg[f] - mo[f]).max() / scale)
+                to_default = max(to_default, np.abs(mg[f] - ref[f]).max() / scale)
+        print(cfg.get("storage", 0), cfg.get("thermal_lattices", 1), knobs,
+              f"vs oracle {worst:.2e}, vs default path {to_default:.2e}")
+        assert worst <= tol, (knobs, worst)
+
+
+def test_batch_index64_path_matches_single_runs():
+    cfgs = [dict(nx=37, ny=29, Ra=5e4, phi0=0.03, dp_nm=40.0), dict(nx=64, ny=48, Ra=2e5, phi0=0.01, dp_nm=80.0)]
+    xis = [inputs.phi_perturbation(110 + k, c["nx"], c["ny"]) for k, c in enumerate(cfgs)]
+    with _knobs(index64=True, streaming=True):
+        b = mc.Batch(cfgs, xis=xis)
+        singles = [mc.Cavity(xi=x, **c) for c, x in zip(cfgs, xis)]
+    b.step(301)
+    for m, s_ in zip(b.members, singles):
+        s_.step(301)
+        # same path and instantiation family: the batch member equals the
+        # single run of the same kernel variant bitwise
+        assert np.array_equal(m.populations(), s_.populations())
+
+
+@pytest.mark.slow
+def test_cavity_above_2gib_matches_oracle():
+    """4608^2 FP32: 2.29 GB of populations, so element offsets need 64 bits
+    and the accesses stream past the caches.  Three steps against the
+    oracle (every wall rule and both parities), and the particle mass.
+    Host memory: ~11 GB for the FP64 oracle."""
+    n = 4608
+    cfg = dict(nx=n, ny=n, Ra=1e6, phi0=0.04, dp_nm=30.0)
+    assert 27 * 4 * n * n > (1 << 31)
+    xi = inputs.phi_perturbation(4, n, n)
+    g = mc.Cavity(xi=xi, **cfg)
+    phi0 = g.moments("phi")["phi"].sum()
+    g.step(3)
+    o = oracle.Oracle(xi=xi, **cfg)
+    o.step(3)
+    # densities and theta (after three steps the velocities are ~1e-9,
+    # below what FP32 deviations resolve to 1e-5 of their size)
+    names = ("rho_f", "theta", "phi")
+    mg, mo = g.moments(names), o.moments(names)
+    del o
+    for f in names:
+        dev = np.abs(mo[f] - mo[f].mean()).max() if f != "theta" else np.abs(mo[f]).max()
+        assert np.abs(mg[f] - mo[f]).max() <= 1e-5 * dev, f
+    assert abs(mg["phi"].sum() - phi0) <= 1e-6 * phi0
