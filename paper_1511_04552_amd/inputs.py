@@ -53,6 +53,10 @@ WORKLOADS = {
                              tau_f=0.8, seed=4),
     "cavity160_paper": dict(nx=160, ny=160, Ra=1e6, Pr=8.923, phi0=0.04, dp_nm=33.0,
                             tau_f=0.8, seed=6),
+    # 1.8 GB of populations: seven times the 256 MB last-level cache, so
+    # every step streams from HBM (2048^2, 450 MB, is still partly cached)
+    "cavity4096_ra1e6": dict(nx=4096, ny=4096, Ra=1e6, Pr=6.2, phi0=0.04, dp_nm=30.0,
+                             tau_f=0.8, seed=7),
 }
 
 
