@@ -85,6 +85,8 @@ def lib():
         L.mclbm_oracle_read_moments.argtypes = [P, ctypes.c_uint32, D, ctypes.c_size_t]
         L.mclbm_oracle_read_populations.argtypes = [P, D, ctypes.c_size_t]
         L.mclbm_oracle_write_populations.argtypes = [P, D, ctypes.c_size_t]
+        L.mclbm_oracle_checkpoint.argtypes = [P, ctypes.c_char_p]
+        L.mclbm_oracle_restore.argtypes = [P, ctypes.c_char_p]
         L.mclbm_oracle_nusselt.argtypes = [P, D, D, D]
         L.mclbm_oracle_residual.argtypes = [P, D, D]
         L.mclbm_oracle_derived.argtypes = [P, D, ctypes.c_int]
@@ -210,6 +212,16 @@ class Oracle:
             raise RuntimeError(f"read_moments failed: {rc}")
         out = out.reshape(len(order), self.ny, self.nx)
         return {n: out[k] for k, n in enumerate(order)}
+
+    def checkpoint(self, path) -> None:
+        rc = lib().mclbm_oracle_checkpoint(self._h, str(path).encode())
+        if rc != 0:
+            raise RuntimeError(f"checkpoint failed: {rc}")
+
+    def restore(self, path) -> None:
+        rc = lib().mclbm_oracle_restore(self._h, str(path).encode())
+        if rc != 0:
+            raise ValueError(f"restore failed: {rc}")
 
     def write_populations(self, pops: np.ndarray) -> None:
         a = np.ascontiguousarray(pops, dtype=np.float64).reshape(-1)

@@ -28,6 +28,7 @@
 #include "mclbm_oracle.h"
 
 #include <math.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 #ifdef _OPENMP
@@ -805,6 +806,102 @@ int mclbm_oracle_write_populations(mo_state* o, const double* in,
   memcpy(o->g, in + 18 * o->nn, 9 * o->nn * sizeof(double));
   if (o->two_t) memcpy(o->g2, in + 27 * o->nn, 9 * o->nn * sizeof(double));
   init_lag_and_snapshot(o);
+  return MO_OK;
+}
+
+/* ---- checkpoint / resume (test infrastructure) ------------------------
+ * One line of JSON (format "mclbm-checkpoint", version, step count, parity,
+ * the configuration as raw bytes, the section sizes), then the FP64
+ * sections: f, p, g[, g2], the lag fields and the residual snapshot. */
+#define MO_CKPT_VERSION 1
+
+static void hex_of(const void* p, size_t n, char* out) {
+  static const char* d = "0123456789abcdef";
+  const unsigned char* b = (const unsigned char*)p;
+  for (size_t k = 0; k < n; ++k) {
+    out[2 * k] = d[b[k] >> 4];
+    out[2 * k + 1] = d[b[k] & 15];
+  }
+  out[2 * n] = 0;
+}
+
+static int ckpt_arrays(mo_state* o, double** arr, size_t* len) {
+  const size_t nn = o->nn;
+  int k = 0;
+  arr[k] = o->f; len[k++] = 9 * nn;
+  arr[k] = o->p; len[k++] = 9 * nn;
+  arr[k] = o->g; len[k++] = 9 * nn;
+  if (o->two_t) { arr[k] = o->g2; len[k++] = 9 * nn; }
+  arr[k] = o->phi_prev; len[k++] = nn;
+  arr[k] = o->th_prev; len[k++] = nn;
+  arr[k] = o->snap_ux; len[k++] = nn;
+  arr[k] = o->snap_uy; len[k++] = nn;
+  arr[k] = o->snap_th; len[k++] = nn;
+  return k;
+}
+
+int mclbm_oracle_checkpoint(mo_state* o, const char* path) {
+  if (!o || !path) return MO_EINVAL;
+  double* arr[9];
+  size_t len[9];
+  const int na = ckpt_arrays(o, arr, len);
+  char* cfg = malloc(2 * sizeof(mo_config) + 1);
+  if (!cfg) return MO_ENOMEM;
+  hex_of(&o->cfg, sizeof(mo_config), cfg);
+  FILE* fp = fopen(path, "wb");
+  if (!fp) { free(cfg); return MO_EINVAL; }
+  fprintf(fp, "{\"format\": \"mclbm-checkpoint\", \"version\": %d, \"payload\": \"fp64\", \"nx\": %d, \"ny\": %d, "
+              "\"t\": %lld, \"parity\": %d, \"config_hex\": \"%s\", \"sections\": %d, \"doubles\": %zu}\n",
+          MO_CKPT_VERSION, o->nx, o->ny, (long long)o->t, (int)(o->t & 1), cfg, na, 9 * (size_t)(na > 8 ? 4 : 3) * o->nn + 5 * o->nn);
+  free(cfg);
+  int ok = 1;
+  for (int k = 0; k < na && ok; ++k) ok = fwrite(arr[k], sizeof(double), len[k], fp) == len[k];
+  ok = (fclose(fp) == 0) && ok;
+  return ok ? MO_OK : MO_EINVAL;
+}
+
+int mclbm_oracle_restore(mo_state* o, const char* path) {
+  if (!o || !path) return MO_EINVAL;
+  FILE* fp = fopen(path, "rb");
+  if (!fp) return MO_EINVAL;
+  size_t cap = 4096 + 2 * sizeof(mo_config), n = 0;
+  char* h = malloc(cap + 1);
+  if (!h) { fclose(fp); return MO_ENOMEM; }
+  int ch;
+  while ((ch = fgetc(fp)) != EOF && ch != '\n' && n < cap) h[n++] = (char)ch;
+  h[n] = 0;
+  char* cfg = malloc(2 * sizeof(mo_config) + 1);
+  if (!cfg) { free(h); fclose(fp); return MO_ENOMEM; }
+  hex_of(&o->cfg, sizeof(mo_config), cfg);
+  int rc = MO_OK;
+  long long t = -1;
+  const char* tp = strstr(h, "\"t\": ");
+  if (!strstr(h, "\"format\": \"mclbm-checkpoint\"") || !strstr(h, "\"payload\": \"fp64\"") || !tp ||
+      !strstr(h, cfg))
+    rc = MO_EINVAL;
+  else
+    t = strtoll(tp + 5, NULL, 10);
+  free(cfg);
+  free(h);
+  if (rc != MO_OK || t < 0) { fclose(fp); return MO_EINVAL; }
+  double* arr[9];
+  size_t len[9];
+  const int na = ckpt_arrays(o, arr, len);
+  /* read into scratch first so that a short file leaves the state unchanged */
+  size_t total = 0;
+  for (int k = 0; k < na; ++k) total += len[k];
+  double* tmp = malloc(total * sizeof(double));
+  if (!tmp) { fclose(fp); return MO_ENOMEM; }
+  const int ok = fread(tmp, sizeof(double), total, fp) == total && fgetc(fp) == EOF;
+  fclose(fp);
+  if (!ok) { free(tmp); return MO_EINVAL; }
+  size_t off = 0;
+  for (int k = 0; k < na; ++k) {
+    memcpy(arr[k], tmp + off, len[k] * sizeof(double));
+    off += len[k];
+  }
+  free(tmp);
+  o->t = t;
   return MO_OK;
 }
 

@@ -116,6 +116,8 @@ int mclbm_oracle_derived(const mo_state* o, double* out, int n);
 void mclbm_oracle_equilibrium(double a, double ux, double uy, double out[9]);
 void mclbm_oracle_forcing(double Fx, double Fy, double out[9]);
 int mclbm_oracle_node_forces(const mo_state* o, const double* in, double* out);
+int mclbm_oracle_checkpoint(mo_state* o, const char* path);
+int mclbm_oracle_restore(mo_state* o, const char* path);
 void mclbm_oracle_destroy(mo_state* o);
 void mclbm_oracle_set_threads(int n);
 int mclbm_oracle_max_threads(void);
