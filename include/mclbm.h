@@ -229,6 +229,21 @@ int mclbm_residual(mclbm_cavity* c, double* res_u, double* res_theta);
 /* Derived lattice constants, MCLBM_D_COUNT doubles (enum slots). */
 int mclbm_derived(const mclbm_cavity* c, double* out, int n);
 
+/* Checkpoint / resume.  mclbm_checkpoint writes the complete state to the
+ * file `path`: one line of JSON (format "mclbm-checkpoint", version, the
+ * configuration in readable form and as raw bytes, the derived constants,
+ * the step count, parity, storage type and the byte size of each section),
+ * then the raw sections: populations (storage format, both A-A parities
+ * as stored), the two lag-field buffers, the adiabatic side buffer and the
+ * residual snapshot.  Sync.  A member of a batch may be checkpointed.
+ * mclbm_restore reads such a file into a cavity created with the identical
+ * configuration (MCLBM_EINVAL otherwise, or for a damaged or foreign file;
+ * the cavity is then unchanged); stepping then continues bitwise as the
+ * checkpointed run would have.  Not for batch members (MCLBM_ESTATE).
+ * Both return MCLBM_EHIP-free host errors as MCLBM_EINVAL with a message. */
+int mclbm_checkpoint(mclbm_cavity* c, const char* path);
+int mclbm_restore(mclbm_cavity* c, const char* path);
+
 /* Release the handle.  Does not free dev_buf.  Waits for the stream. */
 int mclbm_destroy(mclbm_cavity* c);
 

@@ -32,7 +32,8 @@ EXPORTED = ("mclbm_config_defaults", "mclbm_device_bytes", "mclbm_derive_constan
             "mclbm_set_properties", "mclbm_reset", "mclbm_load_fields", "mclbm_step", "mclbm_time",
             "mclbm_export_moments", "mclbm_read_moments", "mclbm_read_populations",
             "mclbm_export_populations", "mclbm_nusselt", "mclbm_residual",
-            "mclbm_derived", "mclbm_destroy", "mclbm_last_error", "mclbm_copy_kernel",
+            "mclbm_derived", "mclbm_checkpoint", "mclbm_restore", "mclbm_destroy", "mclbm_last_error",
+            "mclbm_copy_kernel",
             "mclbm_version", "mclbm_abi_version",
             "mclbm_batch_device_bytes", "mclbm_batch_create", "mclbm_batch_step",
             "mclbm_batch_set_graph_steps", "mclbm_batch_set_active", "mclbm_batch_residual",
@@ -93,6 +94,8 @@ def lib(load_torch: bool = True):
     L.mclbm_create.argtypes = [CP, D, P, ctypes.c_size_t, P, ctypes.POINTER(P)]
     L.mclbm_set_properties.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_double]
     L.mclbm_reset.argtypes = [P]
+    L.mclbm_checkpoint.argtypes = [P, ctypes.c_char_p]
+    L.mclbm_restore.argtypes = [P, ctypes.c_char_p]
     L.mclbm_load_fields.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, D]
     L.mclbm_step.argtypes = [P, ctypes.c_int64]
     L.mclbm_time.argtypes = [P]
@@ -254,6 +257,14 @@ class Cavity:
 
     def set_properties(self, Ra: float, phi0: float, dp_m: float) -> None:
         _check(lib().mclbm_set_properties(self._h, float(Ra), float(phi0), float(dp_m)))
+
+    def checkpoint(self, path) -> None:
+        """Write the complete state to ``path`` (JSON header line + raw sections)."""
+        _check(lib().mclbm_checkpoint(self._h, str(path).encode()))
+
+    def restore(self, path) -> None:
+        """Read a checkpoint of a cavity with the identical configuration."""
+        _check(lib().mclbm_restore(self._h, str(path).encode()))
 
     def load_fields(self, fields, affine=None) -> None:
         """Warm start from fields: a float32 device tensor (sy, sx, nc), nc = 4

@@ -1019,6 +1019,57 @@ int enqueue_load_fields(mclbm_cavity* c, const float* F, int sx, int sy, int nc,
 
 }  // namespace
 
+// ---- checkpoint / resume ----------------------------------------------------
+namespace {
+
+constexpr int kCkptVersion = 1;
+
+struct CkptSection {
+  const char* name;
+  size_t off, bytes;
+};
+
+std::vector<CkptSection> ckpt_sections(const mclbm_cavity* c) {
+  const long long nn = (long long)c->cfg.nx * c->cfg.ny;
+  return {
+      {"populations", c->L.off_pop, (size_t)9 * c->P.nl * c->L.plane * storage_bytes(c->cfg.storage)},
+      {"lag_fields", c->L.off_d2, (size_t)2 * c->L.plane * sizeof(float2)},
+      {"side_buffer", c->L.off_d5, (size_t)6 * (c->P.nl - 2) * c->L.px * sizeof(float)},
+      {"residual_snapshot", c->L.off_snap, (size_t)3 * nn * sizeof(double)},
+  };
+}
+
+std::string hex_of(const void* p, size_t n) {
+  static const char* d = "0123456789abcdef";
+  std::string s;
+  s.reserve(2 * n);
+  const unsigned char* b = static_cast<const unsigned char*>(p);
+  for (size_t k = 0; k < n; ++k) {
+    s.push_back(d[b[k] >> 4]);
+    s.push_back(d[b[k] & 15]);
+  }
+  return s;
+}
+
+std::string json_string_field(const std::string& h, const char* key) {
+  const std::string k = std::string("\"") + key + "\": \"";
+  const size_t a = h.find(k);
+  if (a == std::string::npos) return "";
+  const size_t b = h.find('"', a + k.size());
+  return b == std::string::npos ? "" : h.substr(a + k.size(), b - a - k.size());
+}
+
+bool json_number_field(const std::string& h, const char* key, long long& v) {
+  const std::string k = std::string("\"") + key + "\": ";
+  const size_t a = h.find(k);
+  if (a == std::string::npos) return false;
+  char* end = nullptr;
+  v = std::strtoll(h.c_str() + a + k.size(), &end, 10);
+  return end != h.c_str() + a + k.size();
+}
+
+}  // namespace
+
 // ===========================================================================
 // C ABI
 // ===========================================================================
@@ -1261,6 +1312,97 @@ int mclbm_residual(mclbm_cavity* c, double* res_u, double* res_theta) {
 int mclbm_derived(const mclbm_cavity* c, double* out, int n) {
   if (!c || !out || n < MCLBM_D_COUNT) return fail(MCLBM_EINVAL, "bad arguments");
   std::memcpy(out, c->D.v, sizeof(c->D.v));
+  return MCLBM_OK;
+}
+
+int mclbm_checkpoint(mclbm_cavity* c, const char* path) {
+  if (!c || !path) return fail(MCLBM_EINVAL, "checkpoint: NULL argument");
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  const auto secs = ckpt_sections(c);
+  std::string h = "{\"format\": \"mclbm-checkpoint\", \"version\": " + std::to_string(kCkptVersion) +
+                  ", \"abi\": " + std::to_string(MCLBM_ABI_VERSION);
+  char buf[256];
+  const mclbm_config& g = c->cfg;
+  std::snprintf(buf, sizeof buf, ", \"nx\": %d, \"ny\": %d, \"Ra\": %.17g, \"Pr\": %.17g, \"phi0\": %.17g, \"dp_m\": %.17g",
+                g.nx, g.ny, g.Ra, g.Pr, g.phi0, g.dp_m);
+  h += buf;
+  std::snprintf(buf, sizeof buf, ", \"tau_f\": %.17g, \"force_mask\": %u, \"storage\": %d, \"lattices\": %d",
+                g.tau_f, g.force_mask, g.storage, c->P.nl);
+  h += buf;
+  h += ", \"derived\": [";
+  for (int k = 0; k < MCLBM_D_COUNT; ++k) {
+    std::snprintf(buf, sizeof buf, "%s%.17g", k ? ", " : "", c->D.v[k]);
+    h += buf;
+  }
+  h += "], \"t\": " + std::to_string((long long)c->t) + ", \"parity\": " + std::to_string((int)(c->t & 1));
+  h += ", \"config_hex\": \"" + hex_of(&c->cfg, sizeof(mclbm_config)) + "\"";
+  h += ", \"xi_hex\": \"" + hex_of(c->xi.data(), c->xi.size() * sizeof(double)) + "\"";
+  h += ", \"sections\": [";
+  for (size_t k = 0; k < secs.size(); ++k)
+    h += std::string(k ? ", " : "") + "{\"name\": \"" + secs[k].name + "\", \"bytes\": " + std::to_string(secs[k].bytes) + "}";
+  h += "]}\n";
+  FILE* fp = std::fopen(path, "wb");
+  if (!fp) return fail(MCLBM_EINVAL, std::string("checkpoint: cannot open ") + path);
+  bool ok = std::fwrite(h.data(), 1, h.size(), fp) == h.size();
+  std::vector<char> host;
+  for (const auto& sc : secs) {
+    if (!ok) break;
+    host.resize(sc.bytes);
+    if (sc.bytes) {
+      hipError_t e = hipMemcpy(host.data(), c->base + sc.off, sc.bytes, hipMemcpyDeviceToHost);
+      if (e != hipSuccess) {
+        std::fclose(fp);
+        return hip_fail(e, "checkpoint: hipMemcpy");
+      }
+      ok = std::fwrite(host.data(), 1, sc.bytes, fp) == sc.bytes;
+    }
+  }
+  ok = (std::fclose(fp) == 0) && ok;
+  if (!ok) return fail(MCLBM_EINVAL, std::string("checkpoint: write failed: ") + path);
+  return MCLBM_OK;
+}
+
+int mclbm_restore(mclbm_cavity* c, const char* path) {
+  if (!c || !path) return fail(MCLBM_EINVAL, "restore: NULL argument");
+  if (c->in_batch) return fail(MCLBM_ESTATE, "restore: cavity belongs to a batch");
+  FILE* fp = std::fopen(path, "rb");
+  if (!fp) return fail(MCLBM_EINVAL, std::string("restore: cannot open ") + path);
+  std::string h;
+  for (int ch; (ch = std::fgetc(fp)) != EOF && ch != '\n';) {
+    h.push_back((char)ch);
+    if (h.size() > (64u << 20)) break;
+  }
+  long long ver = 0, t = 0;
+  const auto secs = ckpt_sections(c);
+  auto bad = [&](const std::string& why) {
+    std::fclose(fp);
+    return fail(MCLBM_EINVAL, "restore: " + why);
+  };
+  if (json_string_field(h, "format") != "mclbm-checkpoint" || !json_number_field(h, "version", ver) ||
+      ver != kCkptVersion)
+    return bad("not a checkpoint of this format");
+  if (json_string_field(h, "config_hex") != hex_of(&c->cfg, sizeof(mclbm_config)))
+    return bad("the configuration differs from the cavity's");
+  if (json_string_field(h, "xi_hex") != hex_of(c->xi.data(), c->xi.size() * sizeof(double)))
+    return bad("the initial perturbation field differs from the cavity's");
+  if (!json_number_field(h, "t", t) || t < 0) return bad("no step count");
+  for (const auto& sc : secs) {
+    const std::string key = std::string("{\"name\": \"") + sc.name + "\", \"bytes\": " + std::to_string(sc.bytes) + "}";
+    if (h.find(key) == std::string::npos) return bad(std::string("section size mismatch: ") + sc.name);
+  }
+  // read everything first, so that a short file leaves the cavity unchanged
+  std::vector<std::vector<char>> data(secs.size());
+  for (size_t k = 0; k < secs.size(); ++k) {
+    data[k].resize(secs[k].bytes);
+    if (secs[k].bytes && std::fread(data[k].data(), 1, secs[k].bytes, fp) != secs[k].bytes)
+      return bad("file too short");
+  }
+  if (std::fgetc(fp) != EOF) return bad("trailing bytes");
+  std::fclose(fp);
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  for (size_t k = 0; k < secs.size(); ++k)
+    if (secs[k].bytes) HIP_TRY(hipMemcpy(c->base + secs[k].off, data[k].data(), secs[k].bytes, hipMemcpyHostToDevice));
+  c->t = t;
   return MCLBM_OK;
 }
 

@@ -108,3 +108,56 @@ def test_cavity_above_2gib_matches_oracle():
         dev = np.abs(mo[f] - mo[f].mean()).max() if f != "theta" else np.abs(mo[f]).max()
         assert np.abs(mg[f] - mo[f]).max() <= 1e-5 * dev, f
     assert abs(mg["phi"].sum() - phi0) <= 1e-6 * phi0
+
+
+# ---- checkpoint / resume ----------------------------------------------------
+
+@pytest.mark.parametrize("cfg", [
+    dict(nx=37, ny=29, Ra=5e4, phi0=0.03, dp_nm=40.0),
+    dict(nx=37, ny=29, Ra=5e4, phi0=0.03, dp_nm=40.0, thermal_lattices=2),
+    dict(nx=40, ny=33, Ra=1e5, phi0=0.02, dp_nm=30.0, storage=mc.FP16S),
+])
+def test_checkpoint_resume_is_bitwise(tmp_path, cfg):
+    """Checkpoint at an odd step, destroy, restore into a new cavity and
+    continue: bitwise the uninterrupted run (populations, lag fields, side
+    buffer and residual snapshot all restored)."""
+    xi = inputs.phi_perturbation(120, cfg["nx"], cfg["ny"])
+    full = mc.Cavity(xi=xi, **cfg)
+    full.step(333)
+    full.residual()
+    full.step(400)
+    res_full = full.residual()
+    part = mc.Cavity(xi=xi, **cfg)
+    part.step(333)
+    part.residual()
+    path = tmp_path / "c.ckpt"
+    part.checkpoint(path)
+    del part
+    fresh = mc.Cavity(xi=xi, **cfg)
+    fresh.restore(path)
+    assert fresh.time == 333
+    fresh.step(400)
+    assert np.array_equal(fresh.populations(), full.populations())
+    assert fresh.residual() == res_full
+    assert fresh.nusselt() == full.nusselt()
+
+
+def test_restore_refuses_other_configs(tmp_path):
+    a = mc.Cavity(nx=16, ny=16, Ra=1e4)
+    a.step(3)
+    path = tmp_path / "a.ckpt"
+    a.checkpoint(path)
+    b = mc.Cavity(nx=16, ny=16, Ra=2e4)
+    with pytest.raises(mc.MclbmError):
+        b.restore(path)
+    short = tmp_path / "s.ckpt"
+    short.write_bytes(open(path, "rb").read()[:-4])
+    c = mc.Cavity(nx=16, ny=16, Ra=1e4)
+    before = c.populations()
+    with pytest.raises(mc.MclbmError):
+        c.restore(short)
+    assert np.array_equal(c.populations(), before) and c.time == 0
+    batch = mc.Batch([dict(nx=16, ny=16, Ra=1e4)] * 2)
+    batch.members[0].checkpoint(tmp_path / "m.ckpt")  # members may be checkpointed
+    with pytest.raises(mc.MclbmError):
+        batch.members[0].restore(tmp_path / "m.ckpt")
