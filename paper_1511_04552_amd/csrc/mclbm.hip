@@ -506,6 +506,12 @@ __global__ __launch_bounds__(256) void k_export_pops(StepParams P,
 // past the caches (the fastest of the simple forms measured on MI355X).
 typedef float v4f __attribute__((ext_vector_type(4)));
 constexpr int kCopyUnroll = 4;
+// Fill with quiet NaN (race check of the step kernel).
+__global__ __launch_bounds__(256) void k_poison(float* __restrict__ p, long long n) {
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long long)gridDim.x * blockDim.x)
+    p[k] = __builtin_nanf("");
+}
+
 __global__ __launch_bounds__(256) void k_copy(v4f* __restrict__ dst,
                                               const v4f* __restrict__ src,
                                               long long n) {
@@ -792,6 +798,7 @@ struct mclbm_cavity {
   bool nt;             // non-temporal population traffic
   bool idx32;          // 32-bit element offsets
   bool in_batch;       // owned by a batch: stepped only through it
+  bool poison;         // race check: NaN-fill what a step writes before it runs
   const int64_t* batch_clock;  // the owning batch's step count (members only)
   std::vector<double> host_dev_p;  // initial phi deviations (source of an async copy)
 
@@ -935,6 +942,7 @@ int setup_cavity(mclbm_cavity* c) {
   // not depend on either, which the tests check on small cavities.
   if (env_flag("MCLBM_INDEX64")) c->idx32 = false;
   if (env_flag("MCLBM_STREAMING")) c->nt = true;
+  c->poison = env_flag("MCLBM_POISON");
   return MCLBM_OK;
 }
 
@@ -943,6 +951,20 @@ int launch_step(mclbm_cavity* c) {
   using I = typename K::I;
   using T = typename K::S::T;
   auto* pop = reinterpret_cast<T*>(c->pop());
+  if (c->poison) {
+    // race check: what this step writes and must not read first is NaN
+    // (the lag field it stores; before an even step the side buffer the
+    // odd step reads), so a read before the write shows up in the results
+    const long long n2 = 2 * c->L.plane;
+    k_poison<<<(unsigned)std::min<long long>((n2 + 255) / 256, 65536), 256, 0, c->stream>>>(
+        reinterpret_cast<float*>(c->d2((c->t & 1) ? 1 : 0)), n2);
+    if ((c->t & 1) == 0) {
+      const long long n5 = 6LL * (c->P.nl - 2) * c->L.px;
+      k_poison<<<(unsigned)((n5 + 255) / 256), 256, 0, c->stream>>>(c->d5(), n5);
+    }
+    int r = launch_check("k_poison");
+    if (r) return r;
+  }
   if ((c->t & 1) == 0)
     k_step<false, typename K::SE, I, K::NL><<<c->nblocks, c->block, 0, c->stream>>>(c->P, pop, c->d2(1), c->d2(0),
                                                                            c->d5(), c->tiles_x);

@@ -20,8 +20,9 @@ from paper_1511_04552_amd import inputs  # noqa: E402
 
 
 class _knobs:
-    def __init__(self, index64=False, streaming=False):
-        self.env = {"MCLBM_INDEX64": "1" if index64 else "0", "MCLBM_STREAMING": "1" if streaming else "0"}
+    def __init__(self, index64=False, streaming=False, poison=False):
+        self.env = {"MCLBM_INDEX64": "1" if index64 else "0", "MCLBM_STREAMING": "1" if streaming else "0",
+                    "MCLBM_POISON": "1" if poison else "0"}
 
     def __enter__(self):
         self.old = {k: os.environ.get(k) for k in self.env}
@@ -161,3 +162,26 @@ def test_restore_refuses_other_configs(tmp_path):
     batch.members[0].checkpoint(tmp_path / "m.ckpt")  # members may be checkpointed
     with pytest.raises(mc.MclbmError):
         batch.members[0].restore(tmp_path / "m.ckpt")
+
+
+# ---- race check -------------------------------------------------------------
+
+@pytest.mark.parametrize("cfg", [
+    dict(nx=37, ny=29, Ra=5e4, phi0=0.03, dp_nm=40.0),
+    dict(nx=5, ny=4, Ra=1e4, phi0=0.02, dp_nm=50.0),
+    dict(nx=37, ny=29, Ra=5e4, phi0=0.03, dp_nm=40.0, thermal_lattices=2),
+    dict(nx=40, ny=33, Ra=1e5, phi0=0.02, dp_nm=30.0, storage=mc.FP16S),
+    dict(nx=300, ny=17, Ra=2e4, phi0=0.01, dp_nm=80.0, block_x=64, block_y=4),
+])
+def test_poisoned_buffers_are_never_read_before_written(cfg):
+    """Before every step the lag-field buffer the step writes (and, before
+    even steps, the side buffer the next odd step reads) is filled with NaN;
+    the run must equal the plain run bitwise, so no value is read before
+    the step has written it (no read-before-write race on either buffer)."""
+    xi = inputs.phi_perturbation(130, cfg["nx"], cfg["ny"])
+    ref = _cavity(cfg, xi, 201)
+    got = _cavity(cfg, xi, 201, poison=True)
+    p = got.populations()
+    assert np.isfinite(p).all()
+    assert np.array_equal(p, ref.populations())
+    assert got.nusselt() == ref.nusselt()
