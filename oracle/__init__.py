@@ -62,6 +62,7 @@ class Config(ctypes.Structure):
         ("body_force", ctypes.c_double * 2),
         ("u_f_init", ctypes.c_double * 2), ("u_p_init", ctypes.c_double * 2),
         ("thermal_lattices", ctypes.c_int32),
+        ("reading_flags", ctypes.c_uint32),
     ]
 
 

@@ -160,9 +160,11 @@ static int derive_setup(const mo_config* c, Setup* s) {
   {
     const double Re = c->fluid.rho * KB * c->T0 /
                       (3.0 * PI * c->fluid.mu * c->fluid.mu * c->fluid.d_mol);
-    s->Ck = 64.7 * pow(c->fluid.d_mol / c->dp, 0.369) *
-            pow(c->particle.k / c->fluid.k, 0.7476) * pow(c->Pr, 0.995) *
-            pow(Re, 1.2321);
+    /* alternative reading: the ratio as printed, k_f/k_p */
+    const double kr = (c->reading_flags & 1u) ? c->fluid.k / c->particle.k
+                                              : c->particle.k / c->fluid.k;
+    s->Ck = 64.7 * pow(c->fluid.d_mol / c->dp, 0.369) * pow(kr, 0.7476) *
+            pow(c->Pr, 0.995) * pow(Re, 1.2321);
   }
   s->rhoc_ratio = (c->particle.rho * c->particle.cp) /
                   (c->fluid.rho * c->fluid.cp);
@@ -282,10 +284,11 @@ static void node_physics(const mo_state* o, const NodeIn* in, NodeOut* r) {
   Ffx = c->body_force[0];
   Ffy = c->body_force[1] + rho_m * r_beta * s->G_L * in->theta;
 
-  if (s->s[5] != 0.0) {
+  if (s->s[5] != 0.0 && !(c->reading_flags & 2u)) {
     /* Reading: the settling force of Table 1 (particles) is referenced to
      * the uniform initial suspension; the fluid carries the opposite
-     * uniform weight so that the mixture feels only (phi - phi0). */
+     * uniform weight so that the mixture feels only (phi - phi0).  The
+     * alternative (flag 2) is Table 1 as printed: particles only. */
     Ffy += s->s[5] * s->rho_p0 * (1.0 - 1.0 / s->R) * s->grav_L;
   }
 
@@ -498,6 +501,7 @@ int mclbm_oracle_create(const mo_config* cfg, const double* xi,
     return MO_EINVAL;
   if (cfg->tau_f > 0.0 && !(cfg->tau_f > 0.5)) return MO_EINVAL;
   if (cfg->thermal_lattices < 0 || cfg->thermal_lattices > 2) return MO_EINVAL;
+  if (cfg->reading_flags & ~7u) return MO_EINVAL;
   mo_state* o = (mo_state*)calloc(1, sizeof(mo_state));
   if (!o) return MO_ENOMEM;
   o->cfg = *cfg;
@@ -633,12 +637,24 @@ static void collide_all(mo_state* o) {
       /* S6: BGK collisions, Eqs 18-19 with equilibria of Eqs 26-27.
        * Reading: f and p relax to their own velocities; g to the mixture
        * velocity of Eq 32. */
+      /* equilibrium velocities: each phase its own (R-4), or, as the
+       * alternative reading (flag 4), one common velocity for both, the
+       * average weighted by rho/tau (conserves the collision's momentum) */
+      double uef[2] = {r.ux_f, r.uy_f}, uep[2] = {r.ux_p, r.uy_p};
+      if (o->cfg.reading_flags & 4u) {
+        const double wf = in.rho_f / tau_f, wp = in.rho_p > 1e-12 ? in.rho_p / r.tau_p : 0.0;
+        for (int d = 0; d < 2; ++d) {
+          const double uc = (wf * (d ? r.uy_f : r.ux_f) + wp * (d ? r.uy_p : r.ux_p)) / (wf + wp);
+          uef[d] = uc;
+          uep[d] = uc;
+        }
+      }
       for (int i = 0; i < 9; ++i) {
         const size_t k = i * nn + n;
         const double fi = o->f[k], pi = o->p[k];
-        o->fs[k] = fi - (fi - equilibrium(i, in.rho_f, r.ux_f, r.uy_f)) / tau_f +
+        o->fs[k] = fi - (fi - equilibrium(i, in.rho_f, uef[0], uef[1])) / tau_f +
                    forcing(i, r.Ffx, r.Ffy);
-        o->ps[k] = pi - (pi - equilibrium(i, in.rho_p, r.ux_p, r.uy_p)) / r.tau_p +
+        o->ps[k] = pi - (pi - equilibrium(i, in.rho_p, uep[0], uep[1])) / r.tau_p +
                    forcing(i, r.Fpx, r.Fpy);
       }
       if (!o->two_t) {

@@ -67,6 +67,10 @@ typedef struct {
   /* 1 (0 means 1): one thermal lattice for the suspension; 2: Eq 19 for
    * each phase, the suspension temperature by Eq 33 */
   int32_t thermal_lattices;
+  /* alternative readings: 1 literal Eq 10a ratio k_f/k_p, 2 gravity on the
+   * particles only (no reference weight on the fluid), 4 one common
+   * equilibrium velocity for f and p weighted by rho/tau */
+  uint32_t reading_flags;
 } mo_config;
 
 /* Derived-constant slots returned by mclbm_oracle_derived. */
