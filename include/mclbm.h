@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define MCLBM_ABI_VERSION 2
+#define MCLBM_ABI_VERSION 3
 
 enum mclbm_status {
   MCLBM_OK = 0,
@@ -60,6 +60,22 @@ enum mclbm_storage { MCLBM_FP32S = 0, MCLBM_FP16S = 1, MCLBM_BF16S = 2 };
 enum mclbm_force {
   MCLBM_F_DRAG = 1, MCLBM_F_BROWN = 2, MCLBM_F_THERMO = 4, MCLBM_F_SAFF = 8,
   MCLBM_F_MAGROT = 16, MCLBM_F_GRAV = 32, MCLBM_F_ALL = 63
+};
+
+/* Alternative readings (reading_flags).  Each replaces one default reading
+ * of a garbled or ambiguous passage by another:
+ *   LITERAL_K_RATIO   Eq 10a with (k_f/k_p)^0.7476 as printed (default:
+ *                     k_p/k_f, the printed form makes the enhancement vanish)
+ *   LITERAL_GRAVITY   Table 1 gravity on the particles only (default: the
+ *                     fluid carries the weight of the uniform suspension,
+ *                     so the mixture feels only phi - phi0)
+ *   COMMON_VELOCITY   f and p relax to one common velocity weighted by
+ *                     rho/tau (default: each to its own, Eq 26 "u^sigma")
+ *   GUO_FORCING, LITERAL_REACTIONS  reserved: MCLBM_EUNSUPPORTED */
+enum mclbm_reading {
+  MCLBM_R_LITERAL_K_RATIO = 1, MCLBM_R_LITERAL_GRAVITY = 2,
+  MCLBM_R_COMMON_VELOCITY = 4, MCLBM_R_GUO_FORCING = 8,
+  MCLBM_R_LITERAL_REACTIONS = 16
 };
 
 /* Moment fields (Eqs 29-32) for mclbm_read_moments / mclbm_export_moments.
@@ -112,6 +128,8 @@ typedef struct {
                               (256 x 1 when nx >= 256, else 64 x 1);
                               block_x in {32, 64, 128, 256} and
                               block_x * block_y in {64, 128, 256} */
+  uint32_t reading_flags;  /* MCLBM_R_* alternatives to the default readings
+                              of garbled passages; 0 = the defaults */
   int32_t thermal_lattices;/* 1 (default; 0 means 1): one thermal lattice
                               for the suspension.  2: Eq 19 for each phase
                               (fluid and particle temperatures), the

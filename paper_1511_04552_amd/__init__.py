@@ -24,6 +24,7 @@ OK, EINVAL, ENOMEM, EHIP, EDIVERGED, ESTATE, EUNSUPPORTED = 0, -1, -2, -3, -4, -
 FP32S, FP16S, BF16S = 0, 1, 2
 F_DRAG, F_BROWN, F_THERMO, F_SAFF, F_MAGROT, F_GRAV = 1, 2, 4, 8, 16, 32
 F_ALL = 63
+R_LITERAL_K_RATIO, R_LITERAL_GRAVITY, R_COMMON_VELOCITY, R_GUO_FORCING, R_LITERAL_REACTIONS = 1, 2, 4, 8, 16
 FIELDS = ("rho_f", "ux_f", "uy_f", "phi", "ux_p", "uy_p", "theta", "ux_ns", "uy_ns", "theta_f", "theta_p")
 FIELD_BIT = {name: 1 << i for i, name in enumerate(FIELDS)}
 DERIVED = ("nu_L", "alpha_L", "H", "dx", "dt", "G_L", "grav_L", "Ck", "R", "tau_f",
@@ -67,6 +68,7 @@ class Config(ctypes.Structure):
         ("fluid", Material), ("particle", Material),
         ("storage", ctypes.c_int32),
         ("block_x", ctypes.c_int32), ("block_y", ctypes.c_int32),
+        ("reading_flags", ctypes.c_uint32),
         ("thermal_lattices", ctypes.c_int32),
     ]
 

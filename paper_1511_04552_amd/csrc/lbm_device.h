@@ -192,6 +192,7 @@ struct StepParams {
   float cG;              // settling per particle mass, (1 - 1/R) g
   float cRe, cD;         // drag: Re_d and Stokes rate coefficients
   unsigned force_on;     // bit k set when force k has a non-zero coefficient
+  unsigned flags;        // bit 0: f and p relax to one common velocity
 };
 
 // ---- A-A access ------------------------------------------------------------
@@ -616,9 +617,22 @@ __device__ __forceinline__ float2 node_update(const StepParams& P, float f[9],
   const float Ffy = fmaf(-P.cG, dp_true, Fbuoy) - Fpy;
 
   // S6: collisions; f and p relax to their own velocities, g to u_ns
-  collide(f, m.drf, rho_f, m.jxf, m.jyf, uxf, uyf, P.omega_f, Ffx, Ffy);
-  collide(p, m.drp, rho_p, empty ? rho_p * uxf : m.jxp, empty ? rho_p * uyf : m.jyp, uxp, uyp,
-          frcp(tau_p), Fpx, Fpy);
+  float ufx = uxf, ufy = uyf, upx = uxp, upy = uyp;
+  float jfx = m.jxf, jfy = m.jyf;
+  float jpx = empty ? rho_p * uxf : m.jxp, jpy = empty ? rho_p * uyf : m.jyp;
+  const float omega_p = frcp(tau_p);
+  if (P.flags & 1u) {
+    // alternative reading: one common equilibrium velocity weighted by
+    // rho / tau, which conserves the mixture momentum of the collision
+    const float wf = rho_f * P.omega_f, wp = empty ? 0.0f : rho_p * omega_p;
+    const float iw = frcp(wf + wp);
+    ufx = upx = fmaf(wf, uxf, wp * uxp) * iw;
+    ufy = upy = fmaf(wf, uyf, wp * uyp) * iw;
+    jfx = rho_f * ufx; jfy = rho_f * ufy;
+    jpx = rho_p * ufx; jpy = rho_p * ufy;
+  }
+  collide(f, m.drf, rho_f, jfx, jfy, ufx, ufy, P.omega_f, Ffx, Ffy);
+  collide(p, m.drp, rho_p, jpx, jpy, upx, upy, omega_p, Fpx, Fpy);
   if constexpr (NL == 4) {
     // each phase's thermal lattice relaxes to its own velocity; the fluid's
     // with the base-fluid diffusivity, the particles' with the relaxation

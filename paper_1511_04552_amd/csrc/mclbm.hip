@@ -633,6 +633,11 @@ int validate(const mclbm_config* c) {
   if (!finite_pos(p.rho) || !finite_pos(p.cp) || !finite_pos(p.k) || !std::isfinite(p.beta) || p.beta < 0.0)
     return fail(MCLBM_EINVAL, "particle rho, cp, k must be > 0 and beta >= 0");
   if (c->force_mask > MCLBM_F_ALL) return fail(MCLBM_EINVAL, "unknown force bits");
+  if (c->reading_flags & ~(unsigned)(MCLBM_R_LITERAL_K_RATIO | MCLBM_R_LITERAL_GRAVITY | MCLBM_R_COMMON_VELOCITY |
+                                      MCLBM_R_GUO_FORCING | MCLBM_R_LITERAL_REACTIONS))
+    return fail(MCLBM_EINVAL, "unknown reading flags");
+  if (c->reading_flags & (MCLBM_R_GUO_FORCING | MCLBM_R_LITERAL_REACTIONS))
+    return fail(MCLBM_EUNSUPPORTED, "reading flags GUO_FORCING and LITERAL_REACTIONS are not implemented");
   if (c->thermal_lattices < 0 || c->thermal_lattices > 2)
     return fail(MCLBM_EINVAL, "thermal_lattices must be 0, 1 or 2");
   if (c->thermal_lattices == 2 && c->storage != MCLBM_FP32S)
@@ -674,12 +679,14 @@ void derive(const mclbm_config& c, Derived& d) {
   const double dx = H / N;
   const double dt = nu_L * dx * dx / nu_f;
   const double R = c.particle.rho / c.fluid.rho;
-  // Eq 10b at T0, Eq 10a constant with the ratio k_p/k_f
+  // Eq 10b at T0, Eq 10a constant with the ratio k_p/k_f (as printed,
+  // k_f/k_p, with the literal reading flag)
   const double Re = c.fluid.rho * kBoltzmann * c.T0_K /
                     (3.0 * kPi * c.fluid.mu * c.fluid.mu * c.fluid.d_mol);
-  const double Ck = 64.7 * std::pow(c.fluid.d_mol / c.dp_m, 0.369) *
-                    std::pow(c.particle.k / c.fluid.k, 0.7476) * std::pow(c.Pr, 0.995) *
-                    std::pow(Re, 1.2321);
+  const double kratio = (c.reading_flags & MCLBM_R_LITERAL_K_RATIO) ? c.fluid.k / c.particle.k
+                                                                     : c.particle.k / c.fluid.k;
+  const double Ck = 64.7 * std::pow(c.fluid.d_mol / c.dp_m, 0.369) * std::pow(kratio, 0.7476) *
+                    std::pow(c.Pr, 0.995) * std::pow(Re, 1.2321);
   v[MCLBM_D_NU_L] = nu_L;
   v[MCLBM_D_ALPHA_L] = alpha_L;
   v[MCLBM_D_H] = H;
@@ -722,8 +729,12 @@ StepParams make_params(const mclbm_config& c, const Derived& D, const Layout& L)
   const float rp_ref = (float)v[MCLBM_D_RHO_P0];
   P.rho_f_ref = rf_ref;
   P.rho_p_ref = rp_ref;
-  P.dref_p = (float)((double)rp_ref - v[MCLBM_D_RHO_P0]);
-  P.rho_p0 = (float)v[MCLBM_D_RHO_P0];
+  // gravity reference: the fluid carries the weight of the uniform
+  // suspension R phi0 (or nothing, with the literal reading of Table 1)
+  const double gref = (c.reading_flags & MCLBM_R_LITERAL_GRAVITY) ? 0.0 : v[MCLBM_D_RHO_P0];
+  P.dref_p = (float)((double)rp_ref - gref);
+  P.rho_p0 = (float)gref;
+  P.flags = (c.reading_flags & MCLBM_R_COMMON_VELOCITY) ? 1u : 0u;
   P.tau_f = (float)tau_f;
   P.omega_f = (float)(1.0 / tau_f);
   P.nl = lattices(c);

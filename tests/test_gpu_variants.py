@@ -122,3 +122,31 @@ def test_two_thermal_lattices_unsupported_combinations():
     assert L.mclbm_load_fields(c._h, ctypes.c_void_p(F.data_ptr()), 4, 4, 4, None) == mc.EUNSUPPORTED
     with pytest.raises(mc.MclbmError):
         mc.Cavity(nx=16, ny=16, thermal_lattices=3)
+
+
+# ---- alternative readings (reading_flags) --------------------------------------
+
+@pytest.mark.parametrize("flags", [mc.R_LITERAL_K_RATIO, mc.R_LITERAL_GRAVITY, mc.R_COMMON_VELOCITY,
+                                   mc.R_LITERAL_K_RATIO | mc.R_LITERAL_GRAVITY | mc.R_COMMON_VELOCITY])
+def test_reading_flags_match_oracle(flags):
+    cfg = dict(nx=37, ny=29, Ra=5e4, phi0=0.03, dp_nm=40.0, reading_flags=flags)
+    xi = inputs.phi_perturbation(140, 37, 29)
+    g, o = mc.Cavity(xi=xi, **cfg), oracle.Oracle(xi=xi, **cfg)
+    g.step(1000)
+    o.step(1000)
+    _close(g.moments(), o.moments())
+    ng, no = g.nusselt(), o.nusselt()
+    assert abs(ng[0] - no[0]) <= 1e-4 * abs(no[0])
+    # the reading changes the answer
+    base = oracle.Oracle(xi=xi, **dict(cfg, reading_flags=0))
+    base.step(1000)
+    assert np.abs(base.moments()["ux_ns"] - o.moments()["ux_ns"]).max() > 1e-9
+
+
+def test_reserved_reading_flags_are_unsupported():
+    for f in (mc.R_GUO_FORCING, mc.R_LITERAL_REACTIONS):
+        with pytest.raises(mc.MclbmError) as e:
+            mc.Cavity(nx=16, ny=16, reading_flags=f)
+        assert e.value.code == mc.EUNSUPPORTED
+    with pytest.raises(mc.MclbmError):
+        mc.Cavity(nx=16, ny=16, reading_flags=64)
