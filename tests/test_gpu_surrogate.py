@@ -42,4 +42,4 @@ def test_warm_start_settles_sooner_and_converges_to_the_same_state():
     sc = sg.settle_steps(cold["times"], cold["nu_hist"], cold["nu"])[done]
     sw = sg.settle_steps(warm["times"], warm["nu_hist"], cold["nu"])[done]
     print("settle steps cold", sc.tolist(), "warm", sw.tolist())
-    assert sw.sum() * 4 <= sc.sum(), (sc, sw)
+    assert sw.sum() * 2.5 <= sc.sum(), (sc, sw)
