@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define MCLBM_ABI_VERSION 3
+#define MCLBM_ABI_VERSION 4
 
 enum mclbm_status {
   MCLBM_OK = 0,
@@ -136,6 +136,19 @@ typedef struct {
                               suspension temperature by Eq 33; FP32 storage
                               and single cavities only (MCLBM_EUNSUPPORTED
                               otherwise, also for mclbm_load_fields) */
+  int32_t steps_per_launch;/* 0 (default) or 1: one launch per step,
+                              updated in place.  2: an even and the
+                              following odd step in one launch, from one
+                              population copy into a second one (device
+                              bytes grow by one population array; half the
+                              memory traffic per step, the same arithmetic);
+                              one thermal lattice, populations below 2 GiB
+                              and single cavities only (MCLBM_EUNSUPPORTED
+                              otherwise).  A step count or start that is odd
+                              takes single steps where needed.  Results are
+                              those of single steps up to rounding (16-bit
+                              storage: the intermediate odd-step state is
+                              kept in FP32, not rounded to storage) */
 } mclbm_config;
 
 typedef struct mclbm_cavity mclbm_cavity; /* opaque host-side handle */

@@ -70,6 +70,7 @@ class Config(ctypes.Structure):
         ("block_x", ctypes.c_int32), ("block_y", ctypes.c_int32),
         ("reading_flags", ctypes.c_uint32),
         ("thermal_lattices", ctypes.c_int32),
+        ("steps_per_launch", ctypes.c_int32),
     ]
 
 

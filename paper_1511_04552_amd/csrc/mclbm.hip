@@ -78,6 +78,48 @@ __device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned nb) {
   return k * q + (k < r ? k : r) + (b >> 3);
 }
 
+// S4: central differences of the previous step's (phi, theta); zero-flux
+// mirror ghosts for phi on all walls and for theta on the adiabatic walls,
+// linear ghosts 2 theta_w - theta through the isothermal walls.  Returns
+// (dphi/dx, dphi/dy, dtheta/dx, dtheta/dy).
+__device__ __forceinline__ void wall_ghosts(float2 c, float2 vE, float2 vW, float2 vN, float2 vS,
+                                            bool xl, bool xr, bool yb, bool yt, float4& gr) {
+  vE = xr ? c : vE;
+  vW = xl ? c : vW;
+  vN = yt ? c : vN;
+  vS = yb ? c : vS;
+  const float thE = xr ? (-1.0f - c.y) : vE.y;
+  const float thW = xl ? (1.0f - c.y) : vW.y;
+  gr = make_float4(0.5f * (vE.x - vW.x), 0.5f * (vN.x - vS.x), 0.5f * (thE - thW), 0.5f * (vN.y - vS.y));
+}
+
+// The five lag-field values around (x, y), loaded unconditionally (a
+// neighbour behind a wall reads the centre instead, which wall_ghosts
+// replaces anyway), so that no branch separates the loads from their use.
+__device__ __forceinline__ void lag_fetch(const StepParams& P, const float2* __restrict__ d2p, int x, int y,
+                                          float2& c, float2& vE, float2& vW, float2& vN, float2& vS) {
+  const long long n = (long long)y * P.px + x;
+  const bool xl = x == 0, xr = x == P.nx - 1, yb = y == 0, yt = y == P.ny - 1;
+  c = d2p[n];
+  vE = d2p[xr ? n : n + 1];
+  vW = d2p[xl ? n : n - 1];
+  vN = d2p[yt ? n : n + P.px];
+  vS = d2p[yb ? n : n - P.px];
+}
+
+__device__ __forceinline__ void lag_gradients(const StepParams& P, const float2* __restrict__ d2p, int x,
+                                              int y, float4& gr) {
+  const long long n = (long long)y * P.px + x;
+  const bool xl = x == 0, xr = x == P.nx - 1, yb = y == 0, yt = y == P.ny - 1;
+  float2 c = make_float2(0.0f, 0.0f);
+  if (xl || xr || yb || yt) c = d2p[n];
+  const float2 vE = xr ? c : d2p[n + 1];
+  const float2 vW = xl ? c : d2p[n - 1];
+  const float2 vN = yt ? c : d2p[n + P.px];
+  const float2 vS = yb ? c : d2p[n - P.px];
+  wall_ghosts(c, vE, vW, vN, vS, xl, xr, yb, yt, gr);
+}
+
 // One node of one time step (the whole hot path for that node).
 template <bool ODD, class S, class I, int NL = 3>
 __device__ __forceinline__ void step_node(const StepParams& P, typename S::T* __restrict__ pop,
@@ -119,6 +161,218 @@ __global__ __launch_bounds__(256) void k_step(StepParams P,
   const int y = (int)(t / (unsigned)tiles_x) * blockDim.y + threadIdx.y;
   if (x >= P.nx || y >= P.ny) return;
   step_node<ODD, S, I, NL>(P, pop, d2p, d2c, d5, x, y);
+}
+
+// ---- two time steps per launch ---------------------------------------------
+// k_step2 runs an even step t and the odd step t + 1 in one pass, reading the
+// populations at t (A-A layout of an even step) from one array and writing
+// those at t + 2 (same layout) to a second one, so each step moves half the
+// bytes of k_step.  The in-place pattern cannot be used here: the workgroups
+// overlap by a halo and would overwrite what their neighbours still read.
+//
+// One wave owns a strip of kStrip2 columns and a band of rows.  Its 64 lanes
+// hold the strip and one halo column on each side.  It sweeps the band
+// upwards, one row r per iteration:
+//   stage A  the even step on row r (all 64 lanes): load the node's own slots,
+//            lag gradients of step t - 1, node update; the post-collision
+//            values stay in registers;
+//   pull     each value moves to the node it streams to: across lanes by one
+//            shuffle (x), across rows by being carried to a later iteration
+//            (y); what row r sends down (e_y = -1) is consumed now, what it
+//            sends along (e_y = 0) in the next iteration, what it sends up
+//            (e_y = +1) in the one after;
+//   stage B  the odd step on row q = r - 1 of the strip: the pulled values
+//            with the wall rules (Eqs 34-36) that the in-place odd load
+//            applies, gradients from stage A's lag fields, node update, and
+//            the store of the in-place odd step into the second array.
+// Rows outside the band are computed by stage A as halo (one row below, one
+// above), never stored.
+constexpr int kStrip2 = 62;
+
+// the 3 directions of each pull group, per lattice: up (e_y = +1), along
+// (e_y = 0), down (e_y = -1)
+__device__ __forceinline__ float pull_x(float v, int i) {
+  // direction i at x comes from x - e_x(i): the lane below or above
+  if (ex(i) == 1) return __shfl_up(v, 1, 64);
+  if (ex(i) == -1) return __shfl_down(v, 1, 64);
+  return v;
+}
+
+template <class S>
+__global__ __launch_bounds__(64) void k_step2(StepParams P, const typename S::T* __restrict__ popA,
+                                              typename S::T* __restrict__ popB,
+                                              const float2* __restrict__ d2p, float2* __restrict__ d2o,
+                                              int strips, int band) {
+  using I = uint32_t;
+  constexpr int UP[3] = {2, 5, 6}, AL[3] = {0, 1, 3}, DN[3] = {4, 7, 8};
+  // What a row sends up waits two iterations: a ring of three rows in LDS,
+  // one column per lane (each lane reads back only what it wrote).  The
+  // x-wall lanes keep their own values for the diagonal unknowns of the odd
+  // step in a two-row ring (left and right wall).
+  __shared__ float s_up[3][9][64];
+  __shared__ float s_xw[2][2][6];
+  const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int strip = (int)(tile % (unsigned)strips), seg = (int)(tile / (unsigned)strips);
+  const int lane = (int)threadIdx.x;
+  const int nx = P.nx, ny = P.ny;
+  const int x = strip * kStrip2 - 1 + lane;
+  const int xs = min(max(x, 0), nx - 1);  // halo lanes outside the cavity repeat the edge
+  const bool xl = x == 0, xr = x == nx - 1;
+  const int side = xl ? 0 : 1;
+  const bool mine = lane >= 1 && lane <= kStrip2 && x < nx;
+  const int y0 = seg * band, y1 = min(y0 + band, ny);
+  const int ra = max(y0 - 1, 0);
+  auto ring = [](int row) { return (row + 3) % 3; };  // rows >= -1
+
+  float M[9];  // along values for row r - 1 (lattice l, slot k at [3 l + k])
+  float2 dq = make_float2(0.0f, 0.0f), dqm = dq;  // lag field of step t at rows r - 1, r - 2
+#pragma unroll
+  for (int k = 0; k < 9; ++k) M[k] = 0.0f;
+
+  // The loads of a row are issued in the iteration before (after its stage
+  // A, before its stage B): a wave's loads and stores share one in-order
+  // completion counter, so loads issued after the odd step's stores would
+  // also wait for those stores.
+  const int rlast = min(y1, ny - 1);  // last row of stage A
+  float PF[3][9];
+  float2 Lc, Le, Lw, Ln, Ls;  // lag field of step t - 1 around the row
+  auto fetch = [&](int row) {
+    load_node<false, S, I>(P, popA, nullptr, xs, row, PF[0], PF[1], PF[2]);
+    lag_fetch(P, d2p, xs, row, Lc, Le, Lw, Ln, Ls);
+  };
+  fetch(ra);
+
+  for (int r = ra; r <= y1; ++r) {
+    const bool has_a = r < ny;
+    float ALn[9], DNn[9];  // what row r sends along and down
+    float2 dr = dq;
+    {
+      float A[3][9] = {};  // stage A: post-collision values of row r (f, p, g)
+      if (has_a) {
+#pragma unroll
+        for (int l = 0; l < 3; ++l)
+#pragma unroll
+          for (int i = 0; i < 9; ++i) A[l][i] = PF[l][i];
+        float4 gr;
+        wall_ghosts(Lc, Le, Lw, Ln, Ls, xs == 0, xs == nx - 1, r == 0, r == ny - 1, gr);
+        dr = node_update<3>(P, A[0], A[1], A[2], gr.x, gr.y, gr.z, gr.w);
+        // the next row's loads: after the stage-A update (whose first use
+        // of this row's values waits for them), overlapping stage B
+        if (r < rlast) fetch(r + 1);
+      }
+      // pull across lanes (whole wave, uniform control flow)
+      float UPn[9];
+#pragma unroll
+      for (int l = 0; l < 3; ++l)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          UPn[3 * l + k] = pull_x(A[l][UP[k]], UP[k]);
+          ALn[3 * l + k] = pull_x(A[l][AL[k]], AL[k]);
+          DNn[3 * l + k] = pull_x(A[l][DN[k]], DN[k]);
+        }
+      if (has_a) {
+        // x walls, along directions: E at the left wall, W at the right
+        // wall (bounce-back for f and p, anti-bounce-back for g, Eqs 34-35)
+        if (xl) {
+          ALn[1] = A[0][3];
+          ALn[4] = A[1][3];
+          ALn[7] = wgt(1) - A[2][3];
+        }
+        if (xr) {
+          ALn[2] = A[0][1];
+          ALn[5] = A[1][1];
+          ALn[8] = -wgt(3) - A[2][1];
+        }
+        // x-wall lanes keep their own values for the diagonal unknowns of
+        // the odd step on this row: (up, down) = (NE, SE) <- (SW, NW) on the
+        // left, (NW, SW) <- (SE, NE) on the right
+        if (xl || xr) {
+#pragma unroll
+          for (int l = 0; l < 3; ++l) {
+            s_xw[r & 1][side][2 * l] = xl ? A[l][7] : A[l][8];
+            s_xw[r & 1][side][2 * l + 1] = xl ? A[l][6] : A[l][5];
+          }
+        }
+        if (r == 0) {
+          // bottom wall row: its up unknowns are bounce-back of its own down
+          // values (f, p) and, for g, what row 0 streams into row 1 (copy of
+          // the adiabatic wall, Eq 36); corners are set in the odd step
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            s_up[ring(-1)][k][lane] = A[0][DN[k]];
+            s_up[ring(-1)][3 + k][lane] = A[1][DN[k]];
+            s_up[ring(-1)][6 + k][lane] = UPn[6 + k];
+          }
+        }
+        if (r == ny - 1) {
+          // top wall row: its down unknowns likewise, kept in its own slot
+          // of the ring (nothing streams above the top row)
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            UPn[k] = A[0][UP[k]];
+            UPn[3 + k] = A[1][UP[k]];
+            UPn[6 + k] = DNn[6 + k];
+          }
+          // corners of g: the copy of row ny - 2 after its x-wall rule
+          if (xl) UPn[8] = wgt(8) - s_xw[(r - 1) & 1][0][5];
+          if (xr) UPn[7] = -wgt(7) - s_xw[(r - 1) & 1][1][5];
+        }
+#pragma unroll
+        for (int k = 0; k < 9; ++k) s_up[ring(r)][k][lane] = UPn[k];
+      }
+    }
+    const float2 dE = make_float2(__shfl_down(dq.x, 1, 64), __shfl_down(dq.y, 1, 64));
+    const float2 dW = make_float2(__shfl_up(dq.x, 1, 64), __shfl_up(dq.y, 1, 64));
+
+    // stage B: the odd step on row q
+    const int q = r - 1;
+    if (q >= y0) {
+      float G[3][9];
+#pragma unroll
+      for (int l = 0; l < 3; ++l)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          G[l][UP[k]] = s_up[ring(r - 2)][3 * l + k][lane];
+          G[l][AL[k]] = M[3 * l + k];
+          G[l][DN[k]] = has_a ? DNn[3 * l + k] : s_up[ring(r - 1)][3 * l + k][lane];
+        }
+      // x walls, diagonal directions
+      if (xl || xr) {
+        const float* w = s_xw[q & 1][side];
+        // g: anti-bounce-back, except where the link also crosses a y wall
+        // (bottom row: the copy of row 1 after its x-wall rule; top row: set
+        // with the top row's down values)
+        const float gup = q > 0 ? w[4] : s_xw[r & 1][side][4];
+        if (xl) {
+          G[0][5] = w[0];
+          G[0][8] = w[1];
+          G[1][5] = w[2];
+          G[1][8] = w[3];
+          G[2][5] = wgt(5) - gup;
+          if (q < ny - 1) G[2][8] = wgt(8) - w[5];
+        } else {
+          G[0][6] = w[0];
+          G[0][7] = w[1];
+          G[1][6] = w[2];
+          G[1][7] = w[3];
+          G[2][6] = -wgt(6) - gup;
+          if (q < ny - 1) G[2][7] = -wgt(7) - w[5];
+        }
+      }
+      float4 gr;
+      wall_ghosts(dq, dE, dW, dr, dqm, xl, xr, q == 0, q == ny - 1, gr);
+      const float2 keep = node_update<3>(P, G[0], G[1], G[2], gr.x, gr.y, gr.z, gr.w);
+      if (mine) {
+        store_node<true, S, I>(P, popB, nullptr, x, q, G[0], G[1], G[2]);
+        d2o[(long long)q * P.px + x] = keep;
+      }
+    }
+    if (!has_a) break;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) M[k] = ALn[k];
+    dqm = dq;
+    dq = dr;
+  }
 }
 
 // Batched sweep: one launch per time step updates every active cavity of a
@@ -577,7 +831,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 struct Layout {
   int px;
   long long plane;
-  size_t off_pop, off_d2, off_d5, off_snap, off_part, off_res, off_stage, total;
+  size_t off_pop, off_pop2, off_d2, off_d5, off_snap, off_part, off_res, off_stage, total;
   int red_blocks;
 };
 
@@ -585,14 +839,34 @@ int storage_bytes(int storage) { return storage == MCLBM_FP32S ? 4 : 2; }
 // lattices of a configuration: f, p and one or two thermal lattices
 int lattices(const mclbm_config& c) { return c.thermal_lattices == 2 ? 4 : 3; }
 
-Layout make_layout(const mclbm_config& c) {
+// Working sets above this size stream from HBM; below it they stay in the
+// 256 MB last-level (Infinity) cache, where non-temporal access hurts.
+constexpr size_t kStreamingBytes = 160u << 20;
+
+size_t pop_bytes(const mclbm_config& c) {
+  const size_t px = (size_t)(c.nx + 63) / 64 * 64;
+  return (size_t)9 * lattices(c) * px * (size_t)c.ny * storage_bytes(c.storage);
+}
+
+// Two time steps per launch (k_step2), on request: one thermal lattice and
+// a population array below 2 GiB (32-bit buffer offsets) only.
+bool two_step_possible(const mclbm_config& c) {
+  return lattices(c) == 3 && pop_bytes(c) < ((size_t)1 << 31);
+}
+bool two_step(const mclbm_config& c, bool batch_member) {
+  return !batch_member && c.steps_per_launch == 2 && two_step_possible(c);
+}
+
+Layout make_layout(const mclbm_config& c, bool batch_member = false) {
   Layout L{};
   L.px = (c.nx + 63) / 64 * 64;
   L.plane = (long long)L.px * c.ny;
   const long long nn = (long long)c.nx * c.ny;
   size_t off = 0;
   L.off_pop = off;
-  off = align_up(off + (size_t)9 * lattices(c) * L.plane * storage_bytes(c.storage));
+  off = align_up(off + pop_bytes(c));
+  L.off_pop2 = off;  // second copy (two steps per launch), else empty
+  if (two_step(c, batch_member)) off = align_up(off + pop_bytes(c));
   L.off_d2 = off;
   off = align_up(off + (size_t)2 * L.plane * sizeof(float2));
   L.off_d5 = off;
@@ -648,6 +922,10 @@ int validate(const mclbm_config* c) {
     return fail(MCLBM_EINVAL, "phi_perturb_amp must be >= 0");
   if (c->storage != MCLBM_FP32S && c->storage != MCLBM_FP16S && c->storage != MCLBM_BF16S)
     return fail(MCLBM_EINVAL, "unknown storage type");
+  if (c->steps_per_launch < 0 || c->steps_per_launch > 2)
+    return fail(MCLBM_EINVAL, "steps_per_launch must be 0, 1 or 2");
+  if (c->steps_per_launch == 2 && !two_step_possible(*c))
+    return fail(MCLBM_EUNSUPPORTED, "two steps per launch need one thermal lattice and populations below 2 GiB");
   const int bx = c->block_x == 0 ? 64 : c->block_x;
   const int by = c->block_y == 0 ? 1 : c->block_y;
   if (!(bx == 32 || bx == 64 || bx == 128 || bx == 256) || by < 1 ||
@@ -810,11 +1088,18 @@ struct mclbm_cavity {
   bool idx32;          // 32-bit element offsets
   bool in_batch;       // owned by a batch: stepped only through it
   bool poison;         // race check: NaN-fill what a step writes before it runs
+  bool two;            // two steps per launch (k_step2) from even steps
+  int popsel, d2sel;   // which population copy is current; lag-field swap
+  unsigned nblocks2;   // k_step2 grid: strips x bands
+  int strips2, band2;
   const int64_t* batch_clock;  // the owning batch's step count (members only)
   std::vector<double> host_dev_p;  // initial phi deviations (source of an async copy)
 
-  void* pop() { return base + L.off_pop; }
-  float2* d2(int k) { return reinterpret_cast<float2*>(base + L.off_d2) + (size_t)k * L.plane; }
+  size_t pop_off(int k) const { return k ? L.off_pop2 : L.off_pop; }
+  void* pop() { return base + pop_off(popsel); }
+  void* pop_other() { return base + pop_off(popsel ^ 1); }
+  size_t d2_off(int k) const { return L.off_d2 + (size_t)(k ^ d2sel) * L.plane * sizeof(float2); }
+  float2* d2(int k) { return reinterpret_cast<float2*>(base + d2_off(k)); }
   float* d5() { return reinterpret_cast<float*>(base + L.off_d5); }
   double* snap() { return reinterpret_cast<double*>(base + L.off_snap); }
   double* part() { return reinterpret_cast<double*>(base + L.off_part); }
@@ -931,13 +1216,9 @@ bool env_flag(const char* name) {
   return v && v[0] == '1';
 }
 
-// Working sets above this size stream from HBM; below it they stay in the
-// 256 MB last-level (Infinity) cache, where non-temporal access hurts.
-constexpr size_t kStreamingBytes = 160u << 20;
-
 int setup_cavity(mclbm_cavity* c) {
   derive(c->cfg, c->D);
-  c->L = make_layout(c->cfg);
+  c->L = make_layout(c->cfg, c->in_batch);
   c->P = make_params(c->cfg, c->D, c->L);
   int bx = c->cfg.block_x, by = c->cfg.block_y;
   if (bx == 0) bx = c->cfg.nx >= 256 ? 256 : 64;
@@ -954,6 +1235,19 @@ int setup_cavity(mclbm_cavity* c) {
   if (env_flag("MCLBM_INDEX64")) c->idx32 = false;
   if (env_flag("MCLBM_STREAMING")) c->nt = true;
   c->poison = env_flag("MCLBM_POISON");
+  // two steps per launch: strips of kStrip2 columns; bands of rows as tall
+  // as keeps at least 4096 waves in the grid (16 per CU), 8 .. 64 rows
+  c->two = two_step(c->cfg, c->in_batch) && c->idx32;
+  c->strips2 = (c->cfg.nx + kStrip2 - 1) / kStrip2;
+  int band = 64;
+  while (band > 8 && (long long)c->strips2 * ((c->cfg.ny + band - 1) / band) < 4096) band /= 2;
+  if (const char* e = std::getenv("MCLBM_BAND2")) {
+    // tuning knob: band height of the two-step kernel
+    const int v = std::atoi(e);
+    if (v >= 1 && v <= 65536) band = v;
+  }
+  c->band2 = band;
+  c->nblocks2 = (unsigned)c->strips2 * (unsigned)((c->cfg.ny + band - 1) / band);
   return MCLBM_OK;
 }
 
@@ -983,6 +1277,40 @@ int launch_step(mclbm_cavity* c) {
     k_step<true, typename K::SO, I, K::NL><<<c->nblocks, c->block, 0, c->stream>>>(c->P, pop, c->d2(0), c->d2(1),
                                                                           c->d5(), c->tiles_x);
   return launch_check("k_step");
+}
+
+// Steps t (even) and t + 1 in one launch, from the current population copy
+// into the other one; the lag field of t + 1 goes to the buffer that held the
+// one of t - 1's partner, and both selections flip.
+template <class K>
+int launch_step2(mclbm_cavity* c) {
+  if constexpr (K::NL == 3 && sizeof(typename K::I) == 4) {
+    using S = typename K::SE;
+    using T = typename S::T;
+    auto* src = reinterpret_cast<const T*>(c->pop());
+    auto* dst = reinterpret_cast<T*>(c->pop_other());
+    if (c->poison) {
+      // race check: every slot of the target copy and every lag-field entry
+      // the launch writes start as NaN, so a slot left unwritten (or read
+      // before it is written) shows up in the results
+      const long long np = (long long)pop_bytes(c->cfg) / (long long)sizeof(float);
+      k_poison<<<(unsigned)std::min<long long>((np + 255) / 256, 1 << 20), 256, 0, c->stream>>>(
+          reinterpret_cast<float*>(c->pop_other()), np);
+      const long long n2 = 2 * c->L.plane;
+      k_poison<<<(unsigned)std::min<long long>((n2 + 255) / 256, 65536), 256, 0, c->stream>>>(
+          reinterpret_cast<float*>(c->d2(0)), n2);
+      int r = launch_check("k_poison");
+      if (r) return r;
+    }
+    k_step2<S><<<c->nblocks2, 64, 0, c->stream>>>(c->P, src, dst, c->d2(1), c->d2(0), c->strips2, c->band2);
+    int r = launch_check("k_step2");
+    if (r) return r;
+    c->popsel ^= 1;
+    c->d2sel ^= 1;
+    return MCLBM_OK;
+  } else {
+    return fail(MCLBM_EUNSUPPORTED, "two steps per launch: one thermal lattice and 32-bit offsets only");
+  }
 }
 
 int export_pops(mclbm_cavity* c, int q, double* dev_out) {
@@ -1055,7 +1383,7 @@ int enqueue_load_fields(mclbm_cavity* c, const float* F, int sx, int sy, int nc,
 // ---- checkpoint / resume ----------------------------------------------------
 namespace {
 
-constexpr int kCkptVersion = 1;
+constexpr int kCkptVersion = 2;
 
 struct CkptSection {
   const char* name;
@@ -1065,8 +1393,9 @@ struct CkptSection {
 std::vector<CkptSection> ckpt_sections(const mclbm_cavity* c) {
   const long long nn = (long long)c->cfg.nx * c->cfg.ny;
   return {
-      {"populations", c->L.off_pop, (size_t)9 * c->P.nl * c->L.plane * storage_bytes(c->cfg.storage)},
-      {"lag_fields", c->L.off_d2, (size_t)2 * c->L.plane * sizeof(float2)},
+      {"populations", c->pop_off(c->popsel), pop_bytes(c->cfg)},
+      {"lag_field_0", c->d2_off(0), (size_t)c->L.plane * sizeof(float2)},
+      {"lag_field_1", c->d2_off(1), (size_t)c->L.plane * sizeof(float2)},
       {"side_buffer", c->L.off_d5, (size_t)6 * (c->P.nl - 2) * c->L.px * sizeof(float)},
       {"residual_snapshot", c->L.off_snap, (size_t)3 * nn * sizeof(double)},
   };
@@ -1082,6 +1411,15 @@ std::string hex_of(const void* p, size_t n) {
     s.push_back(d[b[k] & 15]);
   }
   return s;
+}
+
+// The configuration a checkpoint is tied to: the physics, not the launch
+// shape (workgroup shape, steps per launch), which leaves the state alone.
+std::string config_key(const mclbm_config& c) {
+  mclbm_config k = c;
+  k.block_x = k.block_y = 0;
+  k.steps_per_launch = 0;
+  return hex_of(&k, sizeof k);
 }
 
 std::string json_string_field(const std::string& h, const char* key) {
@@ -1218,10 +1556,18 @@ int mclbm_step(mclbm_cavity* c, int64_t nsteps) {
   if (c->in_batch) return fail(MCLBM_ESTATE, "cavity belongs to a batch: use the batch calls");
   if (nsteps < 0) return fail(MCLBM_EINVAL, "nsteps must be >= 0");
   return dispatch(c, [&](auto k) {
-    for (int64_t s = 0; s < nsteps; ++s) {
-      int rc = launch_step<decltype(k)>(c);
-      if (rc) return rc;
-      c->t += 1;
+    for (int64_t s = 0; s < nsteps;) {
+      if (c->two && (c->t & 1) == 0 && nsteps - s >= 2) {
+        int rc = launch_step2<decltype(k)>(c);
+        if (rc) return rc;
+        c->t += 2;
+        s += 2;
+      } else {
+        int rc = launch_step<decltype(k)>(c);
+        if (rc) return rc;
+        c->t += 1;
+        s += 1;
+      }
     }
     return (int)MCLBM_OK;
   });
@@ -1368,7 +1714,7 @@ int mclbm_checkpoint(mclbm_cavity* c, const char* path) {
     h += buf;
   }
   h += "], \"t\": " + std::to_string((long long)c->t) + ", \"parity\": " + std::to_string((int)(c->t & 1));
-  h += ", \"config_hex\": \"" + hex_of(&c->cfg, sizeof(mclbm_config)) + "\"";
+  h += ", \"config_hex\": \"" + config_key(c->cfg) + "\"";
   h += ", \"xi_hex\": \"" + hex_of(c->xi.data(), c->xi.size() * sizeof(double)) + "\"";
   h += ", \"sections\": [";
   for (size_t k = 0; k < secs.size(); ++k)
@@ -1414,7 +1760,7 @@ int mclbm_restore(mclbm_cavity* c, const char* path) {
   if (json_string_field(h, "format") != "mclbm-checkpoint" || !json_number_field(h, "version", ver) ||
       ver != kCkptVersion)
     return bad("not a checkpoint of this format");
-  if (json_string_field(h, "config_hex") != hex_of(&c->cfg, sizeof(mclbm_config)))
+  if (json_string_field(h, "config_hex") != config_key(c->cfg))
     return bad("the configuration differs from the cavity's");
   if (json_string_field(h, "xi_hex") != hex_of(c->xi.data(), c->xi.size() * sizeof(double)))
     return bad("the initial perturbation field differs from the cavity's");
@@ -1517,6 +1863,8 @@ int batch_layout(const mclbm_config* cfgs, int n, BatchLayout& B) {
     if (cfgs[k].storage != cfgs[0].storage) return fail(MCLBM_EINVAL, "all cavities of a batch share the storage type");
     if (cfgs[k].thermal_lattices == 2)
       return fail(MCLBM_EUNSUPPORTED, "cavity " + std::to_string(k) + ": batches take one thermal lattice");
+    if (cfgs[k].steps_per_launch == 2)
+      return fail(MCLBM_EUNSUPPORTED, "cavity " + std::to_string(k) + ": batches run one step per launch");
     int m = 0;
     for (const auto& sh : kShapes) m = std::max(m, tiles_of(cfgs[k].nx, cfgs[k].ny, sh[0], sh[1]));
     cap += m;
@@ -1533,7 +1881,7 @@ int batch_layout(const mclbm_config* cfgs, int n, BatchLayout& B) {
   B.off_cav.resize(n);
   for (int k = 0; k < n; ++k) {
     B.off_cav[k] = off;
-    off = align_up(off + make_layout(cfgs[k]).total);
+    off = align_up(off + make_layout(cfgs[k], true).total);
   }
   B.total = off;
   return MCLBM_OK;
@@ -1696,7 +2044,7 @@ int mclbm_batch_create(const mclbm_config* cfgs, int32_t n, const double* const*
     if (xis && xis[k]) c->xi.assign(xis[k], xis[k] + (size_t)cfgs[k].nx * cfgs[k].ny);
     c->stream = b->stream;
     c->base = b->base + B.off_cav[k];
-    c->bytes = make_layout(cfgs[k]).total;
+    c->bytes = make_layout(cfgs[k], true).total;
     c->in_batch = true;
     c->batch_clock = &b->t;
     setup_cavity(c);

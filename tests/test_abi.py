@@ -66,12 +66,27 @@ def test_defaults_and_sizes():
 @pytest.mark.parametrize("bad", [dict(nx=3), dict(ny=2), dict(Ra=-1.0), dict(Pr=0.0), dict(phi0=0.2),
                                  dict(phi0=-0.01), dict(dp_m=0.0), dict(tau_f=0.5), dict(tau_f=0.3),
                                  dict(force_mask=64), dict(block_x=48), dict(block_x=64, block_y=8),
-                                 dict(storage=7), dict(phi_perturb_amp=-1.0), dict(dT_K=0.0)])
+                                 dict(storage=7), dict(phi_perturb_amp=-1.0), dict(dT_K=0.0),
+                                 dict(steps_per_launch=3), dict(steps_per_launch=-1)])
 def test_invalid_configs_rejected(bad):
     with pytest.raises(mc.MclbmError) as e:
         mc.device_bytes(**bad)
     assert e.value.code == mc.EINVAL
     assert mc.lib().mclbm_last_error()
+
+
+def test_two_steps_per_launch_sizes_and_limits():
+    """Two steps per launch (on request) keep a second population copy; one
+    thermal lattice and populations below 2 GiB only."""
+    pop64 = 27 * 4 * 64 * 64
+    assert mc.device_bytes(nx=64, ny=64, steps_per_launch=2) == mc.device_bytes(nx=64, ny=64) + pop64
+    assert mc.device_bytes(nx=64, ny=64, steps_per_launch=1) == mc.device_bytes(nx=64, ny=64)
+    pop2k = 27 * 4 * 2048 * 2048
+    assert mc.device_bytes(nx=2048, ny=2048, steps_per_launch=2) == mc.device_bytes(nx=2048, ny=2048) + pop2k
+    for bad in (dict(thermal_lattices=2), dict(nx=4608, ny=4608)):
+        with pytest.raises(mc.MclbmError) as e:
+            mc.derive_constants(steps_per_launch=2, **bad)
+        assert e.value.code == mc.EUNSUPPORTED
 
 
 def test_create_rejects_small_or_misaligned_buffers_without_touching_them():
