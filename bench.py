@@ -264,23 +264,30 @@ def main():
         del cav
         torch.cuda.empty_cache()
 
-        def measure(name, steps):
+        def measure(name, steps, steps_per_launch=1):
             w2 = inputs.WORKLOADS[name]
             cfg2 = {k: v for k, v in w2.items() if k != "seed"}
-            cav2 = mc.Cavity(xi=inputs.phi_perturbation(w2["seed"], cfg2["nx"], cfg2["ny"]), **cfg2)
+            cav2 = mc.Cavity(xi=inputs.phi_perturbation(w2["seed"], cfg2["nx"], cfg2["ny"]),
+                             steps_per_launch=steps_per_launch, **cfg2)
             cav2.step(20)
             ms2 = time_steps(torch, cav2, steps)
             n2 = cfg2["nx"] * cfg2["ny"]
-            gbs2 = BYTES_PER_LUP_FP32 * n2 / (ms2 * 1e-3) / 1e9
+            # two steps per launch read and write the populations once per
+            # two steps: half the algorithmic bytes per lattice update
+            bpl = BYTES_PER_LUP_FP32 / steps_per_launch
+            gbs2 = bpl * n2 / (ms2 * 1e-3) / 1e9
             del cav2
             torch.cuda.empty_cache()
             return {"workload": name, "nx": cfg2["nx"], "ny": cfg2["ny"], "steps": steps,
+                    "steps_per_launch": steps_per_launch, "bytes_per_lup": bpl,
                     "ms_per_step": round(ms2, 5), "MLUPS": round(n2 / (ms2 * 1e-3) / 1e6, 1),
                     "achieved_GBps": round(gbs2, 1), "frac": round(gbs2 / HBM_PEAK_GBPS, 4),
                     "frac_of_copy": round(gbs2 / copy_gbps, 4)}
 
         secondary = measure("cavity2048_ra1e6", 200)   # 450 MB: partly served by the 256 MB cache
         streaming = measure("cavity4096_ra1e6", 50)    # 1.8 GB: streams from HBM
+        # the same cavity with an even and an odd step per launch (k_step2)
+        streaming["two_steps_per_launch"] = measure("cavity4096_ra1e6", 50, steps_per_launch=2)
     batched = None
     if a.batch > 0 and not a.no_secondary:
         batched = batch_measure(torch, mc, inputs, a.batch)
