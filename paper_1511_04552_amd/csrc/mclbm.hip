@@ -1235,12 +1235,12 @@ int setup_cavity(mclbm_cavity* c) {
   if (env_flag("MCLBM_INDEX64")) c->idx32 = false;
   if (env_flag("MCLBM_STREAMING")) c->nt = true;
   c->poison = env_flag("MCLBM_POISON");
-  // two steps per launch: strips of kStrip2 columns; bands of rows as tall
-  // as keeps at least 4096 waves in the grid (16 per CU), 8 .. 64 rows
+  // two steps per launch: strips of kStrip2 columns, bands of 8 rows (of
+  // 4 to 64 rows, 8 was fastest from 1024^2 to 4096^2, FP32 and FP16: more
+  // waves in flight outweigh the halo rows recomputed)
   c->two = two_step(c->cfg, c->in_batch) && c->idx32;
   c->strips2 = (c->cfg.nx + kStrip2 - 1) / kStrip2;
-  int band = 64;
-  while (band > 8 && (long long)c->strips2 * ((c->cfg.ny + band - 1) / band) < 4096) band /= 2;
+  int band = 8;
   if (const char* e = std::getenv("MCLBM_BAND2")) {
     // tuning knob: band height of the two-step kernel
     const int v = std::atoi(e);
