@@ -551,6 +551,15 @@ def main(argv=None) -> int:
     ap.add_argument("--horizon", type=int, default=2_000_000, help="steps of both evaluation runs")
     ap.add_argument("--seed", type=int, default=5)
     ap.add_argument("--out", default=None)
+    # A long evaluation can be split over several processes: train once and
+    # save the model, then run the cold and the warm start separately (each
+    # saving its run), then combine the two runs into the report.
+    ap.add_argument("--save-model", default=None, help="write the trained model (.npz)")
+    ap.add_argument("--load-model", default=None, help="skip data and training; use this model (.npz)")
+    ap.add_argument("--eval", choices=("both", "cold", "warm", "none"), default="both")
+    ap.add_argument("--save-run", default=None, help="write the evaluation run(s) made (.npz)")
+    ap.add_argument("--combine", nargs=2, default=None, metavar=("COLD", "WARM"),
+                    help="report from two saved runs instead of running")
     a = ap.parse_args(argv)
     import torch
     log = lambda s: print(s, flush=True)
@@ -558,31 +567,63 @@ def main(argv=None) -> int:
     def cases(seed, n, side):
         return [dict(c, tau_f=-1.0) for c in inputs.sweep_parameters(seed, n, sides=(side,))]
 
+    RUN_KEYS = ("steps", "converged", "nu", "times", "nu_hist", "seconds", "t_load", "fields")
     S = a.train_side
-    train = cases(a.seed * 1000 + 1, a.train_count, S)
-    t0 = time.perf_counter()
-    F, steps, ok = generate_dataset(train, chunk=2000, tol=a.tol, max_steps=2_000_000, log=log)
-    torch.cuda.synchronize()
-    t_gen = time.perf_counter() - t0
-    log(f"training data: {ok.sum()}/{len(train)} cavities of {S}^2 converged in {t_gen:.1f} s")
-    ws = WarmStart(S=S, C=a.channels, m=min(a.modes, S // 4), L=4, Q=64, B=a.batch, seed=a.seed)
-    t0 = time.perf_counter()
-    hist = ws.fit([c for c, o in zip(train, ok) if o], F[ok], epochs=a.epochs, lr=a.lr,
-                  weights=(1, 1, a.theta_weight, 1, 1),
-                  log=lambda s: log(s) if s.strip().startswith("epoch") else None)
-    torch.cuda.synchronize()
-    t_train = time.perf_counter() - t0
-    log(f"trained {a.epochs} epochs in {t_train:.1f} s, loss {hist[0]:.3e} -> {hist[-1]:.3e}")
-    test = cases(a.seed * 1000 + 2, a.eval_count, a.eval_side)
-    # Both starts run the same fixed horizon without drop-out, so that the
-    # steady Nu is taken well past the stopping criterion (which leaves a
-    # drift of order tol times the slowest decay time over the chunk) and
-    # the two final states can be compared.
-    cold = run_to_steady(test, None, chunk=500, tol=a.tol, max_steps=a.horizon, drop=False, log=log)
-    log(f"cold start: {cold['converged'].sum()}/{len(test)} met the criterion, {cold['seconds']:.1f} s")
-    warm = run_to_steady(test, ws, chunk=500, tol=a.tol, max_steps=a.horizon, drop=False, log=log)
-    log(f"warm start: {warm['converged'].sum()}/{len(test)} met the criterion, {warm['seconds']:.1f} s "
-        f"(prediction and loading {warm['t_load'] * 1e3:.1f} ms)")
+    train_rep = {"side": S}
+    ws = None
+    if a.combine:
+        runs = [dict(np.load(f)) for f in a.combine]
+        cold, warm = ({k: (r[k].item() if r[k].ndim == 0 else r[k]) for k in RUN_KEYS} for r in runs)
+    else:
+        if a.load_model:
+            st = dict(np.load(a.load_model))
+            S = int(st.pop("S"))
+            C, m = int(st.pop("C")), int(st.pop("m"))
+            train_rep = {k: (v.item() if v.ndim == 0 else v.tolist()) for k, v in st.items() if k.startswith("rep_")}
+            train_rep = {k[4:]: v for k, v in train_rep.items()}
+            ws = WarmStart(S=S, C=C, m=m, L=4, Q=64, B=a.batch, seed=a.seed)
+            ws.load_state({k: v for k, v in st.items() if not k.startswith("rep_")})
+            log(f"model loaded from {a.load_model} ({S}^2, C={C}, modes {m})")
+        else:
+            train = cases(a.seed * 1000 + 1, a.train_count, S)
+            t0 = time.perf_counter()
+            F, steps, ok = generate_dataset(train, chunk=2000, tol=a.tol, max_steps=2_000_000, log=log)
+            torch.cuda.synchronize()
+            t_gen = time.perf_counter() - t0
+            log(f"training data: {ok.sum()}/{len(train)} cavities of {S}^2 converged in {t_gen:.1f} s")
+            ws = WarmStart(S=S, C=a.channels, m=min(a.modes, S // 4), L=4, Q=64, B=a.batch, seed=a.seed)
+            t0 = time.perf_counter()
+            hist = ws.fit([c for c, o in zip(train, ok) if o], F[ok], epochs=a.epochs, lr=a.lr,
+                          weights=(1, 1, a.theta_weight, 1, 1),
+                          log=lambda s: log(s) if s.strip().startswith("epoch") else None)
+            torch.cuda.synchronize()
+            t_train = time.perf_counter() - t0
+            log(f"trained {a.epochs} epochs in {t_train:.1f} s, loss {hist[0]:.3e} -> {hist[-1]:.3e}")
+            train_rep = {"side": S, "count": int(ok.sum()), "epochs": a.epochs, "channels": a.channels,
+                         "modes": min(a.modes, S // 4), "seconds_data": t_gen, "seconds_train": t_train,
+                         "loss_first": hist[0], "loss_last": hist[-1]}
+            if a.save_model:
+                np.savez(a.save_model, S=S, C=a.channels, m=min(a.modes, S // 4), **ws.state(),
+                         **{"rep_" + k: v for k, v in train_rep.items()})
+        test = cases(a.seed * 1000 + 2, a.eval_count, a.eval_side)
+        # Both starts run the same fixed horizon without drop-out, so that
+        # the steady Nu is taken well past the stopping criterion (which
+        # leaves a drift of order tol times the slowest decay time over the
+        # chunk) and the two final states can be compared.
+        cold = warm = None
+        if a.eval in ("both", "cold"):
+            cold = run_to_steady(test, None, chunk=500, tol=a.tol, max_steps=a.horizon, drop=False, log=log)
+            log(f"cold start: {cold['converged'].sum()}/{len(test)} met the criterion, {cold['seconds']:.1f} s")
+        if a.eval in ("both", "warm"):
+            warm = run_to_steady(test, ws, chunk=500, tol=a.tol, max_steps=a.horizon, drop=False, log=log)
+            log(f"warm start: {warm['converged'].sum()}/{len(test)} met the criterion, {warm['seconds']:.1f} s "
+                f"(prediction and loading {warm['t_load'] * 1e3:.1f} ms)")
+        if a.save_run:
+            made = cold if cold is not None else warm
+            if made is not None:
+                np.savez(a.save_run, **{k: np.asarray(made[k]) for k in RUN_KEYS})
+        if cold is None or warm is None:
+            return 0
     done = cold["converged"] & warm["converged"]
     nu_inf = cold["nu"]
     sc = settle_steps(cold["times"], cold["nu_hist"], nu_inf)
@@ -590,10 +631,8 @@ def main(argv=None) -> int:
     dnu = np.abs(warm["nu"] - nu_inf) / np.abs(nu_inf)
     per_step = cold["seconds"] / cold["times"][-1]
     rep = {
-        "train": {"side": S, "count": int(ok.sum()), "epochs": a.epochs, "channels": a.channels,
-                  "modes": min(a.modes, S // 4), "seconds_data": t_gen, "seconds_train": t_train,
-                  "loss_first": hist[0], "loss_last": hist[-1]},
-        "eval": {"side": a.eval_side, "count": len(test), "tol": a.tol, "horizon": a.horizon,
+        "train": train_rep,
+        "eval": {"side": a.eval_side, "count": len(cold["nu"]), "tol": a.tol, "horizon": a.horizon,
                  "cold_settle_steps": sc.tolist(), "warm_settle_steps": sw.tolist(),
                  "settle_ratio_total": float(sc.sum() / max(sw.sum(), 1)),
                  "settle_ratio_median": float(np.median(sc / np.maximum(sw, 1))),
@@ -606,7 +645,7 @@ def main(argv=None) -> int:
                  "seconds_to_settle_warm": float(sw.max() * per_step + warm["t_load"]),
                  "seconds_load": warm["t_load"]},
     }
-    if a.eval_side == S:
+    if a.eval_side == S and ws is not None:
         pred = ws.predict(test).cpu().numpy() * ws.std + ws.mean
         err = np.sqrt(((pred - cold["fields"]) ** 2).reshape(-1, NCH).mean(0)) / cold["fields"].reshape(-1, NCH).std(0)
         rep["eval"]["rel_rms_error"] = dict(zip(("u", "v", "theta", "phi", "rho_f"), err.tolist()))
