@@ -1439,6 +1439,33 @@ bool json_number_field(const std::string& h, const char* key, long long& v) {
   return end != h.c_str() + a + k.size();
 }
 
+// MCLBM_LOG=debug: one line per configuration on stderr with the lattice
+// constants and the stability numbers at the initial state (phi = phi0,
+// theta = 0, at rest): tau_p and tau_theta (Eqs 23-24), g beta dT (Eq 16),
+// dx, dt, the Mach number of the free-fall velocity sqrt(g beta dT N) and
+// the drag stiffness kappa = beta dt (1 + rho_p / rho_f).
+void log_derived(const mclbm_config& c, const Derived& D) {
+  const char* e = std::getenv("MCLBM_LOG");
+  if (!e || std::strcmp(e, "debug") != 0) return;
+  const StepParams P = make_params(c, D, make_layout(c));
+  const double phi = c.phi0, R = D.v[MCLBM_D_R];
+  const double r_rho = 1.0 + phi * (R - 1.0), r_rhoc = 1.0 + phi * P.crc;
+  const double r_mu = 1.0 + 4.93 * phi + 222.4 * phi * phi;
+  const double r_k = 1.0 + D.v[MCLBM_D_CK] * std::pow(phi, 0.764);
+  const double rho_f = D.v[MCLBM_D_RHO_F0], rho_p = D.v[MCLBM_D_RHO_P0], rho_m = rho_f + rho_p;
+  double tau_p = P.tau_f + P.tp_a * rho_m * (P.tp_b + 222.4 * phi) / r_rho;
+  tau_p = std::min(std::max(tau_p, 0.505), 5.0);
+  const double tau_th = 3.0 * D.v[MCLBM_D_ALPHA_L] * r_k / r_rhoc + 0.5;
+  const double u_ff = std::sqrt(std::max(D.v[MCLBM_D_G_L], 0.0) * c.nx);
+  const double kappa = (double)P.cD * r_mu * (1.0 + (rho_f > 0.0 ? rho_p / rho_f : 0.0));
+  std::fprintf(stderr,
+               "mclbm: nx %d ny %d Ra %.6g phi0 %.6g dp_m %.6g | tau_f %.6g tau_p %.6g tau_theta %.6g "
+               "G_L %.6g dx %.6g dt %.6g | Mach %.4g kappa %.6g\n",
+               c.nx, c.ny, c.Ra, c.phi0, c.dp_m, (double)P.tau_f, tau_p, tau_th, D.v[MCLBM_D_G_L],
+               D.v[MCLBM_D_DX], D.v[MCLBM_D_DT], u_ff * std::sqrt(3.0), kappa);
+  std::fflush(stderr);
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1482,6 +1509,7 @@ int mclbm_derive_constants(const mclbm_config* cfg, double* out, int n) {
   Derived d;
   derive(*cfg, d);
   std::memcpy(out, d.v, sizeof(d.v));
+  log_derived(*cfg, d);
   return MCLBM_OK;
 }
 
@@ -1505,6 +1533,7 @@ int mclbm_create(const mclbm_config* cfg, const double* xi_host, void* dev_buf, 
   c->base = reinterpret_cast<char*>(dev_buf);
   c->bytes = bytes;
   setup_cavity(c);
+  log_derived(c->cfg, c->D);
   rc = enqueue_init(c);
   if (rc) {
     delete c;

@@ -116,3 +116,24 @@ def test_derived_constants_agree_with_independent_oracle_derivation():
         b = oracle.Oracle(**cfg).derived()
         for k in mc.DERIVED:
             assert abs(a[k] - b[k]) <= 1e-14 * max(abs(b[k]), 1e-300), (cfg, k, a[k], b[k])
+
+
+def test_debug_log_prints_derived_constants():
+    """MCLBM_LOG=debug prints one line per configuration with the lattice
+    constants and the stability numbers (host-side)."""
+    import subprocess
+    import sys
+    code = ("import paper_1511_04552_amd as mc; "
+            "d = mc.derive_constants(nx=512, ny=512, Ra=1e5, phi0=0.03, dp_nm=50.0); print(d['G_L'])")
+    env = dict(os.environ, MCLBM_LOG="debug")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, cwd=ROOT, timeout=120)
+    assert r.returncode == 0, r.stderr
+    line = [ln for ln in r.stderr.splitlines() if ln.startswith("mclbm: ")]
+    assert len(line) == 1
+    for key in ("tau_p", "tau_theta", "G_L", "dx", "dt", "Mach", "kappa"):
+        assert f" {key} " in line[0]
+    g = float(line[0].split(" G_L ")[1].split()[0])
+    assert abs(g - float(r.stdout.strip())) <= 1e-5 * g
+    quiet = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                           env=dict(os.environ, MCLBM_LOG="info"), cwd=ROOT, timeout=120)
+    assert "mclbm: " not in quiet.stderr

@@ -164,6 +164,37 @@ def test_restore_refuses_other_configs(tmp_path):
         batch.members[0].restore(tmp_path / "m.ckpt")
 
 
+def test_injected_nan_is_reported_as_divergence(tmp_path):
+    """Failure detection forced from the host: a checkpoint whose file has
+    one interior population set to NaN is restored; after a few steps the
+    residual reports MCLBM_EDIVERGED (every kernel still exits normally)."""
+    cfg = dict(nx=37, ny=29, Ra=5e4, phi0=0.03, dp_nm=40.0)
+    xi = inputs.phi_perturbation(121, cfg["nx"], cfg["ny"])
+    c = mc.Cavity(xi=xi, **cfg)
+    c.step(40)
+    c.residual()
+    path = tmp_path / "n.ckpt"
+    c.checkpoint(path)
+    data = bytearray(open(path, "rb").read())
+    start = data.index(b"\n") + 1  # the populations section follows the header line
+    px = (cfg["nx"] + 63) // 64 * 64
+    node = 14 * px + 18  # plane 0 (fluid rest), an interior node
+    data[start + 4 * node:start + 4 * node + 4] = np.array([np.nan], dtype=np.float32).tobytes()
+    bad = tmp_path / "nan.ckpt"
+    bad.write_bytes(bytes(data))
+    d = mc.Cavity(xi=xi, **cfg)
+    d.restore(bad)
+    d.step(30)
+    with pytest.raises(mc.MclbmError) as e:
+        d.residual()
+    assert e.value.code == mc.EDIVERGED
+    # the intact checkpoint still resumes normally
+    ok = mc.Cavity(xi=xi, **cfg)
+    ok.restore(path)
+    ok.step(30)
+    assert np.isfinite(ok.residual()).all()
+
+
 # ---- race check -------------------------------------------------------------
 
 @pytest.mark.parametrize("cfg", [
