@@ -163,6 +163,19 @@ def test_bench_workload_full_size():
     _assert_nusselt(gpu, ora)
 
 
+def test_paper_shaped_workload():
+    """160^2, Ra 1e6, Pr 8.923, 4 % alumina, 33 nm (the paper's
+    lattice-independence case): full fields and Nu after 1001 steps, past
+    the start-up transient of the convection roll."""
+    w = inputs.WORKLOADS["cavity160_paper"]
+    cfg = {k: v for k, v in w.items() if k != "seed"}
+    gpu, ora = _pair(seed=w["seed"], **cfg)
+    gpu.step(1001)
+    ora.step(1001)
+    _assert_moments(gpu, ora)
+    _assert_nusselt(gpu, ora)
+
+
 def test_large_cavity_2048_and_mass():
     """2048^2, Ra 1e6, phi 4 %, 30 nm: full fields after 200 steps (before
     that the vertical velocity is ~1e-7 and FP32 quantisation of theta,
