@@ -267,10 +267,13 @@ int mclbm_derived(const mclbm_cavity* c, double* out, int n);
  * then the raw sections: populations (storage format, both A-A parities
  * as stored), the two lag-field buffers, the adiabatic side buffer and the
  * residual snapshot.  Sync.  A member of a batch may be checkpointed.
- * mclbm_restore reads such a file into a cavity created with the identical
- * configuration (MCLBM_EINVAL otherwise, or for a damaged or foreign file;
- * the cavity is then unchanged); stepping then continues bitwise as the
- * checkpointed run would have.  Not for batch members (MCLBM_ESTATE).
+ * mclbm_restore reads such a file into a cavity created with the same
+ * configuration apart from its launch shape (block_x, block_y and
+ * steps_per_launch may differ; MCLBM_EINVAL otherwise, or for a damaged or
+ * foreign file; the cavity is then unchanged); stepping then continues
+ * bitwise as the checkpointed run would have with the same launches (with
+ * another launch shape: up to rounding).  Not for batch members
+ * (MCLBM_ESTATE).
  * Both return MCLBM_EHIP-free host errors as MCLBM_EINVAL with a message. */
 int mclbm_checkpoint(mclbm_cavity* c, const char* path);
 int mclbm_restore(mclbm_cavity* c, const char* path);
