@@ -271,8 +271,8 @@ int mclbm_derived(const mclbm_cavity* c, double* out, int n);
  * configuration apart from its launch shape (block_x, block_y and
  * steps_per_launch may differ; MCLBM_EINVAL otherwise, or for a damaged or
  * foreign file; the cavity is then unchanged); stepping then continues
- * bitwise as the checkpointed run would have with the same launches (with
- * another launch shape: up to rounding).  Not for batch members
+ * bitwise as the checkpointed run would have (after a change of
+ * steps_per_launch: up to rounding).  Not for batch members
  * (MCLBM_ESTATE).
  * Both return MCLBM_EHIP-free host errors as MCLBM_EINVAL with a message. */
 int mclbm_checkpoint(mclbm_cavity* c, const char* path);
