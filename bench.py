@@ -21,6 +21,9 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E
 BYTES_PER_LUP_FP32 = 232        # 27 populations read + written (4 B), lag field read + written (8 B)
+BYTES_PER_LUP_16 = 124          # the same with 2-byte populations
+STORAGE = {"fp32": (0, BYTES_PER_LUP_FP32, "fp32"), "fp16": (1, BYTES_PER_LUP_16, "fp16 (scaled)"),
+           "bf16": (2, BYTES_PER_LUP_16, "bf16")}
 
 
 def parse():
@@ -40,6 +43,10 @@ def parse():
                     help="skip the time-to-steady comparison of cold and learned warm starts")
     ap.add_argument("--no-secondary", action="store_true",
                     help="skip the 2048^2 (larger than the last-level cache) measurement")
+    ap.add_argument("--storage", choices=("fp32", "fp16", "bf16"), default="fp32",
+                    help="population storage of the timed workload")
+    ap.add_argument("--steps-per-launch", type=int, choices=(1, 2), default=1,
+                    help="2: an even and an odd step per launch (k_step2)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="summarise two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this "
                          "bench into the traffic file and exit")
@@ -83,7 +90,7 @@ def _counter_rows(d):
     return rows
 
 
-def pmc_summary(fetch_dir, write_dir, workload, out_path):
+def pmc_summary(fetch_dir, write_dir, workload, out_path, storage="fp32", spl=1):
     """Bytes per launch of the step kernels from FETCH_SIZE / WRITE_SIZE
     (KiB per dispatch), each scaled by what the same counter reads for the
     1 GiB copy kernel this bench runs (known to move 1 GiB each way)."""
@@ -95,16 +102,18 @@ def pmc_summary(fetch_dir, write_dir, workload, out_path):
                 continue
             k = r["Kernel_Name"]
             key = "copy" if k.startswith("k_copy") else ("step_even" if "k_step<false" in k else
-                                                         "step_odd" if "k_step<true" in k else None)
+                                                         "step_odd" if "k_step<true" in k else
+                                                         "step_pair" if "k_step2<" in k else None)
             if key:
                 per.setdefault(key, []).append(float(r["Counter_Value"]))
         scale = (1 << 20) / (sum(per["copy"]) / len(per["copy"]))  # KiB of 1 GiB / counted
         res[name] = {"scale": scale, **{k: sum(v) / len(v) * 1024 * scale for k, v in per.items() if k != "copy"}}
-    per_launch = {k: res["FETCH_SIZE"][k] + res["WRITE_SIZE"][k] for k in ("step_even", "step_odd")}
-    out = {"workload": workload, "kernel_hash": kernel_hash(),
-           "bytes_per_launch": 0.5 * (per_launch["step_even"] + per_launch["step_odd"]),
-           "fetch_bytes": {k: res["FETCH_SIZE"][k] for k in ("step_even", "step_odd")},
-           "write_bytes": {k: res["WRITE_SIZE"][k] for k in ("step_even", "step_odd")},
+    kinds = ("step_pair",) if spl == 2 else ("step_even", "step_odd")
+    per_launch = {k: res["FETCH_SIZE"][k] + res["WRITE_SIZE"][k] for k in kinds}
+    out = {"workload": workload, "storage": storage, "steps_per_launch": spl, "kernel_hash": kernel_hash(),
+           "bytes_per_launch": sum(per_launch.values()) / len(kinds),
+           "fetch_bytes": {k: res["FETCH_SIZE"][k] for k in kinds},
+           "write_bytes": {k: res["WRITE_SIZE"][k] for k in kinds},
            "fetch_scale": res["FETCH_SIZE"]["scale"], "write_scale": res["WRITE_SIZE"]["scale"]}
     json.dump(out, open(out_path, "w"), indent=1)
     print(json.dumps(out, indent=1))
@@ -209,7 +218,8 @@ def cpu_baseline(w, xi, seconds):
 def main():
     a = parse()
     if a.pmc_summary:
-        pmc_summary(a.pmc_summary[0], a.pmc_summary[1], a.workload, a.traffic)
+        pmc_summary(a.pmc_summary[0], a.pmc_summary[1], a.workload, a.traffic, a.storage,
+                    a.steps_per_launch)
         return
     if a.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {a.gpus}); the multi-GPU "
@@ -227,7 +237,12 @@ def main():
     nx, ny = cfg["nx"], cfg["ny"]
     xi = inputs.phi_perturbation(w["seed"], nx, ny)
     print(f"# workload {a.workload}: {nx}x{ny}, warmup {a.warmup}, steps {a.steps}", file=sys.stderr, flush=True)
-    cav = mc.Cavity(xi=xi, **cfg)
+    st_code, bytes_lup, st_name = STORAGE[a.storage]
+    spl = a.steps_per_launch
+    if spl == 2 and (a.steps % 2 or a.warmup % 2):
+        print("with two steps per launch, --steps and --warmup must be even", file=sys.stderr)
+        sys.exit(2)
+    cav = mc.Cavity(xi=xi, storage=st_code, steps_per_launch=spl, **cfg)
     stream = cav.stream
     cav.step(a.warmup)
     torch.cuda.synchronize()
@@ -247,13 +262,16 @@ def main():
     print(f"# timed {a.steps} steps: {ms_total:.2f} ms (wall {wall*1e3:.1f} ms), Nu hot {nu_hot:.5f}",
           file=sys.stderr, flush=True)
 
-    bytes_launch = BYTES_PER_LUP_FP32 * nodes
-    achieved = bytes_launch / (ms_step * 1e-3) / 1e9
+    # one launch moves the algorithmic bytes once: one step (k_step) or two
+    # steps (k_step2, which reads and writes the populations once per pair)
+    bytes_launch = bytes_lup * nodes
+    achieved = bytes_launch / (spl * ms_step * 1e-3) / 1e9
     traffic = None
     if os.path.exists(a.traffic):
         try:
             t = json.load(open(a.traffic))
-            if t.get("workload") == a.workload and t.get("kernel_hash") == kernel_hash():
+            if (t.get("workload") == a.workload and t.get("kernel_hash") == kernel_hash()
+                    and t.get("storage", "fp32") == a.storage and t.get("steps_per_launch", 1) == spl):
                 traffic = t.get("bytes_per_launch")
         except Exception:
             traffic = None
@@ -296,7 +314,8 @@ def main():
         warm = warm_start_measure()
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
-            "kernel": "k_step (even and odd A-A parities)",
+            "kernel": ("k_step (even and odd A-A parities)" if spl == 1 else
+                       "k_step2 (an even and an odd step per launch)"),
             "algorithmic_bytes_per_launch": bytes_launch, "copy_kernel_gbps": round(copy_gbps, 1)}
     out = {
         "metric": "MLUPS (3 lattices)", "value": round(mlups, 1), "unit": "MLUPS",
@@ -306,7 +325,9 @@ def main():
         "config": {"workload": a.workload, "nx": nx, "ny": ny, "Ra": cfg["Ra"], "Pr": cfg["Pr"],
                    "phi0": cfg["phi0"], "dp_nm": cfg["dp_nm"], "tau_f": cfg["tau_f"],
                    "forces": "drag+brownian+thermophoresis+saffman+magnus/rotation+gravity+buoyancy",
-                   "storage": "fp32 shifted SoA, A-A in place", "parallelism": "single GPU"},
+                   "storage": f"{st_name} shifted SoA, " + ("A-A in place" if spl == 1 else
+                                                             "two copies, two steps per launch"),
+                   "parallelism": "single GPU"},
         "roofline": roof,
         "nu_hot": nu_hot,
         "larger_than_llc": secondary,
