@@ -45,8 +45,9 @@ def parse():
                     help="skip the 2048^2 (larger than the last-level cache) measurement")
     ap.add_argument("--storage", choices=("fp32", "fp16", "bf16"), default="fp32",
                     help="population storage of the timed workload")
-    ap.add_argument("--steps-per-launch", type=int, choices=(1, 2), default=1,
-                    help="2: an even and an odd step per launch (k_step2)")
+    ap.add_argument("--steps-per-launch", type=int, choices=(0, 1, 2), default=0,
+                    help="1: one step per launch (k_step); 2: an even and an odd step per "
+                         "launch (k_step2); 0: the library's choice for the workload")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="summarise two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this "
                          "bench into the traffic file and exit")
@@ -90,7 +91,7 @@ def _counter_rows(d):
     return rows
 
 
-def pmc_summary(fetch_dir, write_dir, workload, out_path, storage="fp32", spl=1):
+def pmc_summary(fetch_dir, write_dir, workload, out_path, storage="fp32"):
     """Bytes per launch of the step kernels from FETCH_SIZE / WRITE_SIZE
     (KiB per dispatch), each scaled by what the same counter reads for the
     1 GiB copy kernel this bench runs (known to move 1 GiB each way)."""
@@ -108,6 +109,8 @@ def pmc_summary(fetch_dir, write_dir, workload, out_path, storage="fp32", spl=1)
                 per.setdefault(key, []).append(float(r["Counter_Value"]))
         scale = (1 << 20) / (sum(per["copy"]) / len(per["copy"]))  # KiB of 1 GiB / counted
         res[name] = {"scale": scale, **{k: sum(v) / len(v) * 1024 * scale for k, v in per.items() if k != "copy"}}
+    # the kernels the run launched: pairs of steps (k_step2) or single steps
+    spl = 2 if "step_pair" in res["FETCH_SIZE"] else 1
     kinds = ("step_pair",) if spl == 2 else ("step_even", "step_odd")
     per_launch = {k: res["FETCH_SIZE"][k] + res["WRITE_SIZE"][k] for k in kinds}
     out = {"workload": workload, "storage": storage, "steps_per_launch": spl, "kernel_hash": kernel_hash(),
@@ -218,8 +221,7 @@ def cpu_baseline(w, xi, seconds):
 def main():
     a = parse()
     if a.pmc_summary:
-        pmc_summary(a.pmc_summary[0], a.pmc_summary[1], a.workload, a.traffic, a.storage,
-                    a.steps_per_launch)
+        pmc_summary(a.pmc_summary[0], a.pmc_summary[1], a.workload, a.traffic, a.storage)
         return
     if a.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {a.gpus}); the multi-GPU "
@@ -239,6 +241,10 @@ def main():
     print(f"# workload {a.workload}: {nx}x{ny}, warmup {a.warmup}, steps {a.steps}", file=sys.stderr, flush=True)
     st_code, bytes_lup, st_name = STORAGE[a.storage]
     spl = a.steps_per_launch
+    if spl == 0:
+        two = (mc.device_bytes(storage=st_code, **cfg) >
+               mc.device_bytes(storage=st_code, steps_per_launch=1, **cfg))
+        spl = 2 if two else 1
     if spl == 2 and (a.steps % 2 or a.warmup % 2):
         print("with two steps per launch, --steps and --warmup must be even", file=sys.stderr)
         sys.exit(2)
@@ -261,6 +267,15 @@ def main():
     nu_hot, nu_cold, _ = cav.nusselt()
     print(f"# timed {a.steps} steps: {ms_total:.2f} ms (wall {wall*1e3:.1f} ms), Nu hot {nu_hot:.5f}",
           file=sys.stderr, flush=True)
+    # the two reductions, per synchronous call (launch, FP64 reduction, copy of
+    # the result to the host), outside the timed steps
+    red = {}
+    for name, fn in (("nusselt", cav.nusselt), ("residual", cav.residual)):
+        fn()
+        t0 = time.perf_counter()
+        for _ in range(200):
+            fn()
+        red[name + "_call_us"] = round((time.perf_counter() - t0) / 200 * 1e6, 1)
 
     # one launch moves the algorithmic bytes once: one step (k_step) or two
     # steps (k_step2, which reads and writes the populations once per pair)
@@ -282,9 +297,12 @@ def main():
         del cav
         torch.cuda.empty_cache()
 
-        def measure(name, steps, steps_per_launch=1):
+        def measure(name, steps, steps_per_launch=0):
             w2 = inputs.WORKLOADS[name]
             cfg2 = {k: v for k, v in w2.items() if k != "seed"}
+            if steps_per_launch == 0:  # the library's choice for this cavity
+                two = mc.device_bytes(**cfg2) > mc.device_bytes(steps_per_launch=1, **cfg2)
+                steps_per_launch = 2 if two else 1
             cav2 = mc.Cavity(xi=inputs.phi_perturbation(w2["seed"], cfg2["nx"], cfg2["ny"]),
                              steps_per_launch=steps_per_launch, **cfg2)
             cav2.step(20)
@@ -302,10 +320,12 @@ def main():
                     "achieved_GBps": round(gbs2, 1), "frac": round(gbs2 / HBM_PEAK_GBPS, 4),
                     "frac_of_copy": round(gbs2 / copy_gbps, 4)}
 
+        # the default schedule of these sizes is two steps per launch
+        # (k_step2); one step per launch (k_step) is timed beside it
         secondary = measure("cavity2048_ra1e6", 200)   # 450 MB: partly served by the 256 MB cache
+        secondary["one_step_per_launch"] = measure("cavity2048_ra1e6", 200, steps_per_launch=1)
         streaming = measure("cavity4096_ra1e6", 50)    # 1.8 GB: streams from HBM
-        # the same cavity with an even and an odd step per launch (k_step2)
-        streaming["two_steps_per_launch"] = measure("cavity4096_ra1e6", 50, steps_per_launch=2)
+        streaming["one_step_per_launch"] = measure("cavity4096_ra1e6", 50, steps_per_launch=1)
     batched = None
     if a.batch > 0 and not a.no_secondary:
         batched = batch_measure(torch, mc, inputs, a.batch)
@@ -330,6 +350,7 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": roof,
         "nu_hot": nu_hot,
+        "reductions": red,
         "larger_than_llc": secondary,
         "hbm_streaming": streaming,
         "batched_sweep": batched,

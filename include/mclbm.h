@@ -136,19 +136,23 @@ typedef struct {
                               suspension temperature by Eq 33; FP32 storage
                               and single cavities only (MCLBM_EUNSUPPORTED
                               otherwise, also for mclbm_load_fields) */
-  int32_t steps_per_launch;/* 0 (default) or 1: one launch per step,
+  int32_t steps_per_launch;/* 0 (default) = automatic: 2 for FP32 storage
+                              from 2^20 nodes and 256 columns on (where it
+                              is faster), else 1.  1: one launch per step,
                               updated in place.  2: an even and the
                               following odd step in one launch, from one
                               population copy into a second one (device
-                              bytes grow by one population array; half the
-                              memory traffic per step, the same arithmetic);
-                              one thermal lattice, populations below 2 GiB
-                              and single cavities only (MCLBM_EUNSUPPORTED
-                              otherwise).  A step count or start that is odd
-                              takes single steps where needed.  Results are
-                              those of single steps up to rounding (16-bit
-                              storage: the intermediate odd-step state is
-                              kept in FP32, not rounded to storage) */
+                              bytes grow by one population array; 1.25x
+                              instead of 2x the bytes of one step, the same
+                              arithmetic); one thermal lattice, populations
+                              below 2 GiB and single cavities only
+                              (MCLBM_EUNSUPPORTED on request otherwise; the
+                              automatic choice falls back to 1).  A step
+                              count or start that is odd takes single steps
+                              where needed.  Results are those of single
+                              steps up to rounding (16-bit storage: the
+                              intermediate odd-step state is kept in FP32,
+                              not rounded to storage) */
 } mclbm_config;
 
 typedef struct mclbm_cavity mclbm_cavity; /* opaque host-side handle */

@@ -93,20 +93,6 @@ __device__ __forceinline__ void wall_ghosts(float2 c, float2 vE, float2 vW, floa
   gr = make_float4(0.5f * (vE.x - vW.x), 0.5f * (vN.x - vS.x), 0.5f * (thE - thW), 0.5f * (vN.y - vS.y));
 }
 
-// The five lag-field values around (x, y), loaded unconditionally (a
-// neighbour behind a wall reads the centre instead, which wall_ghosts
-// replaces anyway), so that no branch separates the loads from their use.
-__device__ __forceinline__ void lag_fetch(const StepParams& P, const float2* __restrict__ d2p, int x, int y,
-                                          float2& c, float2& vE, float2& vW, float2& vN, float2& vS) {
-  const long long n = (long long)y * P.px + x;
-  const bool xl = x == 0, xr = x == P.nx - 1, yb = y == 0, yt = y == P.ny - 1;
-  c = d2p[n];
-  vE = d2p[xr ? n : n + 1];
-  vW = d2p[xl ? n : n - 1];
-  vN = d2p[yt ? n : n + P.px];
-  vS = d2p[yb ? n : n - P.px];
-}
-
 __device__ __forceinline__ void lag_gradients(const StepParams& P, const float2* __restrict__ d2p, int x,
                                               int y, float4& gr) {
   const long long n = (long long)y * P.px + x;
@@ -235,12 +221,15 @@ __global__ __launch_bounds__(64) void k_step2(StepParams P, const typename S::T*
   // also wait for those stores.
   const int rlast = min(y1, ny - 1);  // last row of stage A
   float PF[3][9];
-  float2 Lc, Le, Lw, Ln, Ls;  // lag field of step t - 1 around the row
-  auto fetch = [&](int row) {
-    load_node<false, S, I>(P, popA, nullptr, xs, row, PF[0], PF[1], PF[2]);
-    lag_fetch(P, d2p, xs, row, Lc, Le, Lw, Ln, Ls);
-  };
-  fetch(ra);
+  load_node<false, S, I>(P, popA, nullptr, xs, ra, PF[0], PF[1], PF[2]);
+  // Lag field of step t - 1 in the lane's column: rows r - 1, r and r + 1
+  // carried from one iteration to the next, row r + 2 in flight; the x
+  // neighbours come from the adjacent lanes, and the two lanes at the ends
+  // of the wave load their outer neighbour (row r, in flight: row r + 1).
+  const int xo = min(max(lane == 0 ? xs - 1 : (lane == 63 ? xs + 1 : xs), 0), nx - 1);
+  auto lag = [&](int row, int col) { return d2p[(long long)min(row, ny - 1) * P.px + col]; };
+  float2 Lm = lag(max(ra - 1, 0), xs), L0 = lag(ra, xs), Lp = lag(ra + 1, xs), Lo = lag(ra, xo);
+  float2 Lpp = Lp, Lon = Lo;
 
   for (int r = ra; r <= y1; ++r) {
     const bool has_a = r < ny;
@@ -253,12 +242,19 @@ __global__ __launch_bounds__(64) void k_step2(StepParams P, const typename S::T*
         for (int l = 0; l < 3; ++l)
 #pragma unroll
           for (int i = 0; i < 9; ++i) A[l][i] = PF[l][i];
+        const float2 sE = make_float2(__shfl_down(L0.x, 1, 64), __shfl_down(L0.y, 1, 64));
+        const float2 sW = make_float2(__shfl_up(L0.x, 1, 64), __shfl_up(L0.y, 1, 64));
         float4 gr;
-        wall_ghosts(Lc, Le, Lw, Ln, Ls, xs == 0, xs == nx - 1, r == 0, r == ny - 1, gr);
+        wall_ghosts(L0, lane == 63 ? Lo : sE, lane == 0 ? Lo : sW, Lp, Lm, xs == 0, xs == nx - 1, r == 0,
+                    r == ny - 1, gr);
         dr = node_update<3>(P, A[0], A[1], A[2], gr.x, gr.y, gr.z, gr.w);
         // the next row's loads: after the stage-A update (whose first use
         // of this row's values waits for them), overlapping stage B
-        if (r < rlast) fetch(r + 1);
+        if (r < rlast) {
+          load_node<false, S, I>(P, popA, nullptr, xs, r + 1, PF[0], PF[1], PF[2]);
+          Lpp = lag(r + 2, xs);
+          Lon = lag(r + 1, xo);
+        }
       }
       // pull across lanes (whole wave, uniform control flow)
       float UPn[9];
@@ -372,6 +368,10 @@ __global__ __launch_bounds__(64) void k_step2(StepParams P, const typename S::T*
     for (int k = 0; k < 9; ++k) M[k] = ALn[k];
     dqm = dq;
     dq = dr;
+    Lm = L0;
+    L0 = Lp;
+    Lp = Lpp;
+    Lo = Lon;
   }
 }
 
@@ -848,13 +848,18 @@ size_t pop_bytes(const mclbm_config& c) {
   return (size_t)9 * lattices(c) * px * (size_t)c.ny * storage_bytes(c.storage);
 }
 
-// Two time steps per launch (k_step2), on request: one thermal lattice and
-// a population array below 2 GiB (32-bit buffer offsets) only.
+// Two time steps per launch (k_step2): one thermal lattice and a population
+// array below 2 GiB (32-bit buffer offsets) only.  By default for FP32
+// storage from 2^20 nodes and 256 columns on, where it was measured faster
+// than one step per launch (1024^2 +8 %, 2048^2 +18 %, 4096^2 +44 %; slower
+// at 512^2, and with 16-bit storage at every size).
 bool two_step_possible(const mclbm_config& c) {
   return lattices(c) == 3 && pop_bytes(c) < ((size_t)1 << 31);
 }
 bool two_step(const mclbm_config& c, bool batch_member) {
-  return !batch_member && c.steps_per_launch == 2 && two_step_possible(c);
+  if (batch_member || !two_step_possible(c)) return false;
+  if (c.steps_per_launch != 0) return c.steps_per_launch == 2;
+  return c.storage == MCLBM_FP32S && (long long)c.nx * c.ny >= (1LL << 20) && c.nx >= 256;
 }
 
 Layout make_layout(const mclbm_config& c, bool batch_member = false) {
@@ -1235,12 +1240,13 @@ int setup_cavity(mclbm_cavity* c) {
   if (env_flag("MCLBM_INDEX64")) c->idx32 = false;
   if (env_flag("MCLBM_STREAMING")) c->nt = true;
   c->poison = env_flag("MCLBM_POISON");
-  // two steps per launch: strips of kStrip2 columns, bands of 8 rows (of
-  // 4 to 64 rows, 8 was fastest from 1024^2 to 4096^2, FP32 and FP16: more
-  // waves in flight outweigh the halo rows recomputed)
+  // two steps per launch: strips of kStrip2 columns, bands of 4 rows from
+  // 2048^2 on and 8 below (the fastest of 4 to 32 rows at 1024^2, 2048^2
+  // and 4096^2: more waves in flight outweigh the halo rows recomputed,
+  // whose loads hit in L2)
   c->two = two_step(c->cfg, c->in_batch) && c->idx32;
   c->strips2 = (c->cfg.nx + kStrip2 - 1) / kStrip2;
-  int band = 8;
+  int band = (long long)c->cfg.nx * c->cfg.ny >= (1LL << 22) ? 4 : 8;
   if (const char* e = std::getenv("MCLBM_BAND2")) {
     // tuning knob: band height of the two-step kernel
     const int v = std::atoi(e);
@@ -1285,7 +1291,11 @@ int launch_step(mclbm_cavity* c) {
 template <class K>
 int launch_step2(mclbm_cavity* c) {
   if constexpr (K::NL == 3 && sizeof(typename K::I) == 4) {
-    using S = typename K::SE;
+    // cached loads and stores at every size: a wave's 64 lanes start one
+    // column before its strip, so its row loads straddle the cache lines it
+    // shares with the neighbouring strips (and bands), which then hit in L2;
+    // non-temporal loads evict them first and read 1.64x the bytes
+    using S = typename K::S;
     using T = typename S::T;
     auto* src = reinterpret_cast<const T*>(c->pop());
     auto* dst = reinterpret_cast<T*>(c->pop_other());

@@ -76,13 +76,21 @@ def test_invalid_configs_rejected(bad):
 
 
 def test_two_steps_per_launch_sizes_and_limits():
-    """Two steps per launch (on request) keep a second population copy; one
-    thermal lattice and populations below 2 GiB only."""
+    """Two steps per launch keep a second population copy: on request, and
+    by default for FP32 storage from 2^20 nodes and 256 columns on (below
+    2 GiB of populations); one thermal lattice only."""
     pop64 = 27 * 4 * 64 * 64
     assert mc.device_bytes(nx=64, ny=64, steps_per_launch=2) == mc.device_bytes(nx=64, ny=64) + pop64
     assert mc.device_bytes(nx=64, ny=64, steps_per_launch=1) == mc.device_bytes(nx=64, ny=64)
     pop2k = 27 * 4 * 2048 * 2048
-    assert mc.device_bytes(nx=2048, ny=2048, steps_per_launch=2) == mc.device_bytes(nx=2048, ny=2048) + pop2k
+    one = mc.device_bytes(nx=2048, ny=2048, steps_per_launch=1)
+    assert mc.device_bytes(nx=2048, ny=2048) == mc.device_bytes(nx=2048, ny=2048, steps_per_launch=2) == one + pop2k
+    assert mc.device_bytes(nx=1024, ny=1024) > mc.device_bytes(nx=1024, ny=1024, steps_per_launch=1)
+    # automatic: one step below 2^20 nodes, for 16-bit storage, narrow
+    # cavities and populations of 2 GiB and more
+    for kw in (dict(nx=512, ny=512), dict(nx=2048, ny=2048, storage=mc.FP16S), dict(nx=128, ny=16384),
+               dict(nx=4608, ny=4608), dict(nx=2048, ny=2048, thermal_lattices=2)):
+        assert mc.device_bytes(**kw) == mc.device_bytes(steps_per_launch=1, **kw), kw
     for bad in (dict(thermal_lattices=2), dict(nx=4608, ny=4608)):
         with pytest.raises(mc.MclbmError) as e:
             mc.derive_constants(steps_per_launch=2, **bad)
