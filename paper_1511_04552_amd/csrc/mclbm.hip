@@ -8,6 +8,9 @@
 //               properties (Eqs 7-11, 22-24), lagged gradients, slip forces
 //               (Table 1, Eqs 6, 20), BGK collision of three lattices
 //               (Eqs 18-19), A-A store
+//   k_step2     the same physics for an even and the following odd step in
+//               one launch, between two population copies (large cavities)
+//   k_step_batch  one launch per step over a batch of uneven cavities
 //   k_nusselt   FP64 wall-Nusselt reduction
 //   k_residual  FP64 relative change of u_ns and theta (steady-state test)
 //   k_export    FP64 moments / populations of the current state
