@@ -1243,13 +1243,13 @@ int setup_cavity(mclbm_cavity* c) {
   if (env_flag("MCLBM_INDEX64")) c->idx32 = false;
   if (env_flag("MCLBM_STREAMING")) c->nt = true;
   c->poison = env_flag("MCLBM_POISON");
-  // two steps per launch: strips of kStrip2 columns, bands of 4 rows from
-  // 2048^2 on and 8 below (the fastest of 4 to 32 rows at 1024^2, 2048^2
-  // and 4096^2: more waves in flight outweigh the halo rows recomputed,
-  // whose loads hit in L2)
+  // two steps per launch: strips of kStrip2 columns, bands of 6 rows below
+  // 2^21 nodes and 4 from there on (of 3 to 32 rows, the fastest or within
+  // 1 % of it at 1024^2, 1536^2, 2048^2, 3072^2 and 4096^2: more waves in
+  // flight outweigh the halo rows recomputed, whose loads hit in L2)
   c->two = two_step(c->cfg, c->in_batch) && c->idx32;
   c->strips2 = (c->cfg.nx + kStrip2 - 1) / kStrip2;
-  int band = (long long)c->cfg.nx * c->cfg.ny >= (1LL << 22) ? 4 : 8;
+  int band = (long long)c->cfg.nx * c->cfg.ny >= (1LL << 21) ? 4 : 6;
   if (const char* e = std::getenv("MCLBM_BAND2")) {
     // tuning knob: band height of the two-step kernel
     const int v = std::atoi(e);
