@@ -155,9 +155,11 @@ __global__ __launch_bounds__(256) void k_step(StepParams P,
 // ---- two time steps per launch ---------------------------------------------
 // k_step2 runs an even step t and the odd step t + 1 in one pass, reading the
 // populations at t (A-A layout of an even step) from one array and writing
-// those at t + 2 (same layout) to a second one, so each step moves half the
-// bytes of k_step.  The in-place pattern cannot be used here: the workgroups
-// overlap by a halo and would overwrite what their neighbours still read.
+// those at t + 2 (same layout) to a second one, so a step needs half the
+// algorithmic bytes of k_step (the halo rows that neighbouring bands read
+// again add about a third).  The in-place pattern cannot be used here: the
+// workgroups overlap by a halo and would overwrite what their neighbours
+// still read.
 //
 // One wave owns a strip of kStrip2 columns and a band of rows.  Its 64 lanes
 // hold the strip and one halo column on each side.  It sweeps the band
