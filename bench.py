@@ -363,15 +363,23 @@ def main():
 
 
 def kernel_hash() -> str:
-    """Hash of the step kernel's device source (the device header and the
-    step_node / k_step text), which the measured traffic belongs to."""
+    """Hash of the step kernels' device code (the device header and the text
+    from step_node to k_step2), which the measured traffic belongs to; line
+    comments and blank lines are left out, so a change of wording keeps the
+    measurement."""
     import hashlib
+    import re
+
+    def code(text):
+        lines = (re.sub(r"//.*", "", ln).rstrip() for ln in text.splitlines())
+        return "\n".join(ln for ln in lines if ln).encode()
+
     h = hashlib.sha256()
-    h.update(open(os.path.join(ROOT, "paper_1511_04552_amd/csrc/lbm_device.h"), "rb").read())
+    h.update(code(open(os.path.join(ROOT, "paper_1511_04552_amd/csrc/lbm_device.h")).read()))
     src = open(os.path.join(ROOT, "paper_1511_04552_amd/csrc/mclbm.hip")).read()
     a = src.index("// One node of one time step")
     b = src.index("// Batched sweep:")
-    h.update(src[a:b].encode())
+    h.update(code(src[a:b]))
     return h.hexdigest()[:16]
 
 
