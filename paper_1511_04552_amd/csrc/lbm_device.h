@@ -5,7 +5,9 @@
 // Lattice (Section 2.d, Eqs 21 and 28): directions rest, E, N, W, S, NE, NW,
 // SW, SE; lattice units dx = dt = 1, c_s^2 = 1/3.
 //
-// Memory layout in HBM (one copy, updated in place):
+// Memory layout in HBM (one copy updated in place by single steps; a second
+// copy when two steps run per launch, each launch writing the copy it does
+// not read):
 //   pop[(l*9 + i)*plane + y*px + x]  l = 0 fluid f, 1 particles p, 2 theta g
 //     (with two thermal lattices, Eq 19 for each phase: 2 fluid temperature
 //     g, 3 particle temperature g2)
