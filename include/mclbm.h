@@ -157,6 +157,19 @@ typedef struct {
 
 typedef struct mclbm_cavity mclbm_cavity; /* opaque host-side handle */
 
+/* Environment variables read when a cavity is created (none changes the
+ * results beyond rounding; the tests use them to reach size-chosen paths on
+ * small cavities):
+ *   MCLBM_LOG=debug      one line on stderr per configuration with the
+ *                        lattice constants and stability numbers
+ *   MCLBM_INDEX64=1      64-bit element offsets (otherwise above 2 GiB of
+ *                        populations; then one step per launch)
+ *   MCLBM_STREAMING=1    non-temporal population access of single steps
+ *                        (otherwise above 160 MiB)
+ *   MCLBM_POISON=1       race check: NaN-fill, before each launch, what it
+ *                        writes and must not read first
+ *   MCLBM_BAND2=<rows>   band height of two steps per launch (tuning) */
+
 /* Fill *cfg with the defaults: 64x64, Ra 1e3, Pr 6.2, phi0 0.01, dp 100 nm,
  * tau_f 0.8, dT 10 K, T0 300 K, all forces at scale 1, amplitude 1e-6,
  * water and alumina properties, FP32 storage, default block shape. */
