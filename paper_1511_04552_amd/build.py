@@ -19,6 +19,23 @@ FLAGS = [
 ]
 
 
+DRIVER_SRC = os.path.join(ROOT, "tests", "c_abi", "cavity_driver.c")
+DRIVER = os.path.join(ROOT, "tests", "c_abi", "cavity_driver")
+
+
+def build_c_driver(verbose: bool = False) -> str:
+    """The plain C program on the C ABI (gcc, host code only; it finds the
+    in-tree library through an rpath relative to itself)."""
+    cmd = ["gcc", "-std=c11", "-O2", "-Wall", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include",
+           "-I", os.path.join(ROOT, "include"), DRIVER_SRC, "-L", HERE, "-lmclbm",
+           "-L/opt/rocm/lib", "-lamdhip64", "-Wl,-rpath,$ORIGIN/../../paper_1511_04552_amd",
+           "-Wl,-rpath,/opt/rocm/lib", "-lm", "-o", DRIVER]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    return DRIVER
+
+
 def build(verbose: bool = False) -> str:
     cmd = [HIPCC, *FLAGS, "-I", os.path.join(ROOT, "include"), "-o", SO + ".tmp", *SRCS]
     if verbose:
