@@ -380,18 +380,20 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def code_text(text: str) -> bytes:
+    """Source text without line comments and blank lines."""
+    import re
+    lines = (re.sub(r"//.*", "", ln).rstrip() for ln in text.splitlines())
+    return "\n".join(ln for ln in lines if ln).encode()
+
+
 def kernel_hash() -> str:
     """Hash of the step kernels' device code (the device header and the text
     from step_node to k_step2), which the measured traffic belongs to; line
     comments and blank lines are left out, so a change of wording keeps the
     measurement."""
     import hashlib
-    import re
-
-    def code(text):
-        lines = (re.sub(r"//.*", "", ln).rstrip() for ln in text.splitlines())
-        return "\n".join(ln for ln in lines if ln).encode()
-
+    code = code_text
     h = hashlib.sha256()
     h.update(code(open(os.path.join(ROOT, "paper_1511_04552_amd/csrc/lbm_device.h")).read()))
     src = open(os.path.join(ROOT, "paper_1511_04552_amd/csrc/mclbm.hip")).read()
