@@ -233,7 +233,9 @@ int mclbm_load_fields(mclbm_cavity* c, const float* dev_fields, int32_t sx,
                       int32_t sy, int32_t nc, const double* affine);
 
 /* Advance nsteps >= 0 time steps (Eqs 18-36: collision with the slip
- * forces, streaming, walls).  Each step is one fused kernel launch.  Async. */
+ * forces, streaming, walls).  Each step is one fused kernel launch, or with
+ * two steps per launch (steps_per_launch) each pair from an even step
+ * count is one launch and a leftover step a single one.  Async. */
 int mclbm_step(mclbm_cavity* c, int64_t nsteps);
 
 /* Number of steps taken since the initial state. */
