@@ -125,31 +125,40 @@ def pmc_summary(fetch_dir, write_dir, workload, out_path, storage="fp32"):
 def batch_measure(torch, mc, inputs, n, steps=64):
     """Uneven-cavity parameter sweep: n cavities with sides from
     {64, 128, 256, 384, 512}, Ra log-uniform in [1e3, 1e6], phi in [0, 5 %],
-    d_p in [10, 100] nm (automatic tau_f), tile shapes from the autotuner,
-    one launch per step replayed from a captured graph."""
-    cfgs = inputs.sweep_parameters(3, n)
-    for c in cfgs:
-        c["tau_f"] = -1.0
-    xis = [inputs.phi_perturbation(c["seed"], c["nx"], c["ny"]) for c in cfgs]
-    b = mc.Batch(cfgs, xis=xis)
-    shapes = b.autotune(steps=8)
-    nodes = sum(c["nx"] * c["ny"] for c in cfgs)
-    b.step(32)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(b.stream)
-    b.step(steps)
-    e1.record(b.stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / steps
-    gbs = BYTES_PER_LUP_FP32 * nodes / (ms * 1e-3) / 1e9
-    out = {"workload": f"sweep of {n} uneven cavities (seed 3)", "nodes": nodes, "steps": steps,
-           "ms_per_step": round(ms, 5), "MLUPS": round(nodes / (ms * 1e-3) / 1e6, 1),
-           "achieved_GBps": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBPS, 4),
-           "tile_shapes": sorted({f"{c['nx']}: {bx}x{by}" for c, (bx, by) in zip(cfgs, shapes)})}
-    b.close()
-    del b
-    torch.cuda.empty_cache()
+    d_p in [10, 100] nm (automatic tau_f), two steps per launch for every
+    cavity with band heights from the autotuner, replayed from a captured
+    graph; beside it the same sweep with one step per launch (tile shapes
+    from the autotuner)."""
+    def run(spl):
+        cfgs = inputs.sweep_parameters(3, n)
+        for c in cfgs:
+            c["tau_f"] = -1.0
+            c["steps_per_launch"] = spl
+        xis = [inputs.phi_perturbation(c["seed"], c["nx"], c["ny"]) for c in cfgs]
+        b = mc.Batch(cfgs, xis=xis)
+        shapes = b.autotune(steps=8)
+        nodes = sum(c["nx"] * c["ny"] for c in cfgs)
+        b.step(32)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(b.stream)
+        b.step(steps)
+        e1.record(b.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        gbs = BYTES_PER_LUP_FP32 / spl * nodes / (ms * 1e-3) / 1e9
+        out = {"workload": f"sweep of {n} uneven cavities (seed 3)", "nodes": nodes, "steps": steps,
+               "steps_per_launch": spl, "ms_per_step": round(ms, 5),
+               "MLUPS": round(nodes / (ms * 1e-3) / 1e6, 1), "achieved_GBps": round(gbs, 1),
+               "frac": round(gbs / HBM_PEAK_GBPS, 4),
+               "tile_shapes": sorted({f"{c['nx']}: {bx}x{by}" for c, (bx, by) in zip(cfgs, shapes)})}
+        b.close()
+        del b
+        torch.cuda.empty_cache()
+        return out
+
+    out = run(2)
+    out["one_step_per_launch"] = run(1)
     return out
 
 

@@ -144,10 +144,12 @@ typedef struct {
                               population copy into a second one (device
                               bytes grow by one population array; 1.25x
                               instead of 2x the bytes of one step, the same
-                              arithmetic); one thermal lattice, populations
-                              below 2 GiB and single cavities only
+                              arithmetic); one thermal lattice and
+                              populations below 2 GiB only
                               (MCLBM_EUNSUPPORTED on request otherwise; the
-                              automatic choice falls back to 1).  A step
+                              automatic choice falls back to 1).  In a
+                              batch: 2 for every cavity or none, and the
+                              automatic choice is 1.  A step
                               count or start that is odd takes single steps
                               where needed.  Results are those of single
                               steps up to rounding (16-bit storage: the
@@ -309,7 +311,11 @@ const char* mclbm_last_error(void);
  * persistent kernel launch per time step updates every active cavity; the
  * step loop is replayed from a captured HIP graph.  Every cavity gives
  * bitwise the same result as the same cavity created alone.  All cavities of
- * a batch share the storage type; each keeps its own workgroup shape. */
+ * a batch share the storage type; each keeps its own workgroup shape.
+ * When every configuration has steps_per_launch = 2, each launch from an
+ * even step runs two steps of every active cavity (tiles of 62 columns by a
+ * band of rows per cavity), as the same cavity alone with two steps per
+ * launch; otherwise one step per launch. */
 typedef struct mclbm_batch mclbm_batch;
 
 /* Bytes of device memory for a batch of n cavities; 0 if any configuration
@@ -326,7 +332,9 @@ int mclbm_batch_create(const mclbm_config* cfgs, int32_t n, const double* const*
 int mclbm_batch_step(mclbm_batch* b, int64_t nsteps);
 
 /* Steps replayed per graph launch (an even number >= 2), or 0 to launch
- * every step directly.  Default 32. */
+ * every step directly.  Default 32.  With two steps per launch a replay of
+ * an odd number of launches makes the next replay rewrite the batch's
+ * device-side descriptors first (a synchronisation). */
 int mclbm_batch_set_graph_steps(mclbm_batch* b, int32_t steps);
 
 /* Mark cavities active (1) or dropped (0); dropped cavities stop stepping
@@ -344,13 +352,16 @@ int mclbm_batch_residual(mclbm_batch* b, double tol, double* out, int32_t* statu
  * Non-finite values are reported as such.  Sync. */
 int mclbm_batch_nusselt(mclbm_batch* b, double* out);
 
-/* Project-written autotuner: for every size class of the batch time
- * `steps` steps with each candidate workgroup shape (256x1, 128x2, 64x4,
- * 32x8), keep the fastest per class, then restart every cavity from its
- * initial state.  The shapes do not change any result.  Sync. */
+/* Project-written autotuner: for every size class of the batch (cavities of
+ * equal nx, ny) time `steps` steps, that class alone, with each candidate
+ * workgroup shape (256x1, 128x2, 64x4, 32x8), or with two steps per launch
+ * each band height of the two-step tiles (3, 4, 6, 8 rows); keep the
+ * fastest per class, then restart every cavity from its initial state.
+ * Neither changes any result.  Sync. */
 int mclbm_batch_autotune(mclbm_batch* b, int32_t steps);
 
-/* Workgroup shape chosen for cavity idx. */
+/* Tile of cavity idx: the workgroup shape (bx, by), or with two steps per
+ * launch the strip width and band height (62, rows). */
 int mclbm_batch_tile_shape(const mclbm_batch* b, int32_t idx, int32_t* bx, int32_t* by);
 
 /* Restart every cavity from its initial state and reactivate it.  Sync. */

@@ -189,11 +189,12 @@ __device__ __forceinline__ float pull_x(float v, int i) {
   return v;
 }
 
+// One tile (strip, band segment seg) of one cavity, by one 64-lane wave.
 template <class S>
-__global__ __launch_bounds__(64) void k_step2(StepParams P, const typename S::T* __restrict__ popA,
-                                              typename S::T* __restrict__ popB,
-                                              const float2* __restrict__ d2p, float2* __restrict__ d2o,
-                                              int strips, int band) {
+__device__ __forceinline__ void step2_tile(const StepParams& P, const typename S::T* __restrict__ popA,
+                                           typename S::T* __restrict__ popB,
+                                           const float2* __restrict__ d2p, float2* __restrict__ d2o,
+                                           int strip, int seg, int band) {
   using I = uint32_t;
   constexpr int UP[3] = {2, 5, 6}, AL[3] = {0, 1, 3}, DN[3] = {4, 7, 8};
   // What a row sends up waits two iterations: a ring of three rows in LDS,
@@ -202,8 +203,6 @@ __global__ __launch_bounds__(64) void k_step2(StepParams P, const typename S::T*
   // step in a two-row ring (left and right wall).
   __shared__ float s_up[3][9][64];
   __shared__ float s_xw[2][2][6];
-  const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int strip = (int)(tile % (unsigned)strips), seg = (int)(tile / (unsigned)strips);
   const int lane = (int)threadIdx.x;
   const int nx = P.nx, ny = P.ny;
   const int x = strip * kStrip2 - 1 + lane;
@@ -380,6 +379,15 @@ __global__ __launch_bounds__(64) void k_step2(StepParams P, const typename S::T*
   }
 }
 
+template <class S>
+__global__ __launch_bounds__(64) void k_step2(StepParams P, const typename S::T* __restrict__ popA,
+                                              typename S::T* __restrict__ popB,
+                                              const float2* __restrict__ d2p, float2* __restrict__ d2o,
+                                              int strips, int band) {
+  const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);
+  step2_tile<S>(P, popA, popB, d2p, d2o, (int)(tile % (unsigned)strips), (int)(tile / (unsigned)strips), band);
+}
+
 // Batched sweep: one launch per time step updates every active cavity of a
 // batch of uneven cavities.  Each entry of the tile table names a cavity and
 // one 256-node tile of it (shape bx x by chosen per cavity); workgroup b
@@ -387,18 +395,25 @@ __global__ __launch_bounds__(64) void k_step2(StepParams P, const typename S::T*
 // entry each).  The table is laid out so that the entries of one XCD are
 // neighbours in space.  The entry count is read from device memory, so a captured
 // graph of this launch stays valid when cavities drop out of the table.
+//
+// Batches with two steps per launch keep two population copies per cavity
+// and a second table of (strip, band) tiles for k_step2_batch.  Every launch
+// of two steps swaps the roles of the copies and of the two lag fields for
+// all active cavities at once; the descriptors hold the roles at the time
+// they were written and each launch takes flip, the number of two-step
+// launches since then modulo 2.
 struct CavDesc {
   StepParams P;
-  void* pop;
+  void* pop[2];  // current and other population copy (the same without a second copy)
   float2* d2[2];
   float* d5;
-  int tiles_x, bx, by, pad;
+  int tiles_x, bx, by, strips2, band2, pad;
 };
 
 template <bool ODD, class S, class I>
 __global__ __launch_bounds__(256) void k_step_batch(const CavDesc* __restrict__ cavs,
                                                     const int2* __restrict__ tiles,
-                                                    const int* __restrict__ ntiles_p) {
+                                                    const int* __restrict__ ntiles_p, int flip) {
   const int ntiles = *ntiles_p;
   for (int k = blockIdx.x; k < ntiles; k += gridDim.x) {
     const int2 tr = tiles[k];
@@ -408,9 +423,24 @@ __global__ __launch_bounds__(256) void k_step_batch(const CavDesc* __restrict__ 
     const int x = (tr.y % C.tiles_x) * bx + (int)threadIdx.x % bx;
     const int y = (tr.y / C.tiles_x) * C.by + (int)threadIdx.x / bx;
     if (x < C.P.nx && y < C.P.ny)
-      step_node<ODD, S, I>(C.P, reinterpret_cast<typename S::T*>(C.pop), C.d2[ODD ? 0 : 1],
-                           C.d2[ODD ? 1 : 0], C.d5, x, y);
+      step_node<ODD, S, I>(C.P, reinterpret_cast<typename S::T*>(C.pop[flip]), C.d2[(ODD ? 0 : 1) ^ flip],
+                           C.d2[(ODD ? 1 : 0) ^ flip], C.d5, x, y);
   }
+}
+
+// Two steps per launch over a batch: one 64-lane workgroup per entry of the
+// (strip, band) table, each running the tile of k_step2.
+template <class S>
+__global__ __launch_bounds__(64) void k_step2_batch(const CavDesc* __restrict__ cavs,
+                                                    const int2* __restrict__ tiles,
+                                                    const int* __restrict__ ntiles_p, int flip) {
+  if ((int)blockIdx.x >= *ntiles_p) return;
+  const int2 tr = tiles[blockIdx.x];
+  if (tr.x < 0) return;  // padding entry
+  const CavDesc& C = cavs[tr.x];
+  using T = typename S::T;
+  step2_tile<S>(C.P, reinterpret_cast<const T*>(C.pop[flip]), reinterpret_cast<T*>(C.pop[flip ^ 1]),
+                C.d2[1 ^ flip], C.d2[flip], tr.y % C.strips2, tr.y / C.strips2, C.band2);
 }
 
 // Block-wide FP64 sum; wave64 shuffles then one LDS slot per wave.
@@ -862,10 +892,25 @@ bool two_step_possible(const mclbm_config& c) {
   return lattices(c) == 3 && pop_bytes(c) < ((size_t)1 << 31);
 }
 bool two_step(const mclbm_config& c, bool batch_member) {
-  if (batch_member || !two_step_possible(c)) return false;
+  if (!two_step_possible(c)) return false;
   if (c.steps_per_launch != 0) return c.steps_per_launch == 2;
+  if (batch_member) return false;  // batches: on request only
   return c.storage == MCLBM_FP32S && (long long)c.nx * c.ny >= (1LL << 20) && c.nx >= 256;
 }
+
+// Band height of the two-step kernel: 6 rows below 2^21 nodes and 4 from
+// there on (of 3 to 32 rows, the fastest or within 1 % of it at 1024^2,
+// 1536^2, 2048^2, 3072^2 and 4096^2: more waves in flight outweigh the halo
+// rows recomputed, whose loads hit in L2); MCLBM_BAND2 sets it (tuning knob).
+int band2_of(const mclbm_config& c) {
+  int band = (long long)c.nx * c.ny >= (1LL << 21) ? 4 : 6;
+  if (const char* e = std::getenv("MCLBM_BAND2")) {
+    const int v = std::atoi(e);
+    if (v >= 1 && v <= 65536) band = v;
+  }
+  return band;
+}
+int strips2_of(const mclbm_config& c) { return (c.nx + kStrip2 - 1) / kStrip2; }
 
 Layout make_layout(const mclbm_config& c, bool batch_member = false) {
   Layout L{};
@@ -1245,20 +1290,11 @@ int setup_cavity(mclbm_cavity* c) {
   if (env_flag("MCLBM_INDEX64")) c->idx32 = false;
   if (env_flag("MCLBM_STREAMING")) c->nt = true;
   c->poison = env_flag("MCLBM_POISON");
-  // two steps per launch: strips of kStrip2 columns, bands of 6 rows below
-  // 2^21 nodes and 4 from there on (of 3 to 32 rows, the fastest or within
-  // 1 % of it at 1024^2, 1536^2, 2048^2, 3072^2 and 4096^2: more waves in
-  // flight outweigh the halo rows recomputed, whose loads hit in L2)
+  // two steps per launch: strips of kStrip2 columns, bands of band2 rows
   c->two = two_step(c->cfg, c->in_batch) && c->idx32;
-  c->strips2 = (c->cfg.nx + kStrip2 - 1) / kStrip2;
-  int band = (long long)c->cfg.nx * c->cfg.ny >= (1LL << 21) ? 4 : 6;
-  if (const char* e = std::getenv("MCLBM_BAND2")) {
-    // tuning knob: band height of the two-step kernel
-    const int v = std::atoi(e);
-    if (v >= 1 && v <= 65536) band = v;
-  }
-  c->band2 = band;
-  c->nblocks2 = (unsigned)c->strips2 * (unsigned)((c->cfg.ny + band - 1) / band);
+  c->strips2 = strips2_of(c->cfg);
+  c->band2 = band2_of(c->cfg);
+  c->nblocks2 = (unsigned)c->strips2 * (unsigned)((c->cfg.ny + c->band2 - 1) / c->band2);
   return MCLBM_OK;
 }
 
@@ -1867,16 +1903,18 @@ struct mclbm_batch {
   hipStream_t cap_stream = nullptr;  // private stream the step graph is captured on
   char* base = nullptr;
   size_t bytes = 0;
-  size_t off_desc = 0, off_ntiles = 0, off_tiles = 0;
-  int tile_cap = 0;
+  size_t off_desc = 0, off_ntiles = 0, off_tiles = 0, off_ntiles2 = 0, off_tiles2 = 0;
+  int tile_cap = 0, tile_cap2 = 0;
   std::vector<char> active;
   std::vector<CavDesc> host_desc;
-  std::vector<int2> host_tiles;
-  int ntiles = 0;
+  std::vector<int2> host_tiles, host_tiles2;
+  int ntiles = 0, ntiles2 = 0;
+  bool two = false;  // two steps per launch (k_step2_batch) from even steps
+  int flip = 0;      // two-step launches since the descriptors were written, mod 2
   int64_t t = 0;  // steps of the active cavities
   int storage = MCLBM_FP32S;
   bool nt = false, idx32 = true;
-  unsigned grid = 0;
+  unsigned grid = 0, grid2 = 0;
   int graph_steps = 32;
   hipGraphExec_t gexec = nullptr;
   int gexec_steps = 0;
@@ -1884,6 +1922,8 @@ struct mclbm_batch {
   CavDesc* d_desc() { return reinterpret_cast<CavDesc*>(base + off_desc); }
   int* d_ntiles() { return reinterpret_cast<int*>(base + off_ntiles); }
   int2* d_tiles() { return reinterpret_cast<int2*>(base + off_tiles); }
+  int* d_ntiles2() { return reinterpret_cast<int*>(base + off_ntiles2); }
+  int2* d_tiles2() { return reinterpret_cast<int2*>(base + off_tiles2); }
 };
 
 namespace {
@@ -1893,28 +1933,46 @@ constexpr int kShapes[4][2] = {{256, 1}, {128, 2}, {64, 4}, {32, 8}};
 int tiles_of(int nx, int ny, int bx, int by) { return ((nx + bx - 1) / bx) * ((ny + by - 1) / by); }
 
 struct BatchLayout {
-  size_t off_desc, off_ntiles, off_tiles, total;
-  int tile_cap;
+  size_t off_desc, off_ntiles, off_tiles, off_ntiles2, off_tiles2, total;
+  int tile_cap, tile_cap2;
+  bool two;
   std::vector<size_t> off_cav;
 };
 
+// band heights the autotuner tries for two-step batches
+constexpr int kBands2[4] = {3, 4, 6, 8};
+
+// two-step tiles of a cavity at the lowest band the batch may use
+int tiles2_of(const mclbm_config& c) {
+  const int band = std::min(kBands2[0], band2_of(c));
+  return strips2_of(c) * ((c.ny + band - 1) / band);
+}
+
 int batch_layout(const mclbm_config* cfgs, int n, BatchLayout& B) {
   if (!cfgs || n < 1) return fail(MCLBM_EINVAL, "batch needs n >= 1 configurations");
-  long long cap = 0;
+  long long cap = 0, cap2 = 0;
+  int n2 = 0;  // cavities asking for two steps per launch
   for (int k = 0; k < n; ++k) {
     int rc = validate(&cfgs[k]);
     if (rc) return fail(rc, "cavity " + std::to_string(k) + ": " + g_err);
     if (cfgs[k].storage != cfgs[0].storage) return fail(MCLBM_EINVAL, "all cavities of a batch share the storage type");
     if (cfgs[k].thermal_lattices == 2)
       return fail(MCLBM_EUNSUPPORTED, "cavity " + std::to_string(k) + ": batches take one thermal lattice");
-    if (cfgs[k].steps_per_launch == 2)
-      return fail(MCLBM_EUNSUPPORTED, "cavity " + std::to_string(k) + ": batches run one step per launch");
+    if (cfgs[k].steps_per_launch == 2) {
+      ++n2;
+      cap2 += tiles2_of(cfgs[k]);
+    }
     int m = 0;
     for (const auto& sh : kShapes) m = std::max(m, tiles_of(cfgs[k].nx, cfgs[k].ny, sh[0], sh[1]));
     cap += m;
   }
-  if (cap > (1LL << 30)) return fail(MCLBM_EINVAL, "batch too large");
+  if (n2 != 0 && n2 != n)
+    return fail(MCLBM_EUNSUPPORTED,
+                "a batch runs every cavity one step per launch, or every cavity two (steps_per_launch 2 for all)");
+  if (cap > (1LL << 30) || cap2 > (1LL << 30)) return fail(MCLBM_EINVAL, "batch too large");
+  B.two = n2 == n;
   B.tile_cap = (int)(8 * ((cap + 7) / 8) + 8);
+  B.tile_cap2 = B.two ? (int)(8 * ((cap2 + 7) / 8) + 8) : 0;
   size_t off = 0;
   B.off_desc = off;
   off = align_up(off + (size_t)n * sizeof(CavDesc));
@@ -1922,6 +1980,10 @@ int batch_layout(const mclbm_config* cfgs, int n, BatchLayout& B) {
   off = align_up(off + sizeof(int));
   B.off_tiles = off;
   off = align_up(off + (size_t)B.tile_cap * sizeof(int2));
+  B.off_ntiles2 = off;
+  off = align_up(off + sizeof(int));
+  B.off_tiles2 = off;
+  off = align_up(off + (size_t)B.tile_cap2 * sizeof(int2));
   B.off_cav.resize(n);
   for (int k = 0; k < n; ++k) {
     B.off_cav[k] = off;
@@ -1934,13 +1996,16 @@ int batch_layout(const mclbm_config* cfgs, int n, BatchLayout& B) {
 CavDesc make_desc(mclbm_cavity* c) {
   CavDesc d{};
   d.P = c->P;
-  d.pop = c->pop();
+  d.pop[0] = c->pop();
+  d.pop[1] = c->two ? c->pop_other() : c->pop();
   d.d2[0] = c->d2(0);
   d.d2[1] = c->d2(1);
   d.d5 = c->d5();
   d.bx = (int)c->block.x;
   d.by = (int)c->block.y;
   d.tiles_x = c->tiles_x;
+  d.strips2 = c->strips2;
+  d.band2 = c->band2;
   return d;
 }
 
@@ -1949,25 +2014,39 @@ CavDesc make_desc(mclbm_cavity* c) {
 // j, j + 8, j + 16, ... so that the workgroups one XCD receives (b = j mod 8
 // under round-robin dealing) sweep one contiguous band.  Then uploaded with
 // the descriptors.  Sync.
+void deal_to_xcds(const std::vector<int2>& list, std::vector<int2>& table) {
+  const int L = (int)list.size();
+  const int m = (L + 7) / 8;
+  table.assign((size_t)8 * m, make_int2(-1, 0));
+  for (int j = 0; j < 8; ++j)
+    for (int q = 0; q < m; ++q) {
+      const int src = j * m + q;
+      if (src < L) table[(size_t)8 * q + j] = list[src];
+    }
+}
+
+// With two steps per launch, the (strip, band) tiles of each active cavity
+// (band-row-major) form the second table, dealt to the XCDs the same way.
+// The descriptors take the current roles of the copies: flip restarts at 0.
 int upload_tables(mclbm_batch* b) {
-  std::vector<int2> list;
+  std::vector<int2> list, list2;
   for (int k = 0; k < b->n; ++k) {
     if (b->cav[k].block.x * b->cav[k].block.y != 256)
       return fail(MCLBM_EINVAL, "batched tiles must cover 256 nodes");
     if (!b->active[k]) continue;
     const int nt = tiles_of(b->cav[k].cfg.nx, b->cav[k].cfg.ny, b->cav[k].block.x, b->cav[k].block.y);
     for (int t = 0; t < nt; ++t) list.push_back(make_int2(k, t));
-  }
-  const int L = (int)list.size();
-  const int m = (L + 7) / 8;
-  b->host_tiles.assign((size_t)8 * m, make_int2(-1, 0));
-  for (int j = 0; j < 8; ++j)
-    for (int q = 0; q < m; ++q) {
-      const int src = j * m + q;
-      if (src < L) b->host_tiles[(size_t)8 * q + j] = list[src];
+    if (b->two) {
+      const int nt2 = b->cav[k].strips2 * ((b->cav[k].cfg.ny + b->cav[k].band2 - 1) / b->cav[k].band2);
+      for (int t = 0; t < nt2; ++t) list2.push_back(make_int2(k, t));
     }
-  b->ntiles = 8 * m;
+  }
+  deal_to_xcds(list, b->host_tiles);
+  b->ntiles = (int)b->host_tiles.size();
   if (b->ntiles > b->tile_cap) return fail(MCLBM_EINVAL, "tile table overflow");
+  deal_to_xcds(list2, b->host_tiles2);
+  b->ntiles2 = (int)b->host_tiles2.size();
+  if (b->ntiles2 > b->tile_cap2) return fail(MCLBM_EINVAL, "two-step tile table overflow");
   b->host_desc.resize(b->n);
   for (int k = 0; k < b->n; ++k) b->host_desc[k] = make_desc(&b->cav[k]);
   HIP_TRY(hipMemcpyAsync(b->d_desc(), b->host_desc.data(), b->host_desc.size() * sizeof(CavDesc),
@@ -1976,17 +2055,36 @@ int upload_tables(mclbm_batch* b) {
     HIP_TRY(hipMemcpyAsync(b->d_tiles(), b->host_tiles.data(), (size_t)b->ntiles * sizeof(int2),
                            hipMemcpyHostToDevice, b->stream));
   HIP_TRY(hipMemcpyAsync(b->d_ntiles(), &b->ntiles, sizeof(int), hipMemcpyHostToDevice, b->stream));
+  if (b->two) {
+    if (b->ntiles2 > 0)
+      HIP_TRY(hipMemcpyAsync(b->d_tiles2(), b->host_tiles2.data(), (size_t)b->ntiles2 * sizeof(int2),
+                             hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(hipMemcpyAsync(b->d_ntiles2(), &b->ntiles2, sizeof(int), hipMemcpyHostToDevice, b->stream));
+  }
   HIP_TRY(hipStreamSynchronize(b->stream));
+  b->flip = 0;
   return MCLBM_OK;
 }
 
 template <class K>
-void batch_launch(mclbm_batch* b, hipStream_t s, bool odd) {
+void batch_launch(mclbm_batch* b, hipStream_t s, bool odd, int flip) {
   using I = typename K::I;
   if (!odd)
-    k_step_batch<false, typename K::SE, I><<<b->grid, 256, 0, s>>>(b->d_desc(), b->d_tiles(), b->d_ntiles());
+    k_step_batch<false, typename K::SE, I><<<b->grid, 256, 0, s>>>(b->d_desc(), b->d_tiles(), b->d_ntiles(), flip);
   else
-    k_step_batch<true, typename K::SO, I><<<b->grid, 256, 0, s>>>(b->d_desc(), b->d_tiles(), b->d_ntiles());
+    k_step_batch<true, typename K::SO, I><<<b->grid, 256, 0, s>>>(b->d_desc(), b->d_tiles(), b->d_ntiles(), flip);
+}
+
+// Two steps (even, odd) of every active cavity; cached access at every size,
+// as for a single cavity.
+template <class K>
+int batch_launch2(mclbm_batch* b, hipStream_t s, int flip) {
+  if constexpr (sizeof(typename K::I) == 4) {
+    k_step2_batch<typename K::S><<<b->grid2, 64, 0, s>>>(b->d_desc(), b->d_tiles2(), b->d_ntiles2(), flip);
+    return MCLBM_OK;
+  } else {
+    return fail(MCLBM_EUNSUPPORTED, "two steps per launch: 32-bit offsets only");
+  }
 }
 
 void batch_advance(mclbm_batch* b, int64_t k) {
@@ -1995,15 +2093,43 @@ void batch_advance(mclbm_batch* b, int64_t k) {
     if (b->active[c]) b->cav[c].t += k;
 }
 
+// after `launches` two-step launches: the copies and lag fields of every
+// active cavity have swapped roles that many times
+void batch_advance2(mclbm_batch* b, int64_t launches) {
+  batch_advance(b, 2 * launches);
+  if (launches & 1) {
+    for (int c = 0; c < b->n; ++c)
+      if (b->active[c]) {
+        b->cav[c].popsel ^= 1;
+        b->cav[c].d2sel ^= 1;
+      }
+    b->flip ^= 1;
+  }
+}
+
 int batch_direct_step(mclbm_batch* b) {
   int rc = dispatch_kinds(b->storage, b->idx32, b->nt, [&](auto k) {
-    batch_launch<decltype(k)>(b, b->stream, (b->t & 1) != 0);
+    batch_launch<decltype(k)>(b, b->stream, (b->t & 1) != 0, b->flip);
     return launch_check("k_step_batch");
   });
   if (rc) return rc;
   batch_advance(b, 1);
   return MCLBM_OK;
 }
+
+int batch_direct_step2(mclbm_batch* b) {
+  int rc = dispatch_kinds(b->storage, b->idx32, b->nt, [&](auto k) {
+    int r = batch_launch2<decltype(k)>(b, b->stream, b->flip);
+    if (r) return r;
+    return launch_check("k_step2_batch");
+  });
+  if (rc) return rc;
+  batch_advance2(b, 1);
+  return MCLBM_OK;
+}
+
+// launches in one replay of the step graph
+int graph_launches(const mclbm_batch* b) { return b->two ? b->graph_steps / 2 : b->graph_steps; }
 
 void drop_graph(mclbm_batch* b) {
   if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
@@ -2012,12 +2138,21 @@ void drop_graph(mclbm_batch* b) {
 }
 
 // Capture graph_steps launches (even, odd, even, ...) on the private
-// stream; the graph is replayed on the batch's stream.
+// stream, or graph_steps / 2 two-step launches with flip 0, 1, 0, ...; the
+// graph is replayed on the batch's stream, from even steps and (two steps
+// per launch) descriptors written with flip 0.
 int capture_graph(mclbm_batch* b) {
   drop_graph(b);
   HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
   int rc = dispatch_kinds(b->storage, b->idx32, b->nt, [&](auto k) {
-    for (int q = 0; q < b->graph_steps; ++q) batch_launch<decltype(k)>(b, b->cap_stream, (q & 1) != 0);
+    for (int q = 0; q < graph_launches(b); ++q) {
+      if (b->two) {
+        int r = batch_launch2<decltype(k)>(b, b->cap_stream, q & 1);
+        if (r) return r;
+      } else {
+        batch_launch<decltype(k)>(b, b->cap_stream, (q & 1) != 0, 0);
+      }
+    }
     return (int)MCLBM_OK;
   });
   hipGraph_t g = nullptr;
@@ -2077,6 +2212,10 @@ int mclbm_batch_create(const mclbm_config* cfgs, int32_t n, const double* const*
   b->off_ntiles = B.off_ntiles;
   b->off_tiles = B.off_tiles;
   b->tile_cap = B.tile_cap;
+  b->off_ntiles2 = B.off_ntiles2;
+  b->off_tiles2 = B.off_tiles2;
+  b->tile_cap2 = B.tile_cap2;
+  b->two = B.two;
   b->storage = cfgs[0].storage;
   b->cav.resize(n);
   b->active.assign(n, 1);
@@ -2120,6 +2259,7 @@ int mclbm_batch_create(const mclbm_config* cfgs, int32_t n, const double* const*
   // takes in turn; separate workgroups overlap them.
   (void)ncu;
   b->grid = (unsigned)B.tile_cap;
+  b->grid2 = (unsigned)B.tile_cap2;
   hipError_t e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
   if (e != hipSuccess) {
     delete b;
@@ -2143,13 +2283,25 @@ int mclbm_batch_step(mclbm_batch* b, int64_t nsteps) {
   if (!any) return MCLBM_OK;
   while (nsteps > 0) {
     if (b->graph_steps > 0 && nsteps >= b->graph_steps && (b->t & 1) == 0) {
+      if (b->flip) {
+        // the graph was captured for descriptors written with flip 0
+        int rc = upload_tables(b);
+        if (rc) return rc;
+      }
       if (!b->gexec || b->gexec_steps != b->graph_steps) {
         int rc = capture_graph(b);
         if (rc) return rc;
       }
       HIP_TRY(hipGraphLaunch(b->gexec, b->stream));
-      batch_advance(b, b->graph_steps);
+      if (b->two)
+        batch_advance2(b, graph_launches(b));
+      else
+        batch_advance(b, b->graph_steps);
       nsteps -= b->graph_steps;
+    } else if (b->two && nsteps >= 2 && (b->t & 1) == 0) {
+      int rc = batch_direct_step2(b);
+      if (rc) return rc;
+      nsteps -= 2;
     } else {
       int rc = batch_direct_step(b);
       if (rc) return rc;
@@ -2217,11 +2369,27 @@ int mclbm_batch_nusselt(mclbm_batch* b, double* out) {
   return MCLBM_OK;
 }
 
+namespace {
+
+void set_band2(mclbm_cavity* c, int band) {
+  c->band2 = band;
+  c->nblocks2 = (unsigned)c->strips2 * (unsigned)((c->cfg.ny + band - 1) / band);
+}
+
+void set_shape(mclbm_cavity* c, int si) {
+  c->block = dim3(kShapes[si][0], kShapes[si][1], 1);
+  c->tiles_x = (c->cfg.nx + kShapes[si][0] - 1) / kShapes[si][0];
+}
+
+}  // namespace
+
+// Per size class (cavities of equal nx, ny), time each candidate with only
+// that class active: the tile shape of the one-step kernel, or with two
+// steps per launch the band height of the two-step tiles.
 int mclbm_batch_autotune(mclbm_batch* b, int32_t steps) {
   if (!b) return fail(MCLBM_EINVAL, "batch is NULL");
   if (steps < 2) return fail(MCLBM_EINVAL, "autotune needs >= 2 steps per trial");
   HIP_TRY(hipStreamSynchronize(b->stream));
-  std::vector<char> saved_active = b->active;
   const int saved_graph = b->graph_steps;
   b->graph_steps = 0;
   // size classes
@@ -2230,21 +2398,29 @@ int mclbm_batch_autotune(mclbm_batch* b, int32_t steps) {
     auto key = std::make_pair(b->cav[k].cfg.nx, b->cav[k].cfg.ny);
     if (std::find(classes.begin(), classes.end(), key) == classes.end()) classes.push_back(key);
   }
+  const int ncand = 4;
+  auto apply = [&](mclbm_cavity* c, int ci) {
+    if (b->two)
+      set_band2(c, kBands2[ci]);
+    else
+      set_shape(c, ci);
+  };
+  auto trial_step = [&]() { return b->two ? batch_direct_step2(b) : batch_direct_step(b); };
+  const int trials = b->two ? std::max(1, steps / 2) : steps;
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
   int rc = MCLBM_OK;
   for (const auto& cl : classes) {
     float best = 1e30f;
-    int best_s = 0;
-    for (int si = 0; si < 4 && !rc; ++si) {
+    int best_c = 0;
+    for (int ci = 0; ci < ncand && !rc; ++ci) {
       for (int k = 0; k < b->n; ++k) {
         mclbm_cavity* c = &b->cav[k];
         const bool in = c->cfg.nx == cl.first && c->cfg.ny == cl.second;
         b->active[k] = in ? 1 : 0;
         if (in) {
-          c->block = dim3(kShapes[si][0], kShapes[si][1], 1);
-          c->tiles_x = (c->cfg.nx + kShapes[si][0] - 1) / kShapes[si][0];
+          apply(c, ci);
           rc = enqueue_init(c);
           if (rc) break;
         }
@@ -2253,10 +2429,10 @@ int mclbm_batch_autotune(mclbm_batch* b, int32_t steps) {
       b->t = 0;
       rc = upload_tables(b);
       if (rc) break;
-      for (int w = 0; w < 2 && !rc; ++w) rc = batch_direct_step(b);
+      for (int w = 0; w < 2 && !rc; ++w) rc = trial_step();
       if (rc) break;
       HIP_TRY(hipEventRecord(e0, b->stream));
-      for (int q = 0; q < steps && !rc; ++q) rc = batch_direct_step(b);
+      for (int q = 0; q < trials && !rc; ++q) rc = trial_step();
       HIP_TRY(hipEventRecord(e1, b->stream));
       if (rc) break;
       hipError_t he = hipEventSynchronize(e1);
@@ -2268,31 +2444,28 @@ int mclbm_batch_autotune(mclbm_batch* b, int32_t steps) {
       HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
       if (ms < best) {
         best = ms;
-        best_s = si;
+        best_c = ci;
       }
     }
     if (rc) break;
     for (int k = 0; k < b->n; ++k) {
       mclbm_cavity* c = &b->cav[k];
-      if (c->cfg.nx == cl.first && c->cfg.ny == cl.second) {
-        c->block = dim3(kShapes[best_s][0], kShapes[best_s][1], 1);
-        c->tiles_x = (c->cfg.nx + kShapes[best_s][0] - 1) / kShapes[best_s][0];
-      }
+      if (c->cfg.nx == cl.first && c->cfg.ny == cl.second) apply(c, best_c);
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   b->graph_steps = saved_graph;
   drop_graph(b);
-  (void)saved_active;
   if (rc) return rc;
   return batch_reset_all(b);
 }
 
 int mclbm_batch_tile_shape(const mclbm_batch* b, int32_t idx, int32_t* bx, int32_t* by) {
   if (!b || idx < 0 || idx >= b->n) return fail(MCLBM_EINVAL, "bad batch index");
-  if (bx) *bx = (int32_t)b->cav[idx].block.x;
-  if (by) *by = (int32_t)b->cav[idx].block.y;
+  const mclbm_cavity& c = b->cav[idx];
+  if (bx) *bx = b->two ? (int32_t)kStrip2 : (int32_t)c.block.x;
+  if (by) *by = b->two ? (int32_t)c.band2 : (int32_t)c.block.y;
   return MCLBM_OK;
 }
 

@@ -1,0 +1,168 @@
+"""Batches with two steps per launch (k_step2_batch): every cavity asks for
+steps_per_launch 2; each launch runs an even and an odd step of every active
+cavity from one population copy into the other.  Bitwise against the same
+cavities run alone with two steps per launch (the tile arithmetic is the
+same), through graph replays, direct launches, drop-out and rejoining, and
+against the oracle."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import oracle  # noqa: E402
+import paper_1511_04552_amd as mc  # noqa: E402
+from paper_1511_04552_amd import inputs  # noqa: E402
+
+# one strip (16, 37, 62 columns) up to five (300), ragged bands, an empty
+# particle phase (phi0 = 0) and the automatic relaxation time
+CFGS = [dict(nx=16, ny=16, Ra=1e4, phi0=0.01, dp_nm=100.0),
+        dict(nx=37, ny=29, Ra=3e4, phi0=0.02, dp_nm=40.0),
+        dict(nx=62, ny=64, Ra=1e3, phi0=0.01, dp_nm=100.0),
+        dict(nx=100, ny=70, Ra=2e5, phi0=0.04, dp_nm=30.0, tau_f=-1.0),
+        dict(nx=300, ny=40, Ra=5e4, phi0=0.0, dp_nm=60.0)]
+TWO = [dict(c, steps_per_launch=2) for c in CFGS]
+
+
+def _xis(cfgs, seed=31):
+    return [inputs.phi_perturbation(seed + k, c["nx"], c["ny"]) for k, c in enumerate(cfgs)]
+
+
+def _single(k, xis, steps):
+    c = mc.Cavity(xi=xis[k], **TWO[k])
+    for n in steps:
+        c.step(n)
+    return c
+
+
+def test_two_step_batch_bitwise_equals_single_cavities():
+    """301 steps: nine graph replays of 16 launches, six direct two-step
+    launches, one single step."""
+    xis = _xis(CFGS)
+    b = mc.Batch(TWO, xis=xis)
+    b.step(301)
+    for k in range(len(CFGS)):
+        assert b.time(k) == 301
+        assert np.array_equal(b.members[k].populations(), _single(k, xis, [301]).populations()), k
+    assert np.isfinite(b.nusselt()).all()
+
+
+def test_two_step_batch_matches_oracle():
+    """Members 1-4 after 1001 steps at the parity bar.  Member 4 has phi0 = 0:
+    the +-1e-6 perturbation leaves about 4e-6 of particle density at half its
+    nodes, where the particle velocity j_p / rho_p is ill-conditioned in FP32
+    (about 1e-4 of its scale by then, alone or batched), so its particle
+    velocities are left out."""
+    xis = _xis(CFGS)
+    b = mc.Batch(TWO, xis=xis)
+    b.step(1001)
+    for k in (1, 2, 3, 4):
+        o = oracle.Oracle(xi=xis[k], **CFGS[k])
+        o.step(1001)
+        mg, mo = b.members[k].moments(), o.moments()
+        for f in mo:
+            if k == 4 and f in ("ux_p", "uy_p"):
+                continue
+            scale = np.abs(mo[f]).max()
+            if scale > 0:
+                assert np.abs(mg[f] - mo[f]).max() <= 1e-5 * scale, (k, f)
+        for a, c in zip(b.members[k].nusselt(), o.nusselt()):
+            assert abs(a - c) <= 1e-4 * max(abs(c), 1.0)
+
+
+@pytest.mark.parametrize("graph_steps", [8, 6])
+def test_two_step_graph_replays_equal_direct_launches(graph_steps):
+    """Replays of 4 launches (even: the copies come back to their roles) and
+    of 3 (odd: the descriptors are written again before the next replay),
+    with eager work between them, against direct launches."""
+    xis = _xis(CFGS)
+    g = mc.Batch(TWO, xis=xis, graph_steps=graph_steps)
+    d = mc.Batch(TWO, xis=xis, graph_steps=0)
+    for rep in range(4):
+        g.step(graph_steps)
+        d.step(graph_steps)
+        torch.cuda.synchronize()
+        scratch = torch.zeros(1 << 20, device="cuda")
+        scratch += 1.0
+        torch.cuda.synchronize()
+        for k in range(len(CFGS)):
+            assert np.array_equal(g.members[k].populations(), d.members[k].populations()), (rep, k)
+
+
+def test_two_step_dropout_and_rejoin():
+    """Cavities dropped after an odd number of two-step launches keep their
+    state; they rejoin (even distance) with their copies in other roles than
+    the rest of the batch and continue bitwise like single runs."""
+    xis = _xis(CFGS)
+    b = mc.Batch(TWO, xis=xis)
+    b.step(202)  # graph replays and one direct launch: an odd launch count
+    b.set_active([1, 0, 1, 0, 1])
+    frozen = {k: b.members[k].populations() for k in (1, 3)}
+    b.step(34)
+    for k in (1, 3):
+        assert b.time(k) == 202
+        assert np.array_equal(b.members[k].populations(), frozen[k])
+    b.set_active([1, 1, 1, 1, 1])
+    b.step(66)
+    assert [b.time(k) for k in range(5)] == [302, 268, 302, 268, 302]
+    for k in range(5):
+        ref = _single(k, xis, [202, 66] if k in (1, 3) else [202, 34, 66])
+        assert np.array_equal(b.members[k].populations(), ref.populations()), k
+    # a single step leaves the batch at an odd step: two-step launches wait
+    # for the next even step, and a cavity at odd distance cannot rejoin
+    b.set_active([1, 0, 1, 1, 1])
+    b.step(1)
+    with pytest.raises(mc.MclbmError):
+        b.set_active([1, 1, 1, 1, 1])
+    b.step(3)  # an odd single step, then one direct two-step launch
+    ref = _single(0, xis, [202, 34, 66, 1, 3])
+    assert np.array_equal(b.members[0].populations(), ref.populations())
+    # converge-and-drop right after a direct launch
+    res, st = b.residual(tol=1e30)
+    assert list(st) == [1, 3, 1, 1, 1]
+    t0 = [b.time(k) for k in range(5)]
+    b.step(10)
+    assert [b.time(k) for k in range(5)] == t0
+
+
+def test_two_step_batch_reset_and_member_checkpoint(tmp_path):
+    """reset restarts every cavity (whichever copy is current); a member's
+    checkpoint resumes in a single cavity like the batch continues."""
+    xis = _xis(CFGS)
+    b = mc.Batch(TWO, xis=xis)
+    b.step(70)
+    b.reset()
+    b.step(34)
+    for k in range(len(CFGS)):
+        assert np.array_equal(b.members[k].populations(), _single(k, xis, [34]).populations()), k
+    path = tmp_path / "m3.ckpt"
+    b.members[3].checkpoint(path)
+    b.step(40)
+    c = mc.Cavity(xi=xis[3], **TWO[3])
+    c.restore(path)
+    c.step(40)
+    assert np.array_equal(c.populations(), b.members[3].populations())
+
+
+def test_two_step_autotune_picks_bands_without_changing_results():
+    """The autotuner picks a band height per size class; the band only
+    decides which halo rows are recomputed, so results stay bitwise."""
+    xis = _xis(CFGS)
+    b = mc.Batch(TWO, xis=xis)
+    b.step(8)
+    shapes = b.autotune(steps=4)
+    assert all(bx == 62 and by in (3, 4, 6, 8) for bx, by in shapes), shapes
+    assert all(b.time(k) == 0 for k in range(len(CFGS)))
+    b.step(65)
+    for k in range(len(CFGS)):
+        assert np.array_equal(b.members[k].populations(), _single(k, xis, [65]).populations()), k
+
+
+def test_mixed_schedules_rejected():
+    with pytest.raises(mc.MclbmError, match="every cavity two"):
+        mc.Batch([dict(nx=16, ny=16, steps_per_launch=2), dict(nx=16, ny=16)])
+    with pytest.raises(mc.MclbmError):
+        mc.Batch([dict(nx=16, ny=16, steps_per_launch=2, thermal_lattices=2)])
