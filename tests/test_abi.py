@@ -97,6 +97,32 @@ def test_two_steps_per_launch_sizes_and_limits():
         assert e.value.code == mc.EUNSUPPORTED
 
 
+def _batch_bytes(cfgs):
+    arr = (mc.Config * len(cfgs))(*[mc.make_config(**c) for c in cfgs])
+    return mc.lib().mclbm_batch_device_bytes(arr, len(cfgs))
+
+
+def test_batch_sizes_with_two_steps_per_launch():
+    """A batch with two steps per launch adds, per cavity, a second
+    population copy, and a second tile table with one 8-byte entry per
+    (62-column strip, band) tile at the lowest band the autotuner tries
+    (3 rows), padded to the 8 XCDs.  Every cavity asks for it or none."""
+    cfgs = [dict(nx=64, ny=64), dict(nx=100, ny=70), dict(nx=300, ny=40)]
+    one = _batch_bytes(cfgs)
+    two = _batch_bytes([dict(c, steps_per_launch=2) for c in cfgs])
+    pops = sum(27 * 4 * ((c["nx"] + 63) // 64 * 64) * c["ny"] for c in cfgs)
+    tiles = sum(-(-c["nx"] // 62) * -(-c["ny"] // 3) for c in cfgs)
+    cap = 8 * -(-tiles // 8) + 8
+    table = -(-8 * cap // 256) * 256  # 256-byte aligned (the entry count is reserved either way)
+    assert one > 0 and two == one + pops + table
+    L = mc.lib()
+    assert _batch_bytes([dict(nx=16, ny=16, steps_per_launch=2), dict(nx=16, ny=16)]) == 0
+    assert "every cavity two" in L.mclbm_last_error().decode()
+    assert _batch_bytes([dict(nx=16, ny=16, steps_per_launch=2, thermal_lattices=2)]) == 0
+    # the automatic choice stays one step per launch in a batch
+    assert _batch_bytes([dict(nx=2048, ny=2048)]) == _batch_bytes([dict(nx=2048, ny=2048, steps_per_launch=1)])
+
+
 def test_create_rejects_small_or_misaligned_buffers_without_touching_them():
     L = mc.lib()
     c = mc.make_config(nx=16, ny=16)
