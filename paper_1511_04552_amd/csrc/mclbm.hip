@@ -11,6 +11,7 @@
 //   k_step2     the same physics for an even and the following odd step in
 //               one launch, between two population copies (large cavities)
 //   k_step_batch  one launch per step over a batch of uneven cavities
+//   k_step2_batch two steps per launch over such a batch (tiles of k_step2)
 //   k_nusselt   FP64 wall-Nusselt reduction
 //   k_residual  FP64 relative change of u_ns and theta (steady-state test)
 //   k_export    FP64 moments / populations of the current state
