@@ -147,9 +147,13 @@ typedef struct {
                               arithmetic); one thermal lattice and
                               populations below 2 GiB only
                               (MCLBM_EUNSUPPORTED on request otherwise; the
-                              automatic choice falls back to 1).  In a
-                              batch: 2 for every cavity or none, and the
-                              automatic choice is 1.  A step
+                              automatic choice falls back to 1).  A batch
+                              takes one schedule for all its cavities: 2
+                              if every cavity asks for 2 (a batch mixing
+                              2 with 0 or 1 is rejected), or if every
+                              cavity leaves 0 and the batch holds FP32
+                              cavities of 2^20 nodes in total that fill at
+                              least 60 % of their 62-column strips; else 1.  A step
                               count or start that is odd takes single steps
                               where needed.  Results are those of single
                               steps up to rounding (16-bit storage: the
@@ -312,10 +316,10 @@ const char* mclbm_last_error(void);
  * step loop is replayed from a captured HIP graph.  Every cavity gives
  * bitwise the same result as the same cavity created alone.  All cavities of
  * a batch share the storage type; each keeps its own workgroup shape.
- * When every configuration has steps_per_launch = 2, each launch from an
- * even step runs two steps of every active cavity (tiles of 62 columns by a
- * band of rows per cavity), as the same cavity alone with two steps per
- * launch; otherwise one step per launch. */
+ * With two steps per launch (steps_per_launch in mclbm_config), each launch
+ * from an even step runs two steps of every active cavity (tiles of 62
+ * columns by a band of rows per cavity), as the same cavity alone with two
+ * steps per launch; otherwise one step per launch. */
 typedef struct mclbm_batch mclbm_batch;
 
 /* Bytes of device memory for a batch of n cavities; 0 if any configuration

@@ -106,7 +106,8 @@ def test_batch_sizes_with_two_steps_per_launch():
     """A batch with two steps per launch adds, per cavity, a second
     population copy, and a second tile table with one 8-byte entry per
     (62-column strip, band) tile at the lowest band the autotuner tries
-    (3 rows), padded to the 8 XCDs.  Every cavity asks for it or none."""
+    (3 rows), padded to the 8 XCDs.  Every cavity asks for it, or none does
+    and the size rule picks it."""
     cfgs = [dict(nx=64, ny=64), dict(nx=100, ny=70), dict(nx=300, ny=40)]
     one = _batch_bytes(cfgs)
     two = _batch_bytes([dict(c, steps_per_launch=2) for c in cfgs])
@@ -119,8 +120,14 @@ def test_batch_sizes_with_two_steps_per_launch():
     assert _batch_bytes([dict(nx=16, ny=16, steps_per_launch=2), dict(nx=16, ny=16)]) == 0
     assert "every cavity two" in L.mclbm_last_error().decode()
     assert _batch_bytes([dict(nx=16, ny=16, steps_per_launch=2, thermal_lattices=2)]) == 0
-    # the automatic choice stays one step per launch in a batch
-    assert _batch_bytes([dict(nx=2048, ny=2048)]) == _batch_bytes([dict(nx=2048, ny=2048, steps_per_launch=1)])
+    # automatic (every cavity 0): two steps per launch for FP32 batches from
+    # 2^20 nodes whose cavities fill 60 % of their strips' lanes
+    for cavs, two in (([dict(nx=512, ny=512)] * 4, True), ([dict(nx=128, ny=128)] * 64, True),
+                      ([dict(nx=64, ny=64)] * 256, False), ([dict(nx=256, ny=256)] * 15, False),
+                      ([dict(nx=512, ny=512, storage=mc.FP16S)] * 4, False),
+                      ([dict(nx=512, ny=512)] * 3 + [dict(nx=512, ny=512, steps_per_launch=1)], False)):
+        want = _batch_bytes([dict(c, steps_per_launch=2 if two else 1) for c in cavs])
+        assert _batch_bytes(cavs) == want, (cavs[0], len(cavs), two)
 
 
 def test_create_rejects_small_or_misaligned_buffers_without_touching_them():

@@ -161,6 +161,24 @@ def test_two_step_autotune_picks_bands_without_changing_results():
         assert np.array_equal(b.members[k].populations(), _single(k, xis, [65]).populations()), k
 
 
+def test_automatic_schedule_of_a_large_batch():
+    """Four 512^2 cavities (2^20 nodes) left to the automatic choice run two
+    steps per launch: bitwise like the same cavities alone with two steps
+    per launch; asking one of them for one step keeps the batch at one."""
+    cfgs = [dict(nx=512, ny=512, Ra=10.0 ** (3 + k), phi0=0.01 * (k + 1), dp_nm=30.0 + 20 * k) for k in range(4)]
+    xis = _xis(cfgs, seed=41)
+    b = mc.Batch(cfgs, xis=xis)
+    assert b.tile_shape(0)[0] == 62
+    b.step(65)
+    for k in (0, 3):
+        s = mc.Cavity(xi=xis[k], steps_per_launch=2, **cfgs[k])
+        s.step(65)
+        assert np.array_equal(b.members[k].populations(), s.populations()), k
+    b.close()
+    one = mc.Batch(cfgs[:3] + [dict(cfgs[3], steps_per_launch=1)], xis=xis)
+    assert one.tile_shape(0)[0] != 62
+
+
 def test_mixed_schedules_rejected():
     with pytest.raises(mc.MclbmError, match="every cavity two"):
         mc.Batch([dict(nx=16, ny=16, steps_per_launch=2), dict(nx=16, ny=16)])
