@@ -179,6 +179,40 @@ def test_automatic_schedule_of_a_large_batch():
     assert one.tile_shape(0)[0] != 62
 
 
+def test_full_sweep_in_the_timed_configuration():
+    """The 256-cavity sweep (sides 64-512, 23.1 M nodes) as the bench times
+    it: automatic schedule (two steps per launch), autotuned bands, graph
+    replays.  One member of every size class bitwise against the same
+    cavity alone with two steps per launch, and the 64^2 and 128^2 members
+    against the oracle."""
+    sweep = inputs.sweep_parameters(3, 256)
+    cfgs = [dict({k: v for k, v in c.items() if k != "seed"}, tau_f=-1.0) for c in sweep]
+    xis = [inputs.phi_perturbation(c["seed"], c["nx"], c["ny"]) for c in sweep]
+    b = mc.Batch(cfgs, xis=xis)
+    shapes = b.autotune(steps=8)
+    assert all(bx == 62 for bx, _ in shapes)
+    b.step(96)
+    first = {}
+    for k, c in enumerate(cfgs):
+        first.setdefault(c["nx"], k)
+    assert sorted(first) == [64, 128, 256, 384, 512]
+    for side, k in sorted(first.items()):
+        s = mc.Cavity(xi=xis[k], steps_per_launch=2, **cfgs[k])
+        s.step(96)
+        assert np.array_equal(b.members[k].populations(), s.populations()), (side, k)
+        del s
+        if side <= 128:
+            o = oracle.Oracle(xi=xis[k], **cfgs[k])
+            o.step(96)
+            mg, mo = b.members[k].moments(), o.moments()
+            for f in mo:
+                scale = np.abs(mo[f]).max()
+                near_empty = cfgs[k]["phi0"] < 0.005 and f in ("ux_p", "uy_p")  # as in the oracle test above
+                if scale > 0 and not near_empty:
+                    assert np.abs(mg[f] - mo[f]).max() <= 1e-5 * scale, (side, f)
+    b.close()
+
+
 def test_mixed_schedules_rejected():
     with pytest.raises(mc.MclbmError, match="every cavity two"):
         mc.Batch([dict(nx=16, ny=16, steps_per_launch=2), dict(nx=16, ny=16)])
