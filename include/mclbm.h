@@ -349,11 +349,12 @@ int mclbm_batch_set_active(mclbm_batch* b, const int32_t* active);
 /* Residual (as mclbm_residual) of every active cavity: out[2k], out[2k+1];
  * status[k] = 0 still running, 1 converged (both below tol; dropped),
  * 2 diverged (non-finite; dropped), 3 inactive.  tol <= 0 only reports.
- * Sync. */
+ * Sync (once for the whole batch). */
 int mclbm_batch_residual(mclbm_batch* b, double tol, double* out, int32_t* status);
 
 /* Nusselt numbers (as mclbm_nusselt) of every cavity: out[3k .. 3k+2].
- * Non-finite values are reported as such.  Sync. */
+ * Non-finite values are reported as such.  Sync (once for the whole
+ * batch). */
 int mclbm_batch_nusselt(mclbm_batch* b, double* out);
 
 /* Project-written autotuner: for every size class of the batch (cavities of

@@ -1430,6 +1430,65 @@ int enqueue_load_fields(mclbm_cavity* c, const float* F, int sx, int sy, int nc,
   return MCLBM_OK;
 }
 
+// The FP64 reductions in two halves: enqueue the kernels and the copy of
+// their results to host memory `h` (pinned for an asynchronous copy), then,
+// after the stream has been synchronised, read them.  A batch enqueues all
+// its cavities before one synchronisation.
+int enqueue_nusselt(mclbm_cavity* c, double* h) {
+  const double rp = (double)c->P.rho_p_ref, R = c->D.v[MCLBM_D_R], Ck = c->D.v[MCLBM_D_CK];
+  int rc = dispatch(c, [&](auto k) {
+    using S = typename decltype(k)::S;
+    using I = typename decltype(k)::I;
+    const auto* pop = reinterpret_cast<const typename S::T*>(c->pop());
+    if (c->t & 1)
+      k_nusselt<true, S, I, decltype(k)::NL><<<1, 256, 0, c->stream>>>(c->P, pop, c->d5(), rp, R, Ck, c->res());
+    else
+      k_nusselt<false, S, I, decltype(k)::NL><<<1, 256, 0, c->stream>>>(c->P, pop, c->d5(), rp, R, Ck, c->res());
+    return launch_check("k_nusselt");
+  });
+  if (rc) return rc;
+  HIP_TRY(hipMemcpyAsync(h, c->res(), 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  return MCLBM_OK;
+}
+
+int finish_nusselt(const double* h, double* nu_hot, double* nu_cold, double* nu_hot_k) {
+  if (nu_hot) *nu_hot = h[0];
+  if (nu_cold) *nu_cold = h[1];
+  if (nu_hot_k) *nu_hot_k = h[2];
+  if (h[3] != 0.0) return fail(MCLBM_EDIVERGED, "non-finite temperature at a wall");
+  return MCLBM_OK;
+}
+
+int enqueue_residual(mclbm_cavity* c, double* h) {
+  const unsigned rb = (unsigned)c->L.red_blocks;
+  const double rf = (double)c->P.rho_f_ref, rp = (double)c->P.rho_p_ref;
+  int rc = dispatch(c, [&](auto k) {
+    using S = typename decltype(k)::S;
+    using I = typename decltype(k)::I;
+    const auto* pop = reinterpret_cast<const typename S::T*>(c->pop());
+    if (c->t & 1)
+      k_residual<true, S, I, decltype(k)::NL><<<rb, 256, 0, c->stream>>>(c->P, pop, c->d5(), rf, rp, c->snap(), c->part());
+    else
+      k_residual<false, S, I, decltype(k)::NL><<<rb, 256, 0, c->stream>>>(c->P, pop, c->d5(), rf, rp, c->snap(), c->part());
+    return launch_check("k_residual");
+  });
+  if (rc) return rc;
+  k_sum_partials<<<1, 256, 0, c->stream>>>(c->part(), (int)rb, c->res() + 4);
+  rc = launch_check("k_sum_partials");
+  if (rc) return rc;
+  HIP_TRY(hipMemcpyAsync(h, c->res() + 4, 5 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  return MCLBM_OK;
+}
+
+int finish_residual(const double* h, double* res_u, double* res_theta) {
+  const double ru = h[1] > 0.0 ? std::sqrt(h[0] / h[1]) : (h[0] > 0.0 ? INFINITY : 0.0);
+  const double rt = h[3] > 0.0 ? std::sqrt(h[2] / h[3]) : (h[2] > 0.0 ? INFINITY : 0.0);
+  if (res_u) *res_u = ru;
+  if (res_theta) *res_theta = rt;
+  if (h[4] != 0.0) return fail(MCLBM_EDIVERGED, "non-finite velocity or temperature");
+  return MCLBM_OK;
+}
+
 }  // namespace
 
 // ---- checkpoint / resume ----------------------------------------------------
@@ -1718,55 +1777,20 @@ int mclbm_read_populations(mclbm_cavity* c, double* host_out, size_t n_doubles) 
 
 int mclbm_nusselt(mclbm_cavity* c, double* nu_hot, double* nu_cold, double* nu_hot_k) {
   if (!c) return fail(MCLBM_EINVAL, "cavity is NULL");
-  const double rp = (double)c->P.rho_p_ref, R = c->D.v[MCLBM_D_R], Ck = c->D.v[MCLBM_D_CK];
-  int rc = dispatch(c, [&](auto k) {
-    using S = typename decltype(k)::S;
-    using I = typename decltype(k)::I;
-    const auto* pop = reinterpret_cast<const typename S::T*>(c->pop());
-    if (c->t & 1)
-      k_nusselt<true, S, I, decltype(k)::NL><<<1, 256, 0, c->stream>>>(c->P, pop, c->d5(), rp, R, Ck, c->res());
-    else
-      k_nusselt<false, S, I, decltype(k)::NL><<<1, 256, 0, c->stream>>>(c->P, pop, c->d5(), rp, R, Ck, c->res());
-    return launch_check("k_nusselt");
-  });
-  if (rc) return rc;
   double h[4];
-  HIP_TRY(hipMemcpyAsync(h, c->res(), sizeof(h), hipMemcpyDeviceToHost, c->stream));
+  int rc = enqueue_nusselt(c, h);
+  if (rc) return rc;
   HIP_TRY(hipStreamSynchronize(c->stream));
-  if (nu_hot) *nu_hot = h[0];
-  if (nu_cold) *nu_cold = h[1];
-  if (nu_hot_k) *nu_hot_k = h[2];
-  if (h[3] != 0.0) return fail(MCLBM_EDIVERGED, "non-finite temperature at a wall");
-  return MCLBM_OK;
+  return finish_nusselt(h, nu_hot, nu_cold, nu_hot_k);
 }
 
 int mclbm_residual(mclbm_cavity* c, double* res_u, double* res_theta) {
   if (!c) return fail(MCLBM_EINVAL, "cavity is NULL");
-  const unsigned rb = (unsigned)c->L.red_blocks;
-  const double rf = (double)c->P.rho_f_ref, rp = (double)c->P.rho_p_ref;
-  int rc = dispatch(c, [&](auto k) {
-    using S = typename decltype(k)::S;
-    using I = typename decltype(k)::I;
-    const auto* pop = reinterpret_cast<const typename S::T*>(c->pop());
-    if (c->t & 1)
-      k_residual<true, S, I, decltype(k)::NL><<<rb, 256, 0, c->stream>>>(c->P, pop, c->d5(), rf, rp, c->snap(), c->part());
-    else
-      k_residual<false, S, I, decltype(k)::NL><<<rb, 256, 0, c->stream>>>(c->P, pop, c->d5(), rf, rp, c->snap(), c->part());
-    return launch_check("k_residual");
-  });
-  if (rc) return rc;
-  k_sum_partials<<<1, 256, 0, c->stream>>>(c->part(), (int)rb, c->res() + 4);
-  rc = launch_check("k_sum_partials");
-  if (rc) return rc;
   double h[5];
-  HIP_TRY(hipMemcpyAsync(h, c->res() + 4, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+  int rc = enqueue_residual(c, h);
+  if (rc) return rc;
   HIP_TRY(hipStreamSynchronize(c->stream));
-  const double ru = h[1] > 0.0 ? std::sqrt(h[0] / h[1]) : (h[0] > 0.0 ? INFINITY : 0.0);
-  const double rt = h[3] > 0.0 ? std::sqrt(h[2] / h[3]) : (h[2] > 0.0 ? INFINITY : 0.0);
-  if (res_u) *res_u = ru;
-  if (res_theta) *res_theta = rt;
-  if (h[4] != 0.0) return fail(MCLBM_EDIVERGED, "non-finite velocity or temperature");
-  return MCLBM_OK;
+  return finish_residual(h, res_u, res_theta);
 }
 
 int mclbm_derived(const mclbm_cavity* c, double* out, int n) {
@@ -1911,6 +1935,7 @@ struct mclbm_batch {
   std::vector<int2> host_tiles, host_tiles2;
   int ntiles = 0, ntiles2 = 0;
   bool two = false;  // two steps per launch (k_step2_batch) from even steps
+  double* h_red = nullptr;  // pinned host results of the reductions, 16 doubles per cavity
   int flip = 0;      // two-step launches since the descriptors were written, mod 2
   int64_t t = 0;  // steps of the active cavities
   int storage = MCLBM_FP32S;
@@ -2281,14 +2306,22 @@ int mclbm_batch_create(const mclbm_config* cfgs, int32_t n, const double* const*
   (void)ncu;
   b->grid = (unsigned)B.tile_cap;
   b->grid2 = (unsigned)B.tile_cap2;
-  hipError_t e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+  hipError_t e = hipHostMalloc((void**)&b->h_red, (size_t)16 * n * sizeof(double), hipHostMallocDefault);
   if (e != hipSuccess) {
+    b->h_red = nullptr;
+    delete b;
+    return hip_fail(e, "hipHostMalloc");
+  }
+  e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    (void)hipHostFree(b->h_red);
     delete b;
     return hip_fail(e, "hipStreamCreateWithFlags");
   }
   rc = batch_reset_all(b);
   if (rc) {
     (void)hipStreamDestroy(b->cap_stream);
+    (void)hipHostFree(b->h_red);
     delete b;
     return rc;
   }
@@ -2352,22 +2385,23 @@ int mclbm_batch_set_active(mclbm_batch* b, const int32_t* active) {
 
 int mclbm_batch_residual(mclbm_batch* b, double tol, double* out, int32_t* status) {
   if (!b || !out) return fail(MCLBM_EINVAL, "NULL argument");
+  // every active cavity's reduction first, then one synchronisation
+  for (int k = 0; k < b->n; ++k)
+    if (b->active[k]) {
+      const int rc = enqueue_residual(&b->cav[k], b->h_red + 16 * k + 4);
+      if (rc) return rc;
+    }
+  HIP_TRY(hipStreamSynchronize(b->stream));
   bool changed = false;
   for (int k = 0; k < b->n; ++k) {
     int32_t st = 3;
     out[2 * k] = out[2 * k + 1] = NAN;
     if (b->active[k]) {
       double ru = 0.0, rt = 0.0;
-      const int rc = mclbm_residual(&b->cav[k], &ru, &rt);
+      const int rc = finish_residual(b->h_red + 16 * k + 4, &ru, &rt);
       out[2 * k] = ru;
       out[2 * k + 1] = rt;
-      if (rc == MCLBM_EDIVERGED) {
-        st = 2;
-      } else if (rc) {
-        return rc;
-      } else {
-        st = (tol > 0.0 && ru < tol && rt < tol) ? 1 : 0;
-      }
+      st = rc == MCLBM_EDIVERGED ? 2 : ((tol > 0.0 && ru < tol && rt < tol) ? 1 : 0);
       if (st != 0 && tol > 0.0) {
         b->active[k] = 0;
         changed = true;
@@ -2383,9 +2417,12 @@ int mclbm_batch_residual(mclbm_batch* b, double tol, double* out, int32_t* statu
 int mclbm_batch_nusselt(mclbm_batch* b, double* out) {
   if (!b || !out) return fail(MCLBM_EINVAL, "NULL argument");
   for (int k = 0; k < b->n; ++k) {
-    const int rc = mclbm_nusselt(&b->cav[k], &out[3 * k], &out[3 * k + 1], &out[3 * k + 2]);
-    if (rc && rc != MCLBM_EDIVERGED) return rc;
+    const int rc = enqueue_nusselt(&b->cav[k], b->h_red + 16 * k);
+    if (rc) return rc;
   }
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  for (int k = 0; k < b->n; ++k)
+    (void)finish_nusselt(b->h_red + 16 * k, &out[3 * k], &out[3 * k + 1], &out[3 * k + 2]);
   g_err.clear();
   return MCLBM_OK;
 }
@@ -2512,6 +2549,7 @@ int mclbm_batch_destroy(mclbm_batch* b) {
   hipError_t e = hipStreamSynchronize(b->stream);
   drop_graph(b);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  if (b->h_red) (void)hipHostFree(b->h_red);
   delete b;
   if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
   return MCLBM_OK;
