@@ -478,13 +478,11 @@ __device__ __forceinline__ double3 node_thetas(const float g[9], const float g2[
   }
 }
 
+// Wall-Nusselt numbers of one cavity by one workgroup (FP64).
 template <bool ODD, class S, class I, int NL>
-__global__ __launch_bounds__(256) void k_nusselt(StepParams P,
-                                                 const typename S::T* __restrict__ pop,
-                                                 const float* __restrict__ d5,
-                                                 double rho_p_ref, double R,
-                                                 double Ck,
-                                                 double* __restrict__ out) {
+__device__ __forceinline__ void nusselt_body(const StepParams& P, const typename S::T* __restrict__ pop,
+                                             const float* __restrict__ d5, double rho_p_ref, double R,
+                                             double Ck, double* __restrict__ out) {
   __shared__ double lds[4];
   const int nx = P.nx, ny = P.ny;
   double sh = 0.0, sc = 0.0, sk = 0.0, bad = 0.0;
@@ -522,18 +520,26 @@ __global__ __launch_bounds__(256) void k_nusselt(StepParams P,
   }
 }
 
+template <bool ODD, class S, class I, int NL>
+__global__ __launch_bounds__(256) void k_nusselt(StepParams P,
+                                                 const typename S::T* __restrict__ pop,
+                                                 const float* __restrict__ d5,
+                                                 double rho_p_ref, double R,
+                                                 double Ck,
+                                                 double* __restrict__ out) {
+  nusselt_body<ODD, S, I, NL>(P, pop, d5, rho_p_ref, R, Ck, out);
+}
+
 // Per-block partial sums of |u - u_ref|^2, |u|^2, (theta - theta_ref)^2,
 // theta^2 and a non-finite count; the snapshot is replaced by the state.
 template <bool ODD, class S, class I, int NL>
-__global__ __launch_bounds__(256) void k_residual(StepParams P,
-                                                  const typename S::T* __restrict__ pop,
-                                                  const float* __restrict__ d5,
-                                                  double rho_f_ref, double rho_p_ref,
-                                                  double* __restrict__ snap,
-                                                  double* __restrict__ partial) {
+__device__ __forceinline__ void residual_block(const StepParams& P, const typename S::T* __restrict__ pop,
+                                               const float* __restrict__ d5, double rho_f_ref,
+                                               double rho_p_ref, double* __restrict__ snap,
+                                               double* __restrict__ partial, int block) {
   __shared__ double lds[4];
   const long long nn = (long long)P.nx * P.ny;
-  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long k = (long long)block * blockDim.x + threadIdx.x;
   double du = 0.0, un = 0.0, dt = 0.0, tn = 0.0, bad = 0.0;
   if (k < nn) {
     const int x = (int)(k % P.nx), y = (int)(k / P.nx);
@@ -564,15 +570,24 @@ __global__ __launch_bounds__(256) void k_residual(StepParams P,
   tn = block_sum(tn, lds);
   bad = block_sum(bad, lds);
   if (threadIdx.x == 0) {
-    double* o = partial + 5 * (long long)blockIdx.x;
+    double* o = partial + 5 * (long long)block;
     o[0] = du; o[1] = un; o[2] = dt; o[3] = tn; o[4] = bad;
   }
 }
 
+template <bool ODD, class S, class I, int NL>
+__global__ __launch_bounds__(256) void k_residual(StepParams P,
+                                                  const typename S::T* __restrict__ pop,
+                                                  const float* __restrict__ d5,
+                                                  double rho_f_ref, double rho_p_ref,
+                                                  double* __restrict__ snap,
+                                                  double* __restrict__ partial) {
+  residual_block<ODD, S, I, NL>(P, pop, d5, rho_f_ref, rho_p_ref, snap, partial, (int)blockIdx.x);
+}
+
 // Fixed-order sum of the per-block partials (deterministic).
-__global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__ partial,
-                                                      int nblocks,
-                                                      double* __restrict__ out) {
+__device__ __forceinline__ void sum_partials_body(const double* __restrict__ partial, int nblocks,
+                                                  double* __restrict__ out) {
   __shared__ double lds[4];
   for (int q = 0; q < 5; ++q) {
     double s = 0.0;
@@ -580,6 +595,52 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__
     s = block_sum(s, lds);
     if (threadIdx.x == 0) out[q] = s;
   }
+}
+
+__global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__ partial,
+                                                      int nblocks,
+                                                      double* __restrict__ out) {
+  sum_partials_body(partial, nblocks, out);
+}
+
+// The reductions of every active cavity of a batch (all at one step
+// parity, current copy C.pop[flip]) in three launches: the Nusselt numbers
+// and the summed partials one workgroup per cavity, the residual's partials
+// one workgroup per (cavity, block) entry.  Results go to out[16 j ..]
+// for the j-th cavity of the list: Nu at 0-3, the residual sums at 4-8.
+struct RedDesc {
+  double* snap;
+  double* part;
+  double rho_f_ref, rho_p_ref, R, Ck;
+  int red_blocks, pad;
+};
+
+template <bool ODD, class S, class I>
+__global__ __launch_bounds__(256) void k_nusselt_batch(const CavDesc* __restrict__ cavs,
+                                                       const RedDesc* __restrict__ red,
+                                                       const int* __restrict__ list, int flip,
+                                                       double* __restrict__ out) {
+  const int m = list[blockIdx.x];
+  const CavDesc& C = cavs[m];
+  nusselt_body<ODD, S, I, 3>(C.P, reinterpret_cast<const typename S::T*>(C.pop[flip]), C.d5,
+                             red[m].rho_p_ref, red[m].R, red[m].Ck, out + 16 * (long long)blockIdx.x);
+}
+
+template <bool ODD, class S, class I>
+__global__ __launch_bounds__(256) void k_residual_batch(const CavDesc* __restrict__ cavs,
+                                                        const RedDesc* __restrict__ red,
+                                                        const int2* __restrict__ tiles, int flip) {
+  const int2 e = tiles[blockIdx.x];
+  const CavDesc& C = cavs[e.x];
+  residual_block<ODD, S, I, 3>(C.P, reinterpret_cast<const typename S::T*>(C.pop[flip]), C.d5,
+                               red[e.x].rho_f_ref, red[e.x].rho_p_ref, red[e.x].snap, red[e.x].part, e.y);
+}
+
+__global__ __launch_bounds__(256) void k_sum_partials_batch(const RedDesc* __restrict__ red,
+                                                            const int* __restrict__ list,
+                                                            double* __restrict__ out) {
+  const int m = list[blockIdx.x];
+  sum_partials_body(red[m].part, red[m].red_blocks, out + 16 * (long long)blockIdx.x + 4);
 }
 
 // Warm start: bilinear samples of channel-last fields (sy x sx x nc) at
@@ -1929,13 +1990,20 @@ struct mclbm_batch {
   char* base = nullptr;
   size_t bytes = 0;
   size_t off_desc = 0, off_ntiles = 0, off_tiles = 0, off_ntiles2 = 0, off_tiles2 = 0;
-  int tile_cap = 0, tile_cap2 = 0;
+  size_t off_red = 0, off_rlist = 0, off_rtiles = 0, off_rout = 0;
+  int tile_cap = 0, tile_cap2 = 0, rtile_cap = 0;
+  int nr = 0, nrt = 0;  // active cavities, (cavity, block) entries of the residual
+  std::vector<int> host_rlist;
+  std::vector<int2> host_rtiles;
+  std::vector<RedDesc> host_red;
   std::vector<char> active;
   std::vector<CavDesc> host_desc;
   std::vector<int2> host_tiles, host_tiles2;
   int ntiles = 0, ntiles2 = 0;
   bool two = false;  // two steps per launch (k_step2_batch) from even steps
-  double* h_red = nullptr;  // pinned host results of the reductions, 16 doubles per cavity
+  // pinned host results of the reductions: 16 doubles per listed active
+  // cavity, then 16 per cavity for the inactive ones' Nusselt numbers
+  double* h_red = nullptr;
   int flip = 0;      // two-step launches since the descriptors were written, mod 2
   int64_t t = 0;  // steps of the active cavities
   int storage = MCLBM_FP32S;
@@ -1950,6 +2018,11 @@ struct mclbm_batch {
   int2* d_tiles() { return reinterpret_cast<int2*>(base + off_tiles); }
   int* d_ntiles2() { return reinterpret_cast<int*>(base + off_ntiles2); }
   int2* d_tiles2() { return reinterpret_cast<int2*>(base + off_tiles2); }
+  RedDesc* d_red() { return reinterpret_cast<RedDesc*>(base + off_red); }
+  int* d_rlist() { return reinterpret_cast<int*>(base + off_rlist); }
+  int2* d_rtiles() { return reinterpret_cast<int2*>(base + off_rtiles); }
+  double* d_rout() { return reinterpret_cast<double*>(base + off_rout); }
+  double* h_inactive(int k) { return h_red + 16 * (size_t)n + 16 * (size_t)k; }
 };
 
 namespace {
@@ -1960,7 +2033,8 @@ int tiles_of(int nx, int ny, int bx, int by) { return ((nx + bx - 1) / bx) * ((n
 
 struct BatchLayout {
   size_t off_desc, off_ntiles, off_tiles, off_ntiles2, off_tiles2, total;
-  int tile_cap, tile_cap2;
+  size_t off_red, off_rlist, off_rtiles, off_rout;
+  int tile_cap, tile_cap2, rtile_cap;
   bool two;
   std::vector<size_t> off_cav;
 };
@@ -1984,7 +2058,7 @@ int tiles2_of(const mclbm_config& c) {
 
 int batch_layout(const mclbm_config* cfgs, int n, BatchLayout& B) {
   if (!cfgs || n < 1) return fail(MCLBM_EINVAL, "batch needs n >= 1 configurations");
-  long long cap = 0, cap2 = 0, nodes = 0;
+  long long cap = 0, cap2 = 0, nodes = 0, rcap = 0;
   int n1 = 0, n2 = 0;    // cavities asking for one or for two steps per launch
   bool possible = true;  // every cavity can take two steps per launch
   double used = 0.0;     // nodes weighted by the share of strip lanes they fill
@@ -2003,11 +2077,13 @@ int batch_layout(const mclbm_config* cfgs, int n, BatchLayout& B) {
     int m = 0;
     for (const auto& sh : kShapes) m = std::max(m, tiles_of(cfgs[k].nx, cfgs[k].ny, sh[0], sh[1]));
     cap += m;
+    rcap += (nn + 255) / 256;
   }
   if (n2 != 0 && n2 != n)
     return fail(MCLBM_EUNSUPPORTED,
                 "a batch runs every cavity one step per launch, or every cavity two (steps_per_launch 2 for all)");
-  if (cap > (1LL << 30)) return fail(MCLBM_EINVAL, "batch too large");
+  if (cap > (1LL << 30) || rcap > (1LL << 30)) return fail(MCLBM_EINVAL, "batch too large");
+  B.rtile_cap = (int)rcap;
   // Automatic (every cavity 0): two steps per launch for FP32 batches from
   // 2^20 nodes whose cavities fill at least 60 % of their strips' lanes
   // (measured: 1.06-1.51x from 1 M to 17 M nodes of 128- to 512-column
@@ -2030,6 +2106,14 @@ int batch_layout(const mclbm_config* cfgs, int n, BatchLayout& B) {
   off = align_up(off + sizeof(int));
   B.off_tiles2 = off;
   off = align_up(off + (size_t)B.tile_cap2 * sizeof(int2));
+  B.off_red = off;
+  off = align_up(off + (size_t)n * sizeof(RedDesc));
+  B.off_rlist = off;
+  off = align_up(off + (size_t)n * sizeof(int));
+  B.off_rtiles = off;
+  off = align_up(off + (size_t)B.rtile_cap * sizeof(int2));
+  B.off_rout = off;
+  off = align_up(off + (size_t)16 * n * sizeof(double));
   B.off_cav.resize(n);
   for (int k = 0; k < n; ++k) {
     B.off_cav[k] = off;
@@ -2095,6 +2179,36 @@ int upload_tables(mclbm_batch* b) {
   if (b->ntiles2 > b->tile_cap2) return fail(MCLBM_EINVAL, "two-step tile table overflow");
   b->host_desc.resize(b->n);
   for (int k = 0; k < b->n; ++k) b->host_desc[k] = make_desc(&b->cav[k]);
+  // reductions: the active cavities, and their (cavity, block) entries
+  b->host_red.resize(b->n);
+  b->host_rlist.clear();
+  b->host_rtiles.clear();
+  for (int k = 0; k < b->n; ++k) {
+    mclbm_cavity* c = &b->cav[k];
+    RedDesc& r = b->host_red[k];
+    r.snap = c->snap();
+    r.part = c->part();
+    r.rho_f_ref = (double)c->P.rho_f_ref;
+    r.rho_p_ref = (double)c->P.rho_p_ref;
+    r.R = c->D.v[MCLBM_D_R];
+    r.Ck = c->D.v[MCLBM_D_CK];
+    r.red_blocks = c->L.red_blocks;
+    r.pad = 0;
+    if (!b->active[k]) continue;
+    b->host_rlist.push_back(k);
+    for (int q = 0; q < c->L.red_blocks; ++q) b->host_rtiles.push_back(make_int2(k, q));
+  }
+  b->nr = (int)b->host_rlist.size();
+  b->nrt = (int)b->host_rtiles.size();
+  if (b->nrt > b->rtile_cap) return fail(MCLBM_EINVAL, "reduction table overflow");
+  HIP_TRY(hipMemcpyAsync(b->d_red(), b->host_red.data(), b->host_red.size() * sizeof(RedDesc),
+                         hipMemcpyHostToDevice, b->stream));
+  if (b->nr > 0) {
+    HIP_TRY(hipMemcpyAsync(b->d_rlist(), b->host_rlist.data(), (size_t)b->nr * sizeof(int),
+                           hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(hipMemcpyAsync(b->d_rtiles(), b->host_rtiles.data(), (size_t)b->nrt * sizeof(int2),
+                           hipMemcpyHostToDevice, b->stream));
+  }
   HIP_TRY(hipMemcpyAsync(b->d_desc(), b->host_desc.data(), b->host_desc.size() * sizeof(CavDesc),
                          hipMemcpyHostToDevice, b->stream));
   if (b->ntiles > 0)
@@ -2261,6 +2375,11 @@ int mclbm_batch_create(const mclbm_config* cfgs, int32_t n, const double* const*
   b->off_ntiles2 = B.off_ntiles2;
   b->off_tiles2 = B.off_tiles2;
   b->tile_cap2 = B.tile_cap2;
+  b->off_red = B.off_red;
+  b->off_rlist = B.off_rlist;
+  b->off_rtiles = B.off_rtiles;
+  b->off_rout = B.off_rout;
+  b->rtile_cap = B.rtile_cap;
   b->two = B.two;
   b->storage = cfgs[0].storage;
   b->cav.resize(n);
@@ -2306,7 +2425,7 @@ int mclbm_batch_create(const mclbm_config* cfgs, int32_t n, const double* const*
   (void)ncu;
   b->grid = (unsigned)B.tile_cap;
   b->grid2 = (unsigned)B.tile_cap2;
-  hipError_t e = hipHostMalloc((void**)&b->h_red, (size_t)16 * n * sizeof(double), hipHostMallocDefault);
+  hipError_t e = hipHostMalloc((void**)&b->h_red, (size_t)32 * n * sizeof(double), hipHostMallocDefault);
   if (e != hipSuccess) {
     b->h_red = nullptr;
     delete b;
@@ -2385,27 +2504,41 @@ int mclbm_batch_set_active(mclbm_batch* b, const int32_t* active) {
 
 int mclbm_batch_residual(mclbm_batch* b, double tol, double* out, int32_t* status) {
   if (!b || !out) return fail(MCLBM_EINVAL, "NULL argument");
-  // every active cavity's reduction first, then one synchronisation
-  for (int k = 0; k < b->n; ++k)
-    if (b->active[k]) {
-      const int rc = enqueue_residual(&b->cav[k], b->h_red + 16 * k + 4);
-      if (rc) return rc;
-    }
+  // every active cavity in three launches and one copy, then one synchronisation
+  if (b->nr > 0) {
+    const bool odd = (b->t & 1) != 0;
+    int rc = dispatch_kinds(b->storage, b->idx32, b->nt, [&](auto k) {
+      using S = typename decltype(k)::S;
+      using I = typename decltype(k)::I;
+      if (odd)
+        k_residual_batch<true, S, I><<<b->nrt, 256, 0, b->stream>>>(b->d_desc(), b->d_red(), b->d_rtiles(), b->flip);
+      else
+        k_residual_batch<false, S, I><<<b->nrt, 256, 0, b->stream>>>(b->d_desc(), b->d_red(), b->d_rtiles(), b->flip);
+      int r = launch_check("k_residual_batch");
+      if (r) return r;
+      k_sum_partials_batch<<<b->nr, 256, 0, b->stream>>>(b->d_red(), b->d_rlist(), b->d_rout());
+      return launch_check("k_sum_partials_batch");
+    });
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(b->h_red, b->d_rout(), (size_t)16 * b->nr * sizeof(double), hipMemcpyDeviceToHost,
+                           b->stream));
+  }
   HIP_TRY(hipStreamSynchronize(b->stream));
-  bool changed = false;
   for (int k = 0; k < b->n; ++k) {
-    int32_t st = 3;
     out[2 * k] = out[2 * k + 1] = NAN;
-    if (b->active[k]) {
-      double ru = 0.0, rt = 0.0;
-      const int rc = finish_residual(b->h_red + 16 * k + 4, &ru, &rt);
-      out[2 * k] = ru;
-      out[2 * k + 1] = rt;
-      st = rc == MCLBM_EDIVERGED ? 2 : ((tol > 0.0 && ru < tol && rt < tol) ? 1 : 0);
-      if (st != 0 && tol > 0.0) {
-        b->active[k] = 0;
-        changed = true;
-      }
+    if (status) status[k] = 3;
+  }
+  bool changed = false;
+  for (int j = 0; j < b->nr; ++j) {
+    const int k = b->host_rlist[j];
+    double ru = 0.0, rt = 0.0;
+    const int rc = finish_residual(b->h_red + 16 * j + 4, &ru, &rt);
+    out[2 * k] = ru;
+    out[2 * k + 1] = rt;
+    const int32_t st = rc == MCLBM_EDIVERGED ? 2 : ((tol > 0.0 && ru < tol && rt < tol) ? 1 : 0);
+    if (st != 0 && tol > 0.0) {
+      b->active[k] = 0;
+      changed = true;
     }
     if (status) status[k] = st;
   }
@@ -2416,13 +2549,37 @@ int mclbm_batch_residual(mclbm_batch* b, double tol, double* out, int32_t* statu
 
 int mclbm_batch_nusselt(mclbm_batch* b, double* out) {
   if (!b || !out) return fail(MCLBM_EINVAL, "NULL argument");
-  for (int k = 0; k < b->n; ++k) {
-    const int rc = enqueue_nusselt(&b->cav[k], b->h_red + 16 * k);
+  // the active cavities in one launch and one copy; the inactive ones
+  // (frozen, each at its own step parity) one by one; one synchronisation
+  if (b->nr > 0) {
+    const bool odd = (b->t & 1) != 0;
+    int rc = dispatch_kinds(b->storage, b->idx32, b->nt, [&](auto k) {
+      using S = typename decltype(k)::S;
+      using I = typename decltype(k)::I;
+      if (odd)
+        k_nusselt_batch<true, S, I><<<b->nr, 256, 0, b->stream>>>(b->d_desc(), b->d_red(), b->d_rlist(), b->flip,
+                                                                  b->d_rout());
+      else
+        k_nusselt_batch<false, S, I><<<b->nr, 256, 0, b->stream>>>(b->d_desc(), b->d_red(), b->d_rlist(), b->flip,
+                                                                   b->d_rout());
+      return launch_check("k_nusselt_batch");
+    });
     if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(b->h_red, b->d_rout(), (size_t)16 * b->nr * sizeof(double), hipMemcpyDeviceToHost,
+                           b->stream));
   }
-  HIP_TRY(hipStreamSynchronize(b->stream));
   for (int k = 0; k < b->n; ++k)
-    (void)finish_nusselt(b->h_red + 16 * k, &out[3 * k], &out[3 * k + 1], &out[3 * k + 2]);
+    if (!b->active[k]) {
+      const int rc = enqueue_nusselt(&b->cav[k], b->h_inactive(k));
+      if (rc) return rc;
+    }
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  for (int j = 0; j < b->nr; ++j) {
+    const int k = b->host_rlist[j];
+    (void)finish_nusselt(b->h_red + 16 * j, &out[3 * k], &out[3 * k + 1], &out[3 * k + 2]);
+  }
+  for (int k = 0; k < b->n; ++k)
+    if (!b->active[k]) (void)finish_nusselt(b->h_inactive(k), &out[3 * k], &out[3 * k + 1], &out[3 * k + 2]);
   g_err.clear();
   return MCLBM_OK;
 }

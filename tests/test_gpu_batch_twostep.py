@@ -213,6 +213,36 @@ def test_full_sweep_in_the_timed_configuration():
     b.close()
 
 
+@pytest.mark.parametrize("two", [False, True])
+def test_batch_reductions_equal_per_cavity_calls(two):
+    """The batch's residual and Nusselt calls (three launches for all active
+    cavities) give bitwise the per-cavity calls' values: two identical
+    batches, one asked through the batch, one cavity by cavity; after an odd
+    number of two-step launches and with one cavity dropped."""
+    cfgs = TWO if two else [dict(c, steps_per_launch=1) for c in CFGS]
+    xis = _xis(CFGS)
+    a, b = mc.Batch(cfgs, xis=xis), mc.Batch(cfgs, xis=xis)
+    for x in (a, b):
+        x.residual(tol=0.0)
+        x.step(202)
+        x.set_active([1, 1, 0, 1, 1])
+        x.step(34)
+    res, st = a.residual(tol=0.0)
+    nu = a.nusselt()
+    assert list(st) == [0, 0, 3, 0, 0]
+    for k in range(len(cfgs)):
+        m = b.members[k]
+        if k != 2:
+            assert tuple(res[k]) == m.residual(), k
+        assert tuple(nu[k]) == m.nusselt(), k
+    # and again one chunk later (the snapshots moved on equally)
+    a.step(10)
+    b.step(10)
+    res, _ = a.residual(tol=0.0)
+    for k in (0, 1, 3, 4):
+        assert tuple(res[k]) == b.members[k].residual(), k
+
+
 def test_mixed_schedules_rejected():
     with pytest.raises(mc.MclbmError, match="every cavity two"):
         mc.Batch([dict(nx=16, ny=16, steps_per_launch=2), dict(nx=16, ny=16)])
