@@ -14,6 +14,7 @@
 //   k_step2_batch two steps per launch over such a batch (tiles of k_step2)
 //   k_nusselt   FP64 wall-Nusselt reduction
 //   k_residual  FP64 relative change of u_ns and theta (steady-state test)
+//   k_*_batch   the same reductions for every active cavity of a batch
 //   k_export    FP64 moments / populations of the current state
 //   k_copy      plain streaming copy, bandwidth and counter calibration
 #include <hip/hip_runtime.h>
