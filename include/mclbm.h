@@ -312,8 +312,9 @@ const char* mclbm_last_error(void);
 /* ---- Batched parameter sweeps ------------------------------------------
  * A batch holds n independent cavities of uneven sizes and parameters (the
  * sweeps over Ra, phi and d_p of Section 3) in one device buffer.  One
- * persistent kernel launch per time step updates every active cavity; the
- * step loop is replayed from a captured HIP graph.  Every cavity gives
+ * kernel launch per time step updates every active cavity (one workgroup
+ * per tile of every cavity); the step loop is replayed from a captured HIP
+ * graph.  Every cavity gives
  * bitwise the same result as the same cavity created alone.  All cavities of
  * a batch share the storage type; each keeps its own workgroup shape.
  * With two steps per launch (steps_per_launch in mclbm_config), each launch
