@@ -957,7 +957,7 @@ bool two_step_possible(const mclbm_config& c) {
 bool two_step(const mclbm_config& c, bool batch_member) {
   if (!two_step_possible(c)) return false;
   if (c.steps_per_launch != 0) return c.steps_per_launch == 2;
-  if (batch_member) return false;  // batches: on request only
+  if (batch_member) return false;  // a batch writes its own choice (member_config)
   return c.storage == MCLBM_FP32S && (long long)c.nx * c.ny >= (1LL << 20) && c.nx >= 256;
 }
 
