@@ -303,6 +303,19 @@ int mclbm_derived(const mclbm_cavity* c, double* out, int n);
 int mclbm_checkpoint(mclbm_cavity* c, const char* path);
 int mclbm_restore(mclbm_cavity* c, const char* path);
 
+/* Inspect a checkpoint file without a cavity (host only, no device work):
+ * the configuration it was written from (launch shape fields zeroed), its
+ * step count and, if the cavity had one, its initial perturbation field, so
+ * that a caller can create the matching cavity before mclbm_restore.  Any
+ * output pointer may be NULL.  *n_xi receives nx*ny, or 0 if the cavity was
+ * created without a field; xi_out (capacity xi_cap doubles) receives the
+ * field when it is non-NULL (MCLBM_EINVAL if xi_cap < nx*ny).  A file that
+ * is not a checkpoint of this format, or whose header is damaged (hex
+ * fields of the wrong length or alphabet, an invalid configuration, no step
+ * count), gives MCLBM_EINVAL and leaves the outputs unchanged. */
+int mclbm_checkpoint_info(const char* path, mclbm_config* cfg_out, int64_t* t_out,
+                          double* xi_out, size_t xi_cap, size_t* n_xi);
+
 /* Release the handle.  Does not free dev_buf.  Waits for the stream. */
 int mclbm_destroy(mclbm_cavity* c);
 

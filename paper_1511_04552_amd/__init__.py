@@ -33,7 +33,7 @@ EXPORTED = ("mclbm_config_defaults", "mclbm_device_bytes", "mclbm_derive_constan
             "mclbm_set_properties", "mclbm_reset", "mclbm_load_fields", "mclbm_step", "mclbm_time",
             "mclbm_export_moments", "mclbm_read_moments", "mclbm_read_populations",
             "mclbm_export_populations", "mclbm_nusselt", "mclbm_residual",
-            "mclbm_derived", "mclbm_checkpoint", "mclbm_restore", "mclbm_destroy", "mclbm_last_error",
+            "mclbm_derived", "mclbm_checkpoint", "mclbm_restore", "mclbm_checkpoint_info", "mclbm_destroy", "mclbm_last_error",
             "mclbm_copy_kernel",
             "mclbm_version", "mclbm_abi_version",
             "mclbm_batch_device_bytes", "mclbm_batch_create", "mclbm_batch_step",
@@ -99,6 +99,8 @@ def lib(load_torch: bool = True):
     L.mclbm_reset.argtypes = [P]
     L.mclbm_checkpoint.argtypes = [P, ctypes.c_char_p]
     L.mclbm_restore.argtypes = [P, ctypes.c_char_p]
+    L.mclbm_checkpoint_info.argtypes = [ctypes.c_char_p, CP, ctypes.POINTER(ctypes.c_int64), D,
+                                        ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
     L.mclbm_load_fields.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, D]
     L.mclbm_step.argtypes = [P, ctypes.c_int64]
     L.mclbm_time.argtypes = [P]
@@ -194,6 +196,27 @@ def derive_constants(**kw) -> dict:
     _check(lib().mclbm_derive_constants(ctypes.byref(make_config(**kw)),
                                         out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), out.size))
     return dict(zip(DERIVED, out.tolist()))
+
+
+def checkpoint_info(path) -> tuple:
+    """(configuration fields, step count, initial perturbation field or None)
+    of a checkpoint file, read on the host (mclbm_checkpoint_info)."""
+    L = lib()
+    cfg = Config()
+    t = ctypes.c_int64()
+    n = ctypes.c_size_t()
+    _check(L.mclbm_checkpoint_info(str(path).encode(), ctypes.byref(cfg), ctypes.byref(t), None, 0,
+                                   ctypes.byref(n)))
+    xi = None
+    if n.value:
+        xi = np.zeros(n.value)
+        _check(L.mclbm_checkpoint_info(str(path).encode(), None, None,
+                                       xi.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), xi.size, None))
+        xi = xi.reshape(cfg.ny, cfg.nx)
+    fields = {name: getattr(cfg, name) for name, _ in Config._fields_
+              if name not in ("force_scale", "fluid", "particle")}
+    fields["force_scale"] = list(cfg.force_scale)
+    return fields, int(t.value), xi
 
 
 def _dptr(a: np.ndarray):
@@ -359,8 +382,9 @@ class _BatchMember(Cavity):
 
 
 class Batch:
-    """Uneven cavities stepped together by one persistent launch per step
-    (graph-replayed).  ``cfgs``: list of keyword dicts as for ``Cavity``;
+    """Uneven cavities stepped together: one launch per step (or per pair of
+    steps) updates every active cavity, one workgroup per tile of every
+    cavity, replayed from a captured graph.  ``cfgs``: list of keyword dicts as for ``Cavity``;
     ``xis``: optional list of perturbation fields (or None entries)."""
 
     def __init__(self, cfgs, xis=None, stream=None, device=None, graph_steps=None):

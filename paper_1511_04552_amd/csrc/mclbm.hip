@@ -1612,6 +1612,59 @@ bool json_number_field(const std::string& h, const char* key, long long& v) {
   return end != h.c_str() + a + k.size();
 }
 
+// Decode a lowercase hex string into exactly n bytes (false on any other
+// length or character).
+bool unhex(const std::string& s, void* out, size_t n) {
+  if (s.size() != 2 * n) return false;
+  unsigned char* b = static_cast<unsigned char*>(out);
+  for (size_t k = 0; k < n; ++k) {
+    int v = 0;
+    for (int q = 0; q < 2; ++q) {
+      const char ch = s[2 * k + q];
+      const int d = (ch >= '0' && ch <= '9') ? ch - '0' : ((ch >= 'a' && ch <= 'f') ? ch - 'a' + 10 : -1);
+      if (d < 0) return false;
+      v = 16 * v + d;
+    }
+    b[k] = (unsigned char)v;
+  }
+  return true;
+}
+
+// The header line of a checkpoint file and what it names: the physics
+// configuration (launch shape zeroed), the initial perturbation field (empty
+// if the cavity had none) and the step count.  Leaves fp after the header.
+struct CkptHeader {
+  std::string line;
+  mclbm_config cfg;
+  std::vector<double> xi;
+  long long t = -1;
+};
+
+int read_ckpt_header(FILE* fp, CkptHeader& H) {
+  H.line.clear();
+  for (int ch; (ch = std::fgetc(fp)) != EOF && ch != '\n';) {
+    H.line.push_back((char)ch);
+    if (H.line.size() > (64u << 20)) return fail(MCLBM_EINVAL, "checkpoint: header line too long");
+  }
+  long long ver = 0;
+  if (json_string_field(H.line, "format") != "mclbm-checkpoint" || !json_number_field(H.line, "version", ver) ||
+      ver != kCkptVersion)
+    return fail(MCLBM_EINVAL, "checkpoint: not a checkpoint of this format");
+  if (!unhex(json_string_field(H.line, "config_hex"), &H.cfg, sizeof H.cfg))
+    return fail(MCLBM_EINVAL, "checkpoint: damaged configuration");
+  if (validate(&H.cfg) != MCLBM_OK) return fail(MCLBM_EINVAL, "checkpoint: invalid configuration");
+  const std::string xh = json_string_field(H.line, "xi_hex");
+  const size_t nn = (size_t)H.cfg.nx * (size_t)H.cfg.ny;
+  H.xi.clear();
+  if (!xh.empty()) {
+    H.xi.resize(nn);
+    if (!unhex(xh, H.xi.data(), nn * sizeof(double)))
+      return fail(MCLBM_EINVAL, "checkpoint: damaged initial perturbation field");
+  }
+  if (!json_number_field(H.line, "t", H.t) || H.t < 0) return fail(MCLBM_EINVAL, "checkpoint: no step count");
+  return MCLBM_OK;
+}
+
 // MCLBM_LOG=debug: one line per configuration on stderr with the lattice
 // constants and the stability numbers at the initial state (phi = phi0,
 // theta = 0, at rest): tau_p and tau_theta (Eqs 23-24), g beta dT (Eq 16),
@@ -1913,25 +1966,19 @@ int mclbm_restore(mclbm_cavity* c, const char* path) {
   if (c->in_batch) return fail(MCLBM_ESTATE, "restore: cavity belongs to a batch");
   FILE* fp = std::fopen(path, "rb");
   if (!fp) return fail(MCLBM_EINVAL, std::string("restore: cannot open ") + path);
-  std::string h;
-  for (int ch; (ch = std::fgetc(fp)) != EOF && ch != '\n';) {
-    h.push_back((char)ch);
-    if (h.size() > (64u << 20)) break;
-  }
-  long long ver = 0, t = 0;
+  CkptHeader H;
   const auto secs = ckpt_sections(c);
   auto bad = [&](const std::string& why) {
     std::fclose(fp);
     return fail(MCLBM_EINVAL, "restore: " + why);
   };
-  if (json_string_field(h, "format") != "mclbm-checkpoint" || !json_number_field(h, "version", ver) ||
-      ver != kCkptVersion)
-    return bad("not a checkpoint of this format");
-  if (json_string_field(h, "config_hex") != config_key(c->cfg))
-    return bad("the configuration differs from the cavity's");
-  if (json_string_field(h, "xi_hex") != hex_of(c->xi.data(), c->xi.size() * sizeof(double)))
+  if (read_ckpt_header(fp, H) != MCLBM_OK) return bad(mclbm_last_error());
+  if (config_key(H.cfg) != config_key(c->cfg)) return bad("the configuration differs from the cavity's");
+  if (H.xi.size() != c->xi.size() ||
+      (!H.xi.empty() && std::memcmp(H.xi.data(), c->xi.data(), H.xi.size() * sizeof(double)) != 0))
     return bad("the initial perturbation field differs from the cavity's");
-  if (!json_number_field(h, "t", t) || t < 0) return bad("no step count");
+  const long long t = H.t;
+  const std::string& h = H.line;
   for (const auto& sc : secs) {
     const std::string key = std::string("{\"name\": \"") + sc.name + "\", \"bytes\": " + std::to_string(sc.bytes) + "}";
     if (h.find(key) == std::string::npos) return bad(std::string("section size mismatch: ") + sc.name);
@@ -1949,6 +1996,25 @@ int mclbm_restore(mclbm_cavity* c, const char* path) {
   for (size_t k = 0; k < secs.size(); ++k)
     if (secs[k].bytes) HIP_TRY(hipMemcpy(c->base + secs[k].off, data[k].data(), secs[k].bytes, hipMemcpyHostToDevice));
   c->t = t;
+  return MCLBM_OK;
+}
+
+int mclbm_checkpoint_info(const char* path, mclbm_config* cfg_out, int64_t* t_out, double* xi_out,
+                          size_t xi_cap, size_t* n_xi) {
+  if (!path) return fail(MCLBM_EINVAL, "checkpoint_info: path is NULL");
+  FILE* fp = std::fopen(path, "rb");
+  if (!fp) return fail(MCLBM_EINVAL, std::string("checkpoint_info: cannot open ") + path);
+  CkptHeader H;
+  const int rc = read_ckpt_header(fp, H);
+  std::fclose(fp);
+  if (rc) return rc;
+  if (xi_out && !H.xi.empty()) {
+    if (xi_cap < H.xi.size()) return fail(MCLBM_EINVAL, "checkpoint_info: xi_out holds fewer than nx*ny values");
+    std::memcpy(xi_out, H.xi.data(), H.xi.size() * sizeof(double));
+  }
+  if (cfg_out) *cfg_out = H.cfg;
+  if (t_out) *t_out = (int64_t)H.t;
+  if (n_xi) *n_xi = H.xi.size();
   return MCLBM_OK;
 }
 

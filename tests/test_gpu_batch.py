@@ -12,6 +12,7 @@ if not torch.cuda.is_available():
 import oracle  # noqa: E402
 import paper_1511_04552_amd as mc  # noqa: E402
 from paper_1511_04552_amd import inputs  # noqa: E402
+from parity import field_errors  # noqa: E402
 
 CFGS = [dict(nx=16, ny=16, Ra=1e4, phi0=0.01, dp_nm=100.0),
         dict(nx=37, ny=29, Ra=3e4, phi0=0.02, dp_nm=40.0),
@@ -38,10 +39,9 @@ def test_batch_bitwise_equals_single_cavities_and_matches_oracle():
     for k in (1, 3):
         o = oracle.Oracle(xi=xis[k], **CFGS[k])
         o.step(301)
-        mg, mo = b.members[k].moments(), o.moments()
-        for f in mo:
-            if np.abs(mo[f]).max() > 0:
-                assert np.abs(mg[f] - mo[f]).max() <= 1e-5 * np.abs(mo[f]).max(), (k, f)
+        err = field_errors(b.members[k].moments(), o.moments())
+        for f, v in err.items():
+            assert v <= 1e-5, (k, f, v)
 
 
 def test_graph_replay_equals_direct_launches():

@@ -17,6 +17,7 @@ if not torch.cuda.is_available():
 import oracle  # noqa: E402
 import paper_1511_04552_amd as mc  # noqa: E402
 from paper_1511_04552_amd import inputs  # noqa: E402
+from parity import field_errors  # noqa: E402
 
 
 class _knobs:
@@ -60,13 +61,11 @@ def test_index64_and_streaming_paths_match_oracle(cfg, tol):
     ref = _cavity(cfg, xi, 1001).moments()
     for knobs in (dict(), dict(index64=True), dict(streaming=True), dict(index64=True, streaming=True)):
         mg = _cavity(cfg, xi, 1001, **knobs).moments()
-        worst, to_default = 0.0, 0.0
-        for f in mo:
-            scale = np.abs(mo[f]).max()
-            if scale > 0:
-                worst = max(worst, np.abs(mg[f] - mo[f]).max() / scale)
-                to_default = max(to_default, np.abs(mg[f] - ref[f]).max() / scale)
+        err = field_errors(mg, mo)
+        worst = max(err.values())
+        to_default = max(field_errors(mg, ref).values())
         print(cfg.get("storage", 0), cfg.get("thermal_lattices", 1), knobs,
+              {k: f"{v:.1e}" for k, v in err.items()},
               f"vs oracle {worst:.2e}, vs default path {to_default:.2e}")
         assert worst <= tol, (knobs, worst)
 
@@ -105,9 +104,8 @@ def test_cavity_above_2gib_matches_oracle():
     names = ("rho_f", "theta", "phi")
     mg, mo = g.moments(names), o.moments(names)
     del o
-    for f in names:
-        dev = np.abs(mo[f] - mo[f].mean()).max() if f != "theta" else np.abs(mo[f]).max()
-        assert np.abs(mg[f] - mo[f]).max() <= 1e-5 * dev, f
+    for f, v in field_errors(mg, mo).items():
+        assert v <= 1e-5, (f, v)
     assert abs(mg["phi"].sum() - phi0) <= 1e-6 * phi0
 
 

@@ -19,6 +19,7 @@ if not torch.cuda.is_available():
 import oracle  # noqa: E402
 import paper_1511_04552_amd as mc  # noqa: E402
 from paper_1511_04552_amd import inputs  # noqa: E402
+from parity import field_errors  # noqa: E402
 
 BOUNDS = {mc.FP16S: (5e-3, 6e-3), mc.BF16S: (1.2e-1, 3e-1)}  # (moments, Nu)
 
@@ -39,7 +40,7 @@ def test_reduced_precision_error_is_bounded(storage, reference):
     g = mc.Cavity(xi=xi, storage=storage, **cfg)
     g.step(1000)
     mg, ng = g.moments(), g.nusselt()
-    err = {k: float(np.abs(mg[k] - mo[k]).max() / np.abs(mo[k]).max()) for k in mo}
+    err = field_errors(mg, mo)
     nu_err = abs(ng[0] - no[0]) / no[0]
     print("storage", storage, {k: f"{v:.1e}" for k, v in err.items()}, f"Nu {nu_err:.1e}")
     mb, nb = BOUNDS[storage]

@@ -12,13 +12,12 @@ if not torch.cuda.is_available():
 import oracle  # noqa: E402
 import paper_1511_04552_amd as mc  # noqa: E402
 from paper_1511_04552_amd import inputs  # noqa: E402
+from parity import field_errors  # noqa: E402
 
 
 def _close(mg, mo, tol=1e-5):
-    for f in mo:
-        scale = np.abs(mo[f]).max()
-        if scale > 0:
-            assert np.abs(mg[f] - mo[f]).max() <= tol * scale, f
+    for f, v in field_errors(mg, mo).items():
+        assert v <= tol, (f, v)
 
 
 @pytest.mark.parametrize("ratio", [0.5, 2.0])

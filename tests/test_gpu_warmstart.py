@@ -14,6 +14,7 @@ import oracle  # noqa: E402
 from oracle import warmstart  # noqa: E402
 import paper_1511_04552_amd as mc  # noqa: E402
 from paper_1511_04552_amd import inputs  # noqa: E402
+from parity import assert_fields  # noqa: E402
 
 DEV = torch.device("cuda")
 
@@ -52,13 +53,8 @@ def _case(cfg, xi, F, affine, steps):
     return g, o
 
 
-def _compare(g, o, tol=1e-5):
-    mg, mo = g.moments(), o.moments()
-    for f in mo:
-        scale = np.abs(mo[f]).max()
-        if scale > 0:
-            err = np.abs(mg[f] - mo[f]).max() / scale
-            assert err <= tol, (f, err)
+def _compare(g, o, tol=1e-5, dev_tol=None):
+    assert_fields(g.moments(), o.moments(), tol, label=f"t={o.time}", dev_tol=dev_tol)
 
 
 NO_ROT = mc.F_ALL & ~mc.F_MAGROT
@@ -89,7 +85,12 @@ def test_load_fields_matches_oracle(cfg, src):
     if nc > 4:
         affine = affine[:4] + [1e-4] + affine[4:] + [0.0]
     g, o = _case(cfg, xi, F, affine, 0)
-    _compare(g, o, tol=1e-6)
+    # at t = 0 the loaded rho_f is uniform (4 channels) or carries a 1e-4
+    # pattern (5 channels), while the same FP32 populations carry the loaded
+    # velocities (u = 0.02): their rounding leaves ~1e-9 in rho_f, up to
+    # 1.1e-5 of the pattern (or of its 1e-4 floor); every other field within
+    # 1e-6 of its scale
+    _compare(g, o, tol=1e-6, dev_tol=5e-5)
     # the lag field and the residual snapshot are those of the loaded state
     res_g, res_o = g.residual(), o.residual()
     assert res_g[0] == 0.0 and res_o[0] == 0.0
