@@ -282,6 +282,27 @@ int mclbm_nusselt(mclbm_cavity* c, double* nu_hot, double* nu_cold,
  * MCLBM_EDIVERGED if any node is not finite. */
 int mclbm_residual(mclbm_cavity* c, double* res_u, double* res_theta);
 
+/* For callers that cannot allocate device memory or wait on the host (code
+ * under HIP graph capture, tight serving loops): mclbm_residual with its
+ * per-block FP64 partials in a library-owned static device array instead
+ * of the cavity's buffer, and its result left in device memory instead of
+ * being returned after a synchronisation.
+ *   dev_out: device memory of 3 doubles, 8-byte aligned, written on the
+ *     cavity's stream: [0] relative L2 change of the mixture velocity,
+ *     [1] of theta (as mclbm_residual), [2] 1.0 if any node was not finite,
+ *     else 0.0 (mclbm_residual's MCLBM_EDIVERGED).
+ * The current state becomes the new reference, as in mclbm_residual.
+ * Async; no device or host allocation, no synchronisation.  The cavity's
+ * device must be current.  The static array holds MCLBM_NOALLOC_SCRATCH_BYTES
+ * on every GPU the library runs on, until the process ends; larger cavities
+ * (more than MCLBM_NOALLOC_MAX_NODES nodes) are rejected with MCLBM_EINVAL.
+ * Every call on one GPU uses the same array: calls that overlap in time on
+ * one GPU (different streams, or different host threads) race and must be
+ * ordered by the caller.  Nothing in the array needs to start at zero. */
+#define MCLBM_NOALLOC_SCRATCH_BYTES (4u << 20)
+#define MCLBM_NOALLOC_MAX_NODES (((MCLBM_NOALLOC_SCRATCH_BYTES) / 40u) * 256u)
+int mclbm_residual_noalloc(mclbm_cavity* c, double* dev_out);
+
 /* Derived lattice constants, MCLBM_D_COUNT doubles (enum slots). */
 int mclbm_derived(const mclbm_cavity* c, double* out, int n);
 

@@ -32,7 +32,7 @@ DERIVED = ("nu_L", "alpha_L", "H", "dx", "dt", "G_L", "grav_L", "Ck", "R", "tau_
 EXPORTED = ("mclbm_config_defaults", "mclbm_device_bytes", "mclbm_derive_constants", "mclbm_create",
             "mclbm_set_properties", "mclbm_reset", "mclbm_load_fields", "mclbm_step", "mclbm_time",
             "mclbm_export_moments", "mclbm_read_moments", "mclbm_read_populations",
-            "mclbm_export_populations", "mclbm_nusselt", "mclbm_residual",
+            "mclbm_export_populations", "mclbm_nusselt", "mclbm_residual", "mclbm_residual_noalloc",
             "mclbm_derived", "mclbm_checkpoint", "mclbm_restore", "mclbm_checkpoint_info", "mclbm_destroy", "mclbm_last_error",
             "mclbm_copy_kernel",
             "mclbm_version", "mclbm_abi_version",
@@ -111,6 +111,7 @@ def lib(load_torch: bool = True):
     L.mclbm_export_populations.argtypes = [P, P, ctypes.c_size_t]
     L.mclbm_nusselt.argtypes = [P, D, D, D]
     L.mclbm_residual.argtypes = [P, D, D]
+    L.mclbm_residual_noalloc.argtypes = [P, P]
     L.mclbm_derived.argtypes = [P, D, I]
     L.mclbm_destroy.argtypes = [P]
     L.mclbm_last_error.restype = ctypes.c_char_p
@@ -356,6 +357,16 @@ class Cavity:
         if check:
             _check(rc)
         return a.value, b.value
+
+    def residual_noalloc(self, dev_out) -> None:
+        """mclbm_residual_noalloc: the residual into ``dev_out`` (a float64
+        device tensor of at least 3 values: res_u, res_theta, non-finite
+        flag) on the cavity's stream, without allocation or synchronisation."""
+        import torch
+        if dev_out.dtype != torch.float64 or not dev_out.is_cuda or dev_out.numel() < 3 \
+                or not dev_out.is_contiguous():
+            raise ValueError("dev_out must be a contiguous float64 device tensor of >= 3 values")
+        _check(lib().mclbm_residual_noalloc(self._h, ctypes.c_void_p(dev_out.data_ptr())))
 
     def derived(self) -> dict:
         out = np.zeros(len(DERIVED))

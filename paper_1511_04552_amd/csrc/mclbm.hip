@@ -24,6 +24,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -602,6 +603,23 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__
                                                       int nblocks,
                                                       double* __restrict__ out) {
   sum_partials_body(partial, nblocks, out);
+}
+
+// The same fixed-order sum, finished on the device: out[0] = residual of
+// the mixture velocity, out[1] = residual of theta (the host formulas of
+// mclbm_residual, in FP64), out[2] = 1 if any node was non-finite, else 0.
+__global__ __launch_bounds__(256) void k_sum_partials_finish(const double* __restrict__ partial,
+                                                             int nblocks,
+                                                             double* __restrict__ out) {
+  __shared__ double sums[5];
+  sum_partials_body(partial, nblocks, sums);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double du = sums[0], un = sums[1], dt = sums[2], tn = sums[3];
+    out[0] = un > 0.0 ? sqrt(du / un) : (du > 0.0 ? (double)INFINITY : 0.0);
+    out[1] = tn > 0.0 ? sqrt(dt / tn) : (dt > 0.0 ? (double)INFINITY : 0.0);
+    out[2] = sums[4] != 0.0 ? 1.0 : 0.0;
+  }
 }
 
 // The reductions of every active cavity of a batch (all at one step
@@ -1189,6 +1207,14 @@ StepParams make_params(const mclbm_config& c, const Derived& D, const Layout& L)
 
 }  // namespace
 
+// ---- static scratch of the allocation-free residual -------------------------
+// mclbm_residual_noalloc keeps its per-block FP64 partials here instead of in
+// the cavity's buffer: one copy of the array per GPU, held for the life of
+// the process.  In host code `scratch` names a host-side stand-in, not a
+// device address; host code uses only the address resolved per device by
+// noalloc_scratch().
+static __device__ __align__(256) double scratch[MCLBM_NOALLOC_SCRATCH_BYTES / sizeof(double)];
+
 struct mclbm_cavity {
   mclbm_config cfg;
   std::vector<double> xi;
@@ -1212,6 +1238,7 @@ struct mclbm_cavity {
   int strips2, band2;
   const int64_t* batch_clock;  // the owning batch's step count (members only)
   std::vector<double> host_dev_p;  // initial phi deviations (source of an async copy)
+  int device = -1;     // HIP device current at creation
 
   size_t pop_off(int k) const { return k ? L.off_pop2 : L.off_pop; }
   void* pop() { return base + pop_off(popsel); }
@@ -1521,25 +1548,63 @@ int finish_nusselt(const double* h, double* nu_hot, double* nu_cold, double* nu_
   return MCLBM_OK;
 }
 
-int enqueue_residual(mclbm_cavity* c, double* h) {
+// Per-block partial sums of the residual into `part` (5 doubles per block
+// of 256 nodes); the snapshot becomes the current state.
+int enqueue_residual_partials(mclbm_cavity* c, double* part) {
   const unsigned rb = (unsigned)c->L.red_blocks;
   const double rf = (double)c->P.rho_f_ref, rp = (double)c->P.rho_p_ref;
-  int rc = dispatch(c, [&](auto k) {
+  return dispatch(c, [&](auto k) {
     using S = typename decltype(k)::S;
     using I = typename decltype(k)::I;
     const auto* pop = reinterpret_cast<const typename S::T*>(c->pop());
     if (c->t & 1)
-      k_residual<true, S, I, decltype(k)::NL><<<rb, 256, 0, c->stream>>>(c->P, pop, c->d5(), rf, rp, c->snap(), c->part());
+      k_residual<true, S, I, decltype(k)::NL><<<rb, 256, 0, c->stream>>>(c->P, pop, c->d5(), rf, rp, c->snap(), part);
     else
-      k_residual<false, S, I, decltype(k)::NL><<<rb, 256, 0, c->stream>>>(c->P, pop, c->d5(), rf, rp, c->snap(), c->part());
+      k_residual<false, S, I, decltype(k)::NL><<<rb, 256, 0, c->stream>>>(c->P, pop, c->d5(), rf, rp, c->snap(), part);
     return launch_check("k_residual");
   });
+}
+
+int enqueue_residual(mclbm_cavity* c, double* h) {
+  const unsigned rb = (unsigned)c->L.red_blocks;
+  int rc = enqueue_residual_partials(c, c->part());
   if (rc) return rc;
   k_sum_partials<<<1, 256, 0, c->stream>>>(c->part(), (int)rb, c->res() + 4);
   rc = launch_check("k_sum_partials");
   if (rc) return rc;
   HIP_TRY(hipMemcpyAsync(h, c->res() + 4, 5 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   return MCLBM_OK;
+}
+
+// Device address of `scratch` on device `dev` (which must be current),
+// resolved once per device and kept.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+int noalloc_scratch(int dev, double** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(MCLBM_EINVAL, "device ordinal out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return MCLBM_OK;
+}
+
+// Set-up step of a cavity: record its device and resolve that device's
+// scratch address while no stream capture can be running.  A failure here
+// is reported by the first mclbm_residual_noalloc call instead.
+void setup_device(mclbm_cavity* c) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return;
+  c->device = dev;
+  double* unused = nullptr;
+  (void)noalloc_scratch(dev, &unused);
+  (void)hipGetLastError();
 }
 
 int finish_residual(const double* h, double* res_u, double* res_theta) {
@@ -1759,6 +1824,7 @@ int mclbm_create(const mclbm_config* cfg, const double* xi_host, void* dev_buf, 
   c->base = reinterpret_cast<char*>(dev_buf);
   c->bytes = bytes;
   setup_cavity(c);
+  setup_device(c);
   log_derived(c->cfg, c->D);
   rc = enqueue_init(c);
   if (rc) {
@@ -1906,6 +1972,27 @@ int mclbm_residual(mclbm_cavity* c, double* res_u, double* res_theta) {
   if (rc) return rc;
   HIP_TRY(hipStreamSynchronize(c->stream));
   return finish_residual(h, res_u, res_theta);
+}
+
+int mclbm_residual_noalloc(mclbm_cavity* c, double* dev_out) {
+  if (!c) return fail(MCLBM_EINVAL, "cavity is NULL");
+  if (!dev_out || reinterpret_cast<uintptr_t>(dev_out) % alignof(double) != 0)
+    return fail(MCLBM_EINVAL, "dev_out must be a non-NULL device pointer aligned to 8 bytes");
+  const size_t need = (size_t)5 * c->L.red_blocks * sizeof(double);
+  if (need > (size_t)MCLBM_NOALLOC_SCRATCH_BYTES)
+    return fail(MCLBM_EINVAL, "cavity of " + std::to_string((long long)c->cfg.nx * c->cfg.ny) +
+                                  " nodes exceeds the static scratch of mclbm_residual_noalloc (at most " +
+                                  std::to_string((long long)MCLBM_NOALLOC_MAX_NODES) + " nodes)");
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != c->device) return fail(MCLBM_EINVAL, "the cavity's device must be current");
+  double* part = nullptr;
+  int rc = noalloc_scratch(dev, &part);
+  if (rc) return rc;
+  rc = enqueue_residual_partials(c, part);
+  if (rc) return rc;
+  k_sum_partials_finish<<<1, 256, 0, c->stream>>>(part, c->L.red_blocks, dev_out);
+  return launch_check("k_sum_partials_finish");
 }
 
 int mclbm_derived(const mclbm_cavity* c, double* out, int n) {
@@ -2463,6 +2550,7 @@ int mclbm_batch_create(const mclbm_config* cfgs, int32_t n, const double* const*
     c->in_batch = true;
     c->batch_clock = &b->t;
     setup_cavity(c);
+    setup_device(c);
     // the batched kernel runs 256-thread workgroups: every tile shape must
     // cover exactly 256 nodes (bx * by == 256)
     if (c->block.x * c->block.y != 256) {

@@ -102,6 +102,7 @@ static void configs(void) {
   mclbm_config bad = c;
   bad.nx = 2;
   EXPECT(mclbm_create(&bad, NULL, (void*)0x1000, 1u << 30, NULL, &cav) == MCLBM_EINVAL);
+  EXPECT(mclbm_residual_noalloc(NULL, NULL) == MCLBM_EINVAL);
   EXPECT(strlen(mclbm_version()) > 0 && mclbm_abi_version() == MCLBM_ABI_VERSION);
 }
 
