@@ -20,6 +20,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E
+LLC_BYTES = 256 << 20           # MI355X last-level cache (MALL)
 BYTES_PER_LUP_FP32 = 232        # 27 populations read + written (4 B), lag field read + written (8 B)
 BYTES_PER_LUP_16 = 124          # the same with 2-byte populations
 STORAGE = {"fp32": (0, BYTES_PER_LUP_FP32, "fp32"), "fp16": (1, BYTES_PER_LUP_16, "fp16 (scaled)"),
@@ -163,11 +164,18 @@ def batch_measure(torch, mc, inputs, n, steps=64):
 
 
 def warm_start_measure():
-    """Time to a steady hot-wall Nu (within 1e-3 of Nu_inf), cold start vs
-    the learned warm start: a surrogate trained on 128 steady states of 32^2
-    cavities predicts 16 held-out 64^2 cavities (up-sampled); both starts run
-    one fixed horizon as a batch, Nu_inf is the cold start's final Nu.  The
-    plain reference runs the cavities one at a time from a cold start."""
+    """Time to a steady hot-wall Nu on 16 held-out 64^2 cavities, four ways:
+    plain (each cavity alone, one after another, FP32, cold start), batched
+    cold, batched warm (a surrogate trained on 128 steady states of 32^2
+    cavities predicts the fields, up-sampled and loaded), and batched warm
+    with the transient in FP16 storage, finished in FP32.  Every run stops
+    where the solver's own criterion is met (change of u and theta over 500
+    steps below 1e-6; batched cavities drop out there).  Nu_inf is the final
+    Nu of a cold batch run for 1e6 steps without drop-out; a run has settled
+    from the first record after which its Nu stays within 1e-3 of Nu_inf.
+    Wall times are measured: to the settled record of every cavity (plain:
+    summed, since the cavities run one after another; batched: the last one)
+    and to the criterion of every cavity."""
     import numpy as np
     import torch
     from paper_1511_04552_amd import inputs, surrogate as sg
@@ -187,40 +195,68 @@ def warm_start_measure():
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     test = cases(9002, 16, 64)
-    cold = sg.run_to_steady(test, None, chunk=500, tol=1e-6, max_steps=1_000_000, drop=False)
-    print(f"# warm start: cold runs {cold['seconds']:.1f} s", file=sys.stderr, flush=True)
-    warm = sg.run_to_steady(test, ws, chunk=500, tol=1e-6, max_steps=1_000_000, drop=False)
-    sc = sg.settle_steps(cold["times"], cold["nu_hist"], cold["nu"])
-    sw = sg.settle_steps(warm["times"], warm["nu_hist"], cold["nu"])
-    both = cold["converged"] & warm["converged"]
-    per_step = cold["seconds"] / cold["times"][-1]
-    # the plain way: one cavity at a time, FP32, cold start, each run until
-    # its Nu has settled, at the measured step time of a single cavity
-    from paper_1511_04552_amd import Cavity
-    one = Cavity(**sg._cavity_kw(test[0]))
-    one.step(200)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(one.stream)
-    one.step(4000)
-    e1.record(one.stream)
-    torch.cuda.synchronize()
-    single_step = e0.elapsed_time(e1) * 1e-3 / 4000
-    del one
-    plain = float(sc.sum() * single_step)
-    warm_s = float(sw.max() * per_step + warm["t_load"])
+    ref = sg.run_to_steady(test, None, chunk=500, tol=1e-6, max_steps=1_000_000, drop=False)
+    nu_inf = ref["nu"]
+    print(f"# warm start: reference runs {ref['seconds']:.1f} s", file=sys.stderr, flush=True)
+    cold = sg.run_to_steady(test, None, chunk=500, tol=1e-6, max_steps=1_000_000, drop=True)
+    warm = sg.run_to_steady(test, ws, chunk=500, tol=1e-6, max_steps=1_000_000, drop=True)
+    # the reduced-precision leg: FP16 storage for the transient, each cavity
+    # moved to FP32 (mclbm_copy_state) once its change over 500 steps is
+    # below 1e-3 (FP16 storage levels off at ~6e-4, its Nu ~3e-3 from Nu_inf)
+    mixed = sg.run_mixed(test, ws, storage=1, switch_tol=1e-3, chunk=500, tol=1e-6, max_steps=1_000_000)
+    plain = sg.run_plain(test, chunk=500, tol=1e-6, max_steps=1_000_000)
+    print(f"# warm start: plain runs {sum(p['seconds'] for p in plain):.1f} s", file=sys.stderr, flush=True)
+
+    def batched(run):
+        st = sg.settle_steps(run["times"], run["nu_hist"], nu_inf)
+        at = {int(t): w for t, w in zip(run["times"], run["walls"])}
+        settle = max(at[int(s)] for s in st) + run["t_load"]
+        own = run["seconds"] + run["t_load"]
+        return st, settle, own
+
+    sc, cold_settle, cold_own = batched(cold)
+    sw, warm_settle, warm_own = batched(warm)
+    sm, mixed_settle, mixed_own = batched(mixed)
+    plain_settle, plain_own, sp = 0.0, 0.0, []
+    for k, p in enumerate(plain):
+        rec = p["records"]
+        s_k = sg.settle_steps(rec[:, 0], rec[:, 2:3], nu_inf[k:k + 1])[0]
+        sp.append(s_k)
+        plain_settle += float(rec[rec[:, 0] == s_k, 1][0])
+        plain_own += p["seconds"]
+    sp = np.array(sp)
+    final = lambda run: np.abs(run["nu"] - nu_inf) / np.abs(nu_inf)
     return {"workload": "16 held-out 64^2 cavities (Ra 1e3-1e6, phi0 0-0.05, d_p 10-100 nm) warm-started "
                         "from an FNO trained on 128 steady states of 32^2",
-            "criterion": "steps until Nu stays within 1e-3 of Nu_inf", "horizon_steps": 1_000_000,
-            "cold_settle_steps_sum": int(sc.sum()), "warm_settle_steps_sum": int(sw.sum()),
+            "criterion": "wall time until the hot-wall Nu stays within 1e-3 of Nu_inf (settle), and until "
+                         "the solver's own criterion (change of u, theta over 500 steps < 1e-6)",
+            "nu_inf": "final Nu of a cold batched FP32 run of 1e6 steps without drop-out",
+            "settle_steps_sum": {"plain": int(sp.sum()), "cold": int(sc.sum()), "warm": int(sw.sum())},
             "settle_ratio": round(float(sc.sum() / max(sw.sum(), 1)), 2),
             "settle_ratio_median": round(float(np.median(sc / np.maximum(sw, 1))), 2),
-            "own_criterion_ratio": round(float(cold["steps"][both].sum() / max(warm["steps"][both].sum(), 1)), 2),
-            "final_nu_rel_diff_max": float(np.max(np.abs(warm["nu"] - cold["nu"]) / np.abs(cold["nu"]))),
-            "seconds_to_settle_cold": round(float(sc.max() * per_step), 3),
-            "seconds_to_settle_warm": round(warm_s, 3),
-            "seconds_to_settle_plain": round(plain, 3),
-            "plain_over_warm_batched": round(plain / warm_s, 1),
+            "own_criterion_steps_sum": {"plain": int(sum(p["steps"] for p in plain)),
+                                        "cold": int(cold["steps"].sum()), "warm": int(warm["steps"].sum())},
+            "own_criterion_met": {"plain": int(sum(p["steps"] > 0 for p in plain)),
+                                  "cold": int(cold["converged"].sum()), "warm": int(warm["converged"].sum())},
+            "final_nu_rel_err_max": {"plain": float(max(abs(p["records"][-1, 2] - nu_inf[k]) / abs(nu_inf[k])
+                                                        for k, p in enumerate(plain))),
+                                     "cold": float(final(cold).max()), "warm": float(final(warm).max())},
+            "seconds_to_settle": {"plain": round(plain_settle, 3), "cold_batched": round(cold_settle, 3),
+                                  "warm_batched": round(warm_settle, 3),
+                                  "warm_batched_fp16_transient": round(mixed_settle, 3)},
+            "seconds_to_own_criterion": {"plain": round(plain_own, 3), "cold_batched": round(cold_own, 3),
+                                         "warm_batched": round(warm_own, 3),
+                                         "warm_batched_fp16_transient": round(mixed_own, 3)},
+            "fp16_transient": {"switch_tol": 1e-3, "switched": int((mixed["switched"] > 0).sum()),
+                               "own_criterion_met": int(mixed["converged"].sum()),
+                               "final_nu_rel_err_max": float(final(mixed).max()),
+                               "settle_steps_sum": int(sm.sum())},
+            "plain_over_warm_batched": round(plain_settle / warm_settle, 1),
+            "plain_over_warm_batched_own_criterion": round(plain_own / warm_own, 1),
+            "gain_from_batching": round(plain_settle / cold_settle, 2),
+            "gain_from_warm_start": round(cold_settle / warm_settle, 2),
+            "gain_from_warm_start_own_criterion": round(cold_own / warm_own, 2),
+            "seconds_load": round(warm["t_load"], 3),
             "seconds_training_data": round(t_data, 1), "seconds_training": round(t_train, 1)}
 
 
@@ -276,6 +312,7 @@ def main():
         print("with two steps per launch, --steps and --warmup must be even", file=sys.stderr)
         sys.exit(2)
     cav = mc.Cavity(xi=xi, storage=st_code, steps_per_launch=spl, **cfg)
+    nbytes_dev = cav.nbytes
     stream = cav.stream
     cav.step(a.warmup)
     torch.cuda.synchronize()
@@ -359,8 +396,15 @@ def main():
     warm = None
     if not a.no_warm_start and not a.no_secondary:
         warm = warm_start_measure()
+    # a working set inside the 256 MB last-level cache (MALL) is served from
+    # it, not from HBM: the fraction is then an effective rate, and the
+    # HBM-bound figure is the hbm_streaming line
+    resident = nbytes_dev <= LLC_BYTES
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
+            "cache_resident": resident, "working_set_bytes": nbytes_dev,
+            "note": ("working set fits the 256 MB last-level cache: effective bandwidth, not HBM; "
+                     "see hbm_streaming for the HBM-bound rate") if resident else "streams from HBM",
             "kernel": ("k_step (even and odd A-A parities)" if spl == 1 else
                        "k_step2 (an even and an odd step per launch)"),
             "algorithmic_bytes_per_launch": bytes_launch, "copy_kernel_gbps": round(copy_gbps, 1)}

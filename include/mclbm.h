@@ -238,6 +238,18 @@ int mclbm_reset(mclbm_cavity* c);
 int mclbm_load_fields(mclbm_cavity* c, const float* dev_fields, int32_t sx,
                       int32_t sy, int32_t nc, const double* affine);
 
+/* Continue a run in another storage type: the state of src (populations,
+ * converted from src's storage type and scale to dst's; the lag fields;
+ * the adiabatic side buffer; the residual reference; the step count)
+ * becomes dst's.  Both cavities must have the same configuration apart
+ * from the storage type and the launch shape (MCLBM_EINVAL otherwise);
+ * src must be at an even step count, and a dst that belongs to a batch
+ * needs its batch at an even step count (MCLBM_ESTATE otherwise).  Used to
+ * run the transient with 16-bit storage (Section 2.d's scheme is unchanged;
+ * only the rounding of the stored populations differs) and finish in FP32.
+ * Waits for src's stream, then enqueues on dst's and waits for it (sync). */
+int mclbm_copy_state(mclbm_cavity* dst, const mclbm_cavity* src);
+
 /* Advance nsteps >= 0 time steps (Eqs 18-36: collision with the slip
  * forces, streaming, walls).  Each step is one fused kernel launch, or with
  * two steps per launch (steps_per_launch) each pair from an even step

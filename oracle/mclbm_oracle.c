@@ -19,11 +19,18 @@
  *
  * Parity status per part: the equilibrium, forcing, streaming, walls,
  * conduction limit, drag integrator and Nusselt definition are pinned by
- * closed forms and invariants in the tests.  The magnitudes of the Brownian,
- * thermophoretic, Saffman, Magnus/rotation and gravity forces follow the
- * printed formulas under the stated readings; they are checked only by
- * scaling laws and limits, their physical values are parity unpinned (the
- * paper prints no value that could fix them).
+ * closed forms and invariants in the tests.  Of the slip forces (Table 1,
+ * under the stated readings): the Magnus term is pinned to the Magnus time
+ * scale of Table 2 (rate v_M / d_p, against the slip), the rotation term to
+ * Table 2's rotation time scale and the sphere's area-to-volume ratio, the
+ * drag coefficient to the Schiller-Naumann law (its value at Re_d = 1 and
+ * its slope), the thermophoretic coefficient to its continuum (k*) and
+ * free-molecular (C_m) limits, and the settling force to Archimedes'
+ * principle.  Parity unpinned: the absolute prefactors of the Brownian force
+ * (the factors of D_B and v_B), of the Saffman lift (K_S / 4) and the
+ * thermophoretic constants C_S and C_t; these are checked only through
+ * directions and scaling laws (the paper prints no value that could fix
+ * them).
  */
 #include "mclbm_oracle.h"
 

@@ -30,7 +30,8 @@ FIELD_BIT = {name: 1 << i for i, name in enumerate(FIELDS)}
 DERIVED = ("nu_L", "alpha_L", "H", "dx", "dt", "G_L", "grav_L", "Ck", "R", "tau_f",
            "rhoc_ratio", "beta_ratio", "rho_f0", "rho_p0", "nu_f", "alpha_f")
 EXPORTED = ("mclbm_config_defaults", "mclbm_device_bytes", "mclbm_derive_constants", "mclbm_create",
-            "mclbm_set_properties", "mclbm_reset", "mclbm_load_fields", "mclbm_step", "mclbm_time",
+            "mclbm_set_properties", "mclbm_reset", "mclbm_load_fields", "mclbm_copy_state", "mclbm_step",
+            "mclbm_time",
             "mclbm_export_moments", "mclbm_read_moments", "mclbm_read_populations",
             "mclbm_export_populations", "mclbm_nusselt", "mclbm_residual", "mclbm_residual_noalloc",
             "mclbm_derived", "mclbm_checkpoint", "mclbm_restore", "mclbm_checkpoint_info", "mclbm_destroy", "mclbm_last_error",
@@ -103,6 +104,7 @@ def lib(load_torch: bool = True):
                                         ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
     L.mclbm_load_fields.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, D]
     L.mclbm_step.argtypes = [P, ctypes.c_int64]
+    L.mclbm_copy_state.argtypes = [P, P]
     L.mclbm_time.argtypes = [P]
     L.mclbm_time.restype = ctypes.c_int64
     L.mclbm_export_moments.argtypes = [P, ctypes.c_uint32, P, ctypes.c_size_t]
@@ -312,6 +314,12 @@ class Cavity:
             aff = _dptr(self._affine)
         _check(lib().mclbm_load_fields(self._h, ctypes.c_void_p(f.data_ptr()), int(f.shape[1]),
                                        int(f.shape[0]), nc, aff))
+
+    def copy_state_from(self, src: "Cavity") -> None:
+        """mclbm_copy_state: continue ``src``'s run here, converting the
+        populations to this cavity's storage type (same configuration
+        otherwise; ``src`` at an even step count)."""
+        _check(lib().mclbm_copy_state(self._h, src._h))
 
     # ---- outputs ------------------------------------------------------------
     @staticmethod

@@ -882,6 +882,20 @@ __global__ __launch_bounds__(256) void k_poison(float* __restrict__ p, long long
     p[k] = __builtin_nanf("");
 }
 
+// Population storage conversion between two cavities of one layout: each
+// stored deviation read in the source's type and scale, written in the
+// destination's (the reference state does not depend on the storage).
+template <class SS, class SD>
+__global__ __launch_bounds__(256) void k_convert(const typename SS::T* __restrict__ src,
+                                                 typename SD::T* __restrict__ dst, long long plane,
+                                                 long long n, StepParams PS, StepParams PD) {
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (long long)gridDim.x * blockDim.x) {
+    const int l = min((int)(k / (9 * plane)), 2);
+    SD::st(dst + k, SS::ld(src + k, PS.inv_scale[l]), PD.scale[l]);
+  }
+}
+
 __global__ __launch_bounds__(256) void k_copy(v4f* __restrict__ dst,
                                               const v4f* __restrict__ src,
                                               long long n) {
@@ -1763,6 +1777,28 @@ void log_derived(const mclbm_config& c, const Derived& D) {
 // C ABI
 // ===========================================================================
 
+namespace {
+template <class SS>
+int launch_convert(mclbm_cavity* dst, const mclbm_cavity* src, long long n) {
+  const auto* from = reinterpret_cast<const typename SS::T*>(const_cast<mclbm_cavity*>(src)->pop());
+  const unsigned grid = (unsigned)std::min<long long>((n + 255) / 256, 1 << 16);
+  switch (dst->cfg.storage) {
+    case MCLBM_FP32S:
+      k_convert<SS, StorF32<false>><<<grid, 256, 0, dst->stream>>>(
+          from, reinterpret_cast<float*>(dst->pop()), dst->L.plane, n, src->P, dst->P);
+      break;
+    case MCLBM_FP16S:
+      k_convert<SS, StorF16<false>><<<grid, 256, 0, dst->stream>>>(
+          from, reinterpret_cast<__half*>(dst->pop()), dst->L.plane, n, src->P, dst->P);
+      break;
+    default:
+      k_convert<SS, StorBF16<false>><<<grid, 256, 0, dst->stream>>>(
+          from, reinterpret_cast<__hip_bfloat16*>(dst->pop()), dst->L.plane, n, src->P, dst->P);
+  }
+  return launch_check("k_convert");
+}
+}  // namespace
+
 extern "C" {
 
 void mclbm_config_defaults(mclbm_config* c) {
@@ -1870,6 +1906,37 @@ int mclbm_load_fields(mclbm_cavity* c, const float* dev_fields, int32_t sx, int3
     for (int q = 0; q < 2 * nc; ++q)
       if (!std::isfinite(affine[q])) return fail(MCLBM_EINVAL, "load_fields: affine map not finite");
   return enqueue_load_fields(c, dev_fields, sx, sy, nc, affine);
+}
+
+int mclbm_copy_state(mclbm_cavity* dst, const mclbm_cavity* src) {
+  if (!dst || !src || dst == src) return fail(MCLBM_EINVAL, "copy_state: NULL or identical cavities");
+  mclbm_config a = dst->cfg, b = src->cfg;
+  a.storage = b.storage = MCLBM_FP32S;
+  if (config_key(a) != config_key(b))
+    return fail(MCLBM_EINVAL, "copy_state: the configurations differ beyond storage and launch shape");
+  if (src->t & 1) return fail(MCLBM_ESTATE, "copy_state: the source is at an odd step; step it once more");
+  if (dst->in_batch && (!dst->batch_clock || (*dst->batch_clock & 1)))
+    return fail(MCLBM_ESTATE, "copy_state: the destination's batch is at an odd step");
+  HIP_TRY(hipStreamSynchronize(src->stream));
+  const long long n = 9LL * dst->P.nl * dst->L.plane;
+  int rc;
+  switch (src->cfg.storage) {
+    case MCLBM_FP32S: rc = launch_convert<StorF32<false>>(dst, src, n); break;
+    case MCLBM_FP16S: rc = launch_convert<StorF16<false>>(dst, src, n); break;
+    default: rc = launch_convert<StorBF16<false>>(dst, src, n);
+  }
+  if (rc) return rc;
+  mclbm_cavity* s_ = const_cast<mclbm_cavity*>(src);
+  for (int k = 0; k < 2; ++k)
+    HIP_TRY(hipMemcpyAsync(dst->d2(k), s_->d2(k), (size_t)dst->L.plane * sizeof(float2),
+                           hipMemcpyDeviceToDevice, dst->stream));
+  HIP_TRY(hipMemcpyAsync(dst->d5(), s_->d5(), (size_t)6 * (dst->P.nl - 2) * dst->L.px * sizeof(float),
+                         hipMemcpyDeviceToDevice, dst->stream));
+  HIP_TRY(hipMemcpyAsync(dst->snap(), s_->snap(), (size_t)3 * dst->cfg.nx * dst->cfg.ny * sizeof(double),
+                         hipMemcpyDeviceToDevice, dst->stream));
+  HIP_TRY(hipStreamSynchronize(dst->stream));
+  dst->t = src->t;
+  return MCLBM_OK;
 }
 
 int mclbm_step(mclbm_cavity* c, int64_t nsteps) {

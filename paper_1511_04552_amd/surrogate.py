@@ -468,9 +468,9 @@ def run_to_steady(cases, warm: WarmStart | None = None, chunk: int = 500, tol: f
     every cavity runs ``max_steps`` steps.  Records the hot-wall Nu and the
     residuals of every cavity after every chunk.  Returns a dict: steps
     (first chunk end meeting the criterion, 0 if none), converged, nu
-    (final), times, nu_hist and res_hist (len(times) x n [x 2]), t_load
-    (seconds of prediction and loading), seconds (of stepping), fields
-    (final nondimensional fields)."""
+    (final), times, walls (seconds of stepping at each record), nu_hist and
+    res_hist (len(times) x n [x 2]), t_load (seconds of prediction and
+    loading), seconds (of stepping), fields (final nondimensional fields)."""
     import time
     from . import Batch
     torch = warm.torch if warm is not None else __import__("torch")
@@ -487,7 +487,7 @@ def run_to_steady(cases, warm: WarmStart | None = None, chunk: int = 500, tol: f
         t_load = time.perf_counter() - t0
     steps = np.zeros(n, np.int64)
     alive = np.ones(n, bool)
-    times, hist, rhist = [], [], []
+    times, walls, hist, rhist = [], [], [], []
     b.residual(tol=0.0)
     t = 0
     t0 = time.perf_counter()
@@ -503,14 +503,110 @@ def run_to_steady(cases, warm: WarmStart | None = None, chunk: int = 500, tol: f
         times.append(t)
         hist.append(b.nusselt()[:, 0].copy())
         rhist.append(res.copy())
+        walls.append(time.perf_counter() - t0)
         if log and (t // chunk) % 200 == 0:
             log(f"  t={t} met the criterion {(steps > 0).sum()}/{n}")
     torch.cuda.synchronize()
     secs = time.perf_counter() - t0
     fields = np.stack([nondimensional(b.members[k].moments(TARGETS), cases[k]) for k in range(n)])
     return dict(steps=steps, converged=steps > 0, nu=hist[-1], times=np.array(times),
-                nu_hist=np.array(hist), res_hist=np.array(rhist), t_load=t_load, seconds=secs,
-                fields=fields)
+                walls=np.array(walls), nu_hist=np.array(hist), res_hist=np.array(rhist), t_load=t_load,
+                seconds=secs, fields=fields)
+
+
+def run_mixed(cases, warm: WarmStart | None = None, storage: int = 1, switch_tol: float = 1e-4,
+              chunk: int = 500, tol: float = 1e-6, max_steps: int = 4_000_000, log=None):
+    """The transient with 16-bit population storage (``storage``: 1 FP16,
+    2 BF16), the finish in FP32.  Every case starts (cold, or from ``warm``)
+    in a 16-bit batch; when its change of u and theta over ``chunk`` steps
+    falls below ``switch_tol`` it leaves that batch and its state moves to
+    its member of an FP32 batch (``mclbm_copy_state``), which then runs it
+    to the solver's own criterion (``tol``, drop-out).  Returns what
+    ``run_to_steady`` returns, plus switched (the step of the move, 0 if
+    none)."""
+    import time
+    from . import Batch
+    torch = warm.torch if warm is not None else __import__("torch")
+    n = len(cases)
+    lo = Batch([dict(_cavity_kw(c), storage=storage) for c in cases])
+    hi = Batch([_cavity_kw(c) for c in cases])
+    t_load = 0.0
+    if warm is not None:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pred = warm.predict(cases)
+        for k, c in enumerate(cases):
+            warm.load(lo.members[k], c, pred[k])
+        torch.cuda.synchronize()
+        t_load = time.perf_counter() - t0
+    in_hi = np.zeros(n, bool)
+    hi.set_active(in_hi.astype(np.int32))
+    steps = np.zeros(n, np.int64)
+    switched = np.zeros(n, np.int64)
+    alive_lo = np.ones(n, bool)
+    times, walls, hist, rhist = [], [], [], []
+    lo.residual(tol=0.0)
+    hi.residual(tol=0.0)
+    t = 0
+    t0 = time.perf_counter()
+    while t < max_steps and (alive_lo.any() or (in_hi & (steps == 0)).any()):
+        lo.step(chunk)
+        hi.step(chunk)
+        t += chunk
+        res_lo, st_lo = lo.residual(tol=switch_tol)
+        res_hi, st_hi = hi.residual(tol=tol)
+        met = in_hi & (res_hi[:, 0] < tol) & (res_hi[:, 1] < tol) & (st_hi != 3)
+        steps[met & (steps == 0)] = t
+        # a moved cavity takes the 16-bit state and its residual reference
+        # (the state now), so its next FP32 residual spans one chunk
+        move = alive_lo & (st_lo == 1)
+        alive_lo &= (st_lo == 0)
+        for k in np.nonzero(move)[0]:
+            hi.members[k].copy_state_from(lo.members[k])
+            switched[k] = t
+        if move.any():
+            in_hi |= move
+            hi.set_active((in_hi & (steps == 0)).astype(np.int32))
+        nu = np.where(in_hi, hi.nusselt()[:, 0], lo.nusselt()[:, 0])
+        times.append(t)
+        hist.append(nu.copy())
+        rhist.append(np.where(in_hi[:, None], res_hi, res_lo))
+        walls.append(time.perf_counter() - t0)
+        if log and (t // chunk) % 200 == 0:
+            log(f"  t={t} switched {int((switched > 0).sum())}/{n}, met the criterion {(steps > 0).sum()}/{n}")
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    return dict(steps=steps, converged=steps > 0, switched=switched, nu=hist[-1], times=np.array(times),
+                walls=np.array(walls), nu_hist=np.array(hist), res_hist=np.array(rhist), t_load=t_load,
+                seconds=secs)
+
+
+def run_plain(cases, chunk: int = 500, tol: float = 1e-6, max_steps: int = 4_000_000):
+    """The plain way: every case alone, one after another, from a cold start
+    in FP32 with one ``Cavity`` each, each until the solver's own criterion
+    (as ``run_to_steady``).  Returns per case the records (steps, seconds
+    since that case started, hot-wall Nu) and the steps and seconds at which
+    the criterion was met (0 and the run's end if never)."""
+    import time
+    from . import Cavity
+    out = []
+    for c in cases:
+        cav = Cavity(**_cavity_kw(c))
+        cav.residual()
+        t, rec = 0, []
+        t0 = time.perf_counter()
+        met = 0
+        while t < max_steps:
+            cav.step(chunk)
+            t += chunk
+            ru, rt = cav.residual()
+            rec.append((t, time.perf_counter() - t0, cav.nusselt()[0]))
+            if ru < tol and rt < tol:
+                met = t
+                break
+        out.append(dict(records=np.array(rec), steps=met, seconds=rec[-1][1]))
+        cav.close()
+    return out
 
 
 def settle_steps(times, nu_hist, nu_ref, rtol: float = 1e-3) -> np.ndarray:
