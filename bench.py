@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--steps-per-launch", type=int, choices=(0, 1, 2), default=0,
                     help="1: one step per launch (k_step); 2: an even and an odd step per "
                          "launch (k_step2); 0: the library's choice for the workload")
+    ap.add_argument("--gemm-only", action="store_true",
+                    help="time only the warm-start network's BF16 GEMM at 4096^3 and print its line")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="summarise two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this "
                          "bench into the traffic file and exit")
@@ -160,6 +162,50 @@ def batch_measure(torch, mc, inputs, n, steps=64):
 
     out = run(2)
     out["one_step_per_launch"] = run(1)
+    return out
+
+
+def gemm_measure(torch, mc, n=4096, reps=20):
+    """The warm-start network's GEMM (mclbm_nn_gemm: FP32 operands rounded to
+    BF16, MFMA with FP32 accumulation) on an n^3 product, B as K x N and as
+    N x K, against the dense BF16 peak of 2.5 PFLOP/s; torch's BF16 matmul
+    (hipBLASLt, BF16 operands) on the same shape for context."""
+    import ctypes
+    g = torch.Generator(device="cuda").manual_seed(0)
+    A = torch.randn(n, n, device="cuda", generator=g)
+    B = torch.randn(n, n, device="cuda", generator=g)
+    C = torch.empty(n, n, device="cuda")
+    s = torch.cuda.current_stream()
+    out = {"shape": f"{n}^3", "peak_tflops": 2500.0}
+    for tb, name in ((0, "b_k_by_n"), (1, "b_n_by_k")):
+        def run():
+            rc = mc.lib().mclbm_nn_gemm(0, tb, n, n, n, 1.0, ctypes.c_void_p(A.data_ptr()), n, 0, 0,
+                                        ctypes.c_void_p(B.data_ptr()), n, 0, 0, 0.0,
+                                        ctypes.c_void_p(C.data_ptr()), n, 0, 0, 1, 1,
+                                        ctypes.c_void_p(s.cuda_stream))
+            if rc != 0:
+                raise RuntimeError(mc.lib().mclbm_last_error())
+        run()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(reps):
+            run()
+        e1.record(s)
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) / reps * 1e3
+        tf = 2.0 * n ** 3 / (us * 1e-6) / 1e12
+        out[name] = {"us": round(us, 1), "tflops": round(tf, 1), "frac": round(tf / 2500.0, 4)}
+    Ab, Bb = A.bfloat16(), B.bfloat16()
+    for _ in range(3):
+        torch.matmul(Ab, Bb)
+    torch.cuda.synchronize()
+    e0.record(s)
+    for _ in range(reps):
+        torch.matmul(Ab, Bb)
+    e1.record(s)
+    torch.cuda.synchronize()
+    out["torch_bf16_matmul_tflops"] = round(2.0 * n ** 3 / (e0.elapsed_time(e1) / reps * 1e-3) / 1e12, 1)
     return out
 
 
@@ -297,6 +343,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if a.gemm_only:
+        print(json.dumps({"gemm_bf16": gemm_measure(torch, mc)}), flush=True)
+        return
     w = inputs.WORKLOADS[a.workload]
     cfg = {k: v for k, v in w.items() if k != "seed"}
     nx, ny = cfg["nx"], cfg["ny"]
@@ -396,6 +445,7 @@ def main():
     warm = None
     if not a.no_warm_start and not a.no_secondary:
         warm = warm_start_measure()
+    gemm = None if a.no_secondary else gemm_measure(torch, mc)
     # a working set inside the 256 MB last-level cache (MALL) is served from
     # it, not from HBM: the fraction is then an effective rate, and the
     # HBM-bound figure is the hbm_streaming line
@@ -426,6 +476,7 @@ def main():
         "hbm_streaming": streaming,
         "batched_sweep": batched,
         "time_to_steady": warm,
+        "gemm_bf16": gemm,
     }
     if not a.no_cpu_baseline:
         print("# cpu baseline (FP64 oracle) ...", file=sys.stderr, flush=True)

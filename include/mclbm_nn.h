@@ -34,7 +34,13 @@ extern "C" {
  * op(B) is K x N: tb == 0 -> B is K x N (ldb >= N); tb == 1 -> N x K (ldb >= K).
  * C is M x N with row stride ldc >= N.  beta == 0 does not read C.
  * Strides may be 0 (broadcast).  M, N, K >= 1, nb1, nb2 >= 1,
- * nb1 * nb2 <= 65535 and ceil(M / 64) <= 65535 (MCLBM_EINVAL otherwise). */
+ * nb1 * nb2 <= 65535 and ceil(M / 64) <= 65535 (MCLBM_EINVAL otherwise).
+ * Products with ta == 0, M % 128 == 0, N % 256 == 0, K % 32 == 0, leading
+ * dimensions and batch strides of A and B multiples of 4, A and B 16-byte
+ * aligned and each batch entry's operands within 2^31 bytes run on a
+ * large-tile kernel (128 x 256 tiles of C, 32 x 32 x 16 MFMAs); all others
+ * on a general 64 x 64 kernel.  Both round the operands identically; the
+ * order of the FP32 accumulation differs. */
 int mclbm_nn_gemm(int32_t ta, int32_t tb, int32_t M, int32_t N, int32_t K, float alpha,
                   const float* A, int64_t lda, int64_t sa1, int64_t sa2,
                   const float* B, int64_t ldb, int64_t sb1, int64_t sb2,

@@ -96,6 +96,158 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
       }
 }
 
+// Large products: C tiles of 128 x 256 per 256-thread workgroup, op(A) = A
+// (M x K row-major), op(B) = B (K x N, TB = 0) or B^T (B is N x K, TB = 1),
+// M % 128 == 0, N % 256 == 0, K % 32 == 0, every row and batch offset
+// 16-byte aligned (checked by the host).  The four waves own 64 x 128
+// quadrants: per 16-wide K step each runs 2 x 4 MFMAs of 32 x 32 x 16
+// (FP32 accumulation).  The operands of the next 32-wide K step are loaded
+// into registers (16-byte loads) while the
+// current step computes, then rounded to BF16 and written to LDS as
+// [row][k] (a K x N B is read as 16-byte row pieces and transposed in
+// registers), so that each MFMA operand is one 16-byte LDS read: lane l holds
+// row (l mod 32), K values 8 (l div 32) .. +7.  Accumulator r of lane l is
+// row 8 (r div 4) + 4 (l div 32) + (r mod 4), column (l mod 32).
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+constexpr int GM = 128, GN = 256, GK = 32, GLK = GK + 8;
+
+__device__ __forceinline__ unsigned gemm_tile(unsigned b, unsigned nb) {
+  // workgroups are dealt round-robin to the 8 XCDs: give each XCD one
+  // contiguous run of tiles (row-major over the C tiles), so that the A row
+  // panels and B column panels it reads stay in its own L2
+  const unsigned q = nb >> 3, r = nb & 7u, k = b & 7u;
+  return k * q + (k < r ? k : r) + (b >> 3);
+}
+
+template <int TB>
+__global__ __launch_bounds__(256, 2) void k_gemm_big(GemmArgs g) {
+  __shared__ __attribute__((aligned(16))) __bf16 As[GM][GLK];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[GN][GLK];
+  const long long z = blockIdx.z;
+  const long long z1 = z / g.nb2, z2 = z % g.nb2;
+  const float* __restrict__ A = g.A + z1 * g.sa1 + z2 * g.sa2;
+  const float* __restrict__ B = g.B + z1 * g.sb1 + z2 * g.sb2;
+  float* __restrict__ C = g.C + z1 * g.sc1 + z2 * g.sc2;
+  const unsigned tiles_n = (unsigned)(g.N / GN), tiles_m = (unsigned)(g.M / GM);
+  const unsigned t = gemm_tile(blockIdx.x, gridDim.x);
+  // groups of 8 tile rows, column by column inside a group: the tiles an
+  // XCD runs at once cover a square-ish block of C, so each A row panel and
+  // each B column panel they read is shared by several of them
+  const unsigned per_group = 8u * tiles_n, first = t / per_group * 8u;
+  const unsigned gm = tiles_m - first < 8u ? tiles_m - first : 8u, w = t % per_group;
+  const int m0 = (int)(first + w % gm) * GM, n0 = (int)(w / gm) * GN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 128;
+
+  f32x16 acc[2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+  // register stage of one K step: A as 4 float4 (rows tid/8 + 32 q, K
+  // quad tid % 8); B as 8 float4 of B^T rows (TB = 1) or 32 values of one
+  // column (TB = 0).  Buffer loads: one per-lane byte offset, the row and K
+  // shifts in wave-uniform scalar offsets (the host keeps them below 2^31).
+  const __amdgpu_buffer_rsrc_t RA = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(A), 0, 0x7fffffff, 0x00020000);
+  const __amdgpu_buffer_rsrc_t RB = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(B), 0, 0x7fffffff, 0x00020000);
+  const int vra = (int)((((tid >> 3) + 0LL) * g.lda + 4 * (tid & 7)) * 4);
+  const int vrb = TB == 1 ? (int)((((tid >> 3) + 0LL) * g.ldb + 4 * (tid & 7)) * 4) : (n0 + 4 * lane) * 4;
+  float4 ra[4];
+  float rb[32];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int so = (int)(((long long)(m0 + 32 * q) * g.lda + k0) * 4);
+      ra[q] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(RA, vra, so, 0));
+    }
+    if constexpr (TB == 1) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int so = (int)(((long long)(n0 + 32 * q) * g.ldb + k0) * 4);
+        const float4 v = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(RB, vrb, so, 0));
+        rb[4 * q] = v.x; rb[4 * q + 1] = v.y; rb[4 * q + 2] = v.z; rb[4 * q + 3] = v.w;
+      }
+    } else {
+      // K x N: the wave takes K rows 8 w .. 8 w + 7, each lane 4 columns
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int so = (int)((long long)(k0 + 8 * wave + e) * g.ldb * 4);
+        const float4 v = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(RB, vrb, so, 0));
+        rb[4 * e] = v.x; rb[4 * e + 1] = v.y; rb[4 * e + 2] = v.z; rb[4 * e + 3] = v.w;
+      }
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int row = (tid >> 3) + 32 * q, kq = 4 * (tid & 7);
+      typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+      bf16x4 v = {(__bf16)ra[q].x, (__bf16)ra[q].y, (__bf16)ra[q].z, (__bf16)ra[q].w};
+      *reinterpret_cast<bf16x4*>(&As[row][kq]) = v;
+    }
+    if constexpr (TB == 1) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int row = (tid >> 3) + 32 * q, kq = 4 * (tid & 7);
+        typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+        bf16x4 v = {(__bf16)rb[4 * q], (__bf16)rb[4 * q + 1], (__bf16)rb[4 * q + 2], (__bf16)rb[4 * q + 3]};
+        *reinterpret_cast<bf16x4*>(&Bs[row][kq]) = v;
+      }
+    } else {
+      // the 8 x 4 block transposed: column 4 lane + i gets its 8 K values
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        bf16x8 v;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = (__bf16)rb[4 * e + i];
+        *reinterpret_cast<bf16x8*>(&Bs[4 * lane + i][8 * wave]) = v;
+      }
+    }
+  };
+
+  load(0);
+  store();
+  __syncthreads();
+  const int rl = lane & 31, kh = 8 * (lane >> 5);
+  for (int k0 = 0; k0 < g.K; k0 += GK) {
+    const bool more = k0 + GK < g.K;
+    if (more) load(k0 + GK);
+#pragma unroll
+    for (int ks = 0; ks < GK; ks += 16) {
+      bf16x8 a[2], b[4];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const bf16x8*>(&As[wm + 32 * i + rl][ks + kh]);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = *reinterpret_cast<const bf16x8*>(&Bs[wn + 32 * j + rl][ks + kh]);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+    if (more) {
+      store();
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int m = m0 + wm + 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int n = n0 + wn + 32 * j + (lane & 31);
+        float* c = C + (long long)m * g.ldc + n;
+        const float v = g.alpha * acc[i][j][r];
+        *c = g.beta == 0.f ? v : v + g.beta * *c;
+      }
+}
+
 __device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
 __device__ __forceinline__ float gelu_grad(float x) {
   // d/dx [x Phi(x)] = Phi(x) + x phi(x)
@@ -231,8 +383,26 @@ int mclbm_nn_gemm(int32_t ta, int32_t tb, int32_t M, int32_t N, int32_t K, float
   if ((long long)nb1 * nb2 > 65535 || (M + BM - 1) / BM > 65535)
     return nn_fail(MCLBM_EINVAL, "gemm: more than 65535 batches or row tiles");
   GemmArgs g{ta, tb, M, N, K, nb2, alpha, beta, A, lda, sa1, sa2, B, ldb, sb1, sb2, C, ldc, sc1, sc2};
+  const hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  // the large-tile kernel where the shape and alignment allow it
+  auto a16 = [](const void* p) { return reinterpret_cast<uintptr_t>(p) % 16 == 0; };
+  // (byte offsets within one batch entry below 2^31: the kernel addresses
+  // its operands with 32-bit buffer offsets)
+  const long long lim = (1LL << 31) - 64;
+  const bool big = ta == 0 && M % GM == 0 && N % GN == 0 && K % GK == 0 && lda % 4 == 0 && sa1 % 4 == 0 &&
+                   sa2 % 4 == 0 && a16(A) && (long long)(M / GM) * (N / GN) <= 0x7fffffff &&
+                   (long long)M * lda * 4 < lim && (tb ? (long long)N * ldb * 4 : (long long)K * ldb * 4) < lim &&
+                   ldb % 4 == 0 && sb1 % 4 == 0 && sb2 % 4 == 0 && a16(B);
+  if (big) {
+    dim3 grid((unsigned)((M / GM) * (N / GN)), 1, (unsigned)((long long)nb1 * nb2));
+    if (tb)
+      k_gemm_big<1><<<grid, 256, 0, st>>>(g);
+    else
+      k_gemm_big<0><<<grid, 256, 0, st>>>(g);
+    return nn_check("k_gemm_big");
+  }
   dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, (unsigned)((long long)nb1 * nb2));
-  k_gemm<<<grid, 256, 0, reinterpret_cast<hipStream_t>(stream)>>>(g);
+  k_gemm<<<grid, 256, 0, st>>>(g);
   return nn_check("k_gemm");
 }
 

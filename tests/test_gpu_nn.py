@@ -84,6 +84,59 @@ def test_gemm_matches_fp64_of_bf16_operands(ta, tb, M, N, K):
     assert np.array_equal(got[mask], C0.astype(np.float64)[mask])
 
 
+@pytest.mark.parametrize("tb", [0, 1])
+@pytest.mark.parametrize("M,N,K", [(128, 256, 32), (256, 512, 160), (384, 256, 64)])
+def test_large_tile_gemm_matches_fp64_of_bf16_operands(tb, M, N, K):
+    """Shapes that take the 128 x 256 large-tile kernel (M % 128, N % 256,
+    K % 32, 16-byte aligned rows and batch offsets), with both layouts of B,
+    two-level batches, padded leading dimensions and alpha/beta: the same
+    bound as the general kernel."""
+    rng = np.random.default_rng(M + N + K + tb)
+    nb1, nb2 = 2, 2
+    br, bc = (N, K) if tb else (K, N)
+    lda, ldb, ldc = K + 4, bc + 8, N + 3
+    sa2, sb2, sc2 = M * lda + 4, br * ldb + 12, M * ldc + 1
+    sa1, sb1, sc1 = nb2 * sa2 + 8, nb2 * sb2, nb2 * sc2
+    A = rng.normal(size=nb1 * sa1).astype(np.float32)
+    B = rng.normal(size=nb1 * sb1).astype(np.float32)
+    C0 = rng.normal(size=nb1 * sc1).astype(np.float32)
+    alpha, beta = 1.25, 0.5
+    tA, tB, tC = (torch.tensor(x, device=DEV) for x in (A, B, C0))
+    _gemm(0, tb, M, N, K, alpha, tA, lda, (sa1, sa2), tB, ldb, (sb1, sb2), beta, tC, ldc, (sc1, sc2), nb1, nb2)
+    got = tC.cpu().numpy().astype(np.float64)
+    Ab, Bb = bf16(A), bf16(B)
+    for z1 in range(nb1):
+        for z2 in range(nb2):
+            a = Ab[z1 * sa1 + z2 * sa2:][:M * lda].reshape(M, lda)[:, :K]
+            b = Bb[z1 * sb1 + z2 * sb2:][:br * ldb].reshape(br, ldb)[:, :bc]
+            opb = b.T if tb else b
+            o = z1 * sc1 + z2 * sc2
+            c0 = C0[o:o + M * ldc].astype(np.float64).reshape(M, ldc)[:, :N]
+            ref = alpha * (a @ opb) + beta * c0
+            bound = 2.0 * K * 2.0 ** -24 * abs(alpha) * (np.abs(a) @ np.abs(opb)) + 2.0 ** -23 * np.abs(ref) + 1e-30
+            g = got[o:o + M * ldc].reshape(M, ldc)[:, :N]
+            assert (np.abs(g - ref) <= bound).all(), (z1, z2, np.abs(g - ref).max())
+
+
+def test_large_gemm_sampled_rows_2048():
+    """2048^3 with the large-tile kernel: sampled rows of C (every tile row
+    position, both wave halves) against FP64 products of the BF16-rounded
+    operands."""
+    n = 2048
+    g = torch.Generator(device="cpu").manual_seed(5)
+    A = torch.randn(n, n, generator=g)
+    B = torch.randn(n, n, generator=g)
+    tA, tB = A.to(DEV), B.to(DEV)
+    tC = torch.zeros(n, n, device=DEV)
+    _gemm(0, 0, n, n, n, 1.0, tA, n, (0, 0), tB, n, (0, 0), 0.0, tC, n, (0, 0), 1, 1)
+    rows = np.array([0, 1, 31, 32, 63, 64, 100, 127, 128, 1000, 2047])
+    Ab, Bb = bf16(A.numpy()), bf16(B.numpy())
+    ref = Ab[rows] @ Bb
+    bound = 2.0 * n * 2.0 ** -24 * (np.abs(Ab[rows]) @ np.abs(Bb)) + 1e-30
+    got = tC.cpu().numpy()[rows].astype(np.float64)
+    assert (np.abs(got - ref) <= bound).all(), np.abs(got - ref).max()
+
+
 def test_gemm_beta_zero_ignores_nan_in_c():
     A = torch.ones(4, 4, device=DEV)
     C = torch.full((4, 4), float("nan"), device=DEV)
