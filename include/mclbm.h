@@ -256,6 +256,23 @@ int mclbm_copy_state(mclbm_cavity* dst, const mclbm_cavity* src);
  * count is one launch and a leftover step a single one.  Async. */
 int mclbm_step(mclbm_cavity* c, int64_t nsteps);
 
+/* Periodic Nusselt numbers on the device (the average hot-wall Nu of
+ * Section 2.d, Fig 3a, as mclbm_nusselt), with no host synchronisation per
+ * record: while every > 0, each time mclbm_step brings the step count to a
+ * multiple t of `every`, record k (k = 0, 1, ... since this call) is written
+ * on the cavity's stream to dev_ring[4 (k mod capacity) ..]: nu_hot,
+ * nu_cold, nu_hot_k and a flag (1.0 if a wall value was not finite, else
+ * 0.0).  dev_ring: 4 capacity doubles of device memory, 8-byte aligned,
+ * owned by the caller and borrowed until recording is switched off (every
+ * = 0) or the cavity is destroyed.  With two steps per launch, a pair whose
+ * odd step is a multiple of `every` runs as two single steps.  Not for
+ * batch members (MCLBM_ESTATE). */
+int mclbm_record_nusselt(mclbm_cavity* c, int32_t every, double* dev_ring, int32_t capacity);
+
+/* Records written since the last mclbm_record_nusselt call (-1 for NULL);
+ * the newest is in slot (count - 1) mod capacity. */
+int64_t mclbm_nusselt_records(const mclbm_cavity* c);
+
 /* Number of steps taken since the initial state. */
 int64_t mclbm_time(const mclbm_cavity* c);
 

@@ -31,7 +31,7 @@ DERIVED = ("nu_L", "alpha_L", "H", "dx", "dt", "G_L", "grav_L", "Ck", "R", "tau_
            "rhoc_ratio", "beta_ratio", "rho_f0", "rho_p0", "nu_f", "alpha_f")
 EXPORTED = ("mclbm_config_defaults", "mclbm_device_bytes", "mclbm_derive_constants", "mclbm_create",
             "mclbm_set_properties", "mclbm_reset", "mclbm_load_fields", "mclbm_copy_state", "mclbm_step",
-            "mclbm_time",
+            "mclbm_time", "mclbm_record_nusselt", "mclbm_nusselt_records",
             "mclbm_export_moments", "mclbm_read_moments", "mclbm_read_populations",
             "mclbm_export_populations", "mclbm_nusselt", "mclbm_residual", "mclbm_residual_noalloc",
             "mclbm_derived", "mclbm_checkpoint", "mclbm_restore", "mclbm_checkpoint_info", "mclbm_destroy", "mclbm_last_error",
@@ -105,6 +105,9 @@ def lib(load_torch: bool = True):
     L.mclbm_load_fields.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, D]
     L.mclbm_step.argtypes = [P, ctypes.c_int64]
     L.mclbm_copy_state.argtypes = [P, P]
+    L.mclbm_record_nusselt.argtypes = [P, ctypes.c_int32, P, ctypes.c_int32]
+    L.mclbm_nusselt_records.argtypes = [P]
+    L.mclbm_nusselt_records.restype = ctypes.c_int64
     L.mclbm_time.argtypes = [P]
     L.mclbm_time.restype = ctypes.c_int64
     L.mclbm_export_moments.argtypes = [P, ctypes.c_uint32, P, ctypes.c_size_t]
@@ -314,6 +317,25 @@ class Cavity:
             aff = _dptr(self._affine)
         _check(lib().mclbm_load_fields(self._h, ctypes.c_void_p(f.data_ptr()), int(f.shape[1]),
                                        int(f.shape[0]), nc, aff))
+
+    def record_nusselt(self, every: int, ring=None) -> None:
+        """mclbm_record_nusselt: every ``every`` steps the Nusselt numbers go
+        to ``ring`` (a float64 device tensor of 4 * capacity values), with
+        no host synchronisation; every = 0 switches recording off."""
+        import torch
+        if every > 0:
+            if ring is None or ring.dtype != torch.float64 or not ring.is_cuda or not ring.is_contiguous() \
+                    or ring.numel() < 4:
+                raise ValueError("ring must be a contiguous float64 device tensor of 4 * capacity values")
+            self._nu_ring = ring
+            _check(lib().mclbm_record_nusselt(self._h, int(every), ctypes.c_void_p(ring.data_ptr()),
+                                              int(ring.numel() // 4)))
+        else:
+            _check(lib().mclbm_record_nusselt(self._h, 0, None, 0))
+            self._nu_ring = None
+
+    def nusselt_records(self) -> int:
+        return int(lib().mclbm_nusselt_records(self._h))
 
     def copy_state_from(self, src: "Cavity") -> None:
         """mclbm_copy_state: continue ``src``'s run here, converting the

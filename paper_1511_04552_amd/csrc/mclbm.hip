@@ -1253,6 +1253,11 @@ struct mclbm_cavity {
   const int64_t* batch_clock;  // the owning batch's step count (members only)
   std::vector<double> host_dev_p;  // initial phi deviations (source of an async copy)
   int device = -1;     // HIP device current at creation
+  uint64_t epoch = 0;  // bumped by every change of state other than stepping
+  int32_t nu_every = 0;   // record the Nusselt numbers every nu_every steps (0: off)
+  double* nu_ring = nullptr;
+  int32_t nu_cap = 0;
+  int64_t nu_count = 0;   // records written since recording was enabled
 
   size_t pop_off(int k) const { return k ? L.off_pop2 : L.off_pop; }
   void* pop() { return base + pop_off(popsel); }
@@ -1336,6 +1341,7 @@ unsigned node_blocks(const mclbm_cavity* c) {
 }
 
 int enqueue_init(mclbm_cavity* c) {
+  ++c->epoch;
   const mclbm_config& cfg = c->cfg;
   const long long nn = (long long)cfg.nx * cfg.ny;
   const double R = c->D.v[MCLBM_D_R];
@@ -1483,6 +1489,7 @@ int export_pops(mclbm_cavity* c, int q, double* dev_out) {
 }
 
 int enqueue_load_fields(mclbm_cavity* c, const float* F, int sx, int sy, int nc, const double* affine) {
+  ++c->epoch;
   const mclbm_config& cfg = c->cfg;
   const long long nn = (long long)cfg.nx * cfg.ny;
   FieldMap M{};
@@ -1537,18 +1544,24 @@ int enqueue_load_fields(mclbm_cavity* c, const float* F, int sx, int sy, int nc,
 // their results to host memory `h` (pinned for an asynchronous copy), then,
 // after the stream has been synchronised, read them.  A batch enqueues all
 // its cavities before one synchronisation.
-int enqueue_nusselt(mclbm_cavity* c, double* h) {
+// The Nusselt numbers of the current state into device memory `out` (4
+// doubles: hot, cold, hot conductivity-weighted, non-finite flag).  Async.
+int launch_nusselt(mclbm_cavity* c, double* out) {
   const double rp = (double)c->P.rho_p_ref, R = c->D.v[MCLBM_D_R], Ck = c->D.v[MCLBM_D_CK];
-  int rc = dispatch(c, [&](auto k) {
+  return dispatch(c, [&](auto k) {
     using S = typename decltype(k)::S;
     using I = typename decltype(k)::I;
     const auto* pop = reinterpret_cast<const typename S::T*>(c->pop());
     if (c->t & 1)
-      k_nusselt<true, S, I, decltype(k)::NL><<<1, 256, 0, c->stream>>>(c->P, pop, c->d5(), rp, R, Ck, c->res());
+      k_nusselt<true, S, I, decltype(k)::NL><<<1, 256, 0, c->stream>>>(c->P, pop, c->d5(), rp, R, Ck, out);
     else
-      k_nusselt<false, S, I, decltype(k)::NL><<<1, 256, 0, c->stream>>>(c->P, pop, c->d5(), rp, R, Ck, c->res());
+      k_nusselt<false, S, I, decltype(k)::NL><<<1, 256, 0, c->stream>>>(c->P, pop, c->d5(), rp, R, Ck, out);
     return launch_check("k_nusselt");
   });
+}
+
+int enqueue_nusselt(mclbm_cavity* c, double* h) {
+  int rc = launch_nusselt(c, c->res());
   if (rc) return rc;
   HIP_TRY(hipMemcpyAsync(h, c->res(), 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   return MCLBM_OK;
@@ -1936,6 +1949,7 @@ int mclbm_copy_state(mclbm_cavity* dst, const mclbm_cavity* src) {
                          hipMemcpyDeviceToDevice, dst->stream));
   HIP_TRY(hipStreamSynchronize(dst->stream));
   dst->t = src->t;
+  ++dst->epoch;
   return MCLBM_OK;
 }
 
@@ -1943,9 +1957,13 @@ int mclbm_step(mclbm_cavity* c, int64_t nsteps) {
   if (!c) return fail(MCLBM_EINVAL, "cavity is NULL");
   if (c->in_batch) return fail(MCLBM_ESTATE, "cavity belongs to a batch: use the batch calls");
   if (nsteps < 0) return fail(MCLBM_EINVAL, "nsteps must be >= 0");
+  const int64_t every = c->nu_every;
   return dispatch(c, [&](auto k) {
     for (int64_t s = 0; s < nsteps;) {
-      if (c->two && (c->t & 1) == 0 && nsteps - s >= 2) {
+      // a pair of steps keeps its odd step in registers: where a record
+      // falls on that odd step, the pair is run as two single steps
+      const bool split = every > 0 && (c->t + 1) % every == 0;
+      if (c->two && (c->t & 1) == 0 && nsteps - s >= 2 && !split) {
         int rc = launch_step2<decltype(k)>(c);
         if (rc) return rc;
         c->t += 2;
@@ -1956,10 +1974,30 @@ int mclbm_step(mclbm_cavity* c, int64_t nsteps) {
         c->t += 1;
         s += 1;
       }
+      if (every > 0 && c->t % every == 0) {
+        int rc = launch_nusselt(c, c->nu_ring + 4 * (c->nu_count % c->nu_cap));
+        if (rc) return rc;
+        ++c->nu_count;
+      }
     }
     return (int)MCLBM_OK;
   });
 }
+
+int mclbm_record_nusselt(mclbm_cavity* c, int32_t every, double* dev_ring, int32_t capacity) {
+  if (!c) return fail(MCLBM_EINVAL, "cavity is NULL");
+  if (c->in_batch) return fail(MCLBM_ESTATE, "cavity belongs to a batch: use the batch calls");
+  if (every < 0) return fail(MCLBM_EINVAL, "record_nusselt: every must be >= 0");
+  if (every > 0 && (!dev_ring || capacity < 1 || reinterpret_cast<uintptr_t>(dev_ring) % alignof(double) != 0))
+    return fail(MCLBM_EINVAL, "record_nusselt: needs an aligned device ring of capacity >= 1");
+  c->nu_every = every;
+  c->nu_ring = every > 0 ? dev_ring : nullptr;
+  c->nu_cap = every > 0 ? capacity : 0;
+  c->nu_count = 0;
+  return MCLBM_OK;
+}
+
+int64_t mclbm_nusselt_records(const mclbm_cavity* c) { return c ? c->nu_count : -1; }
 
 int64_t mclbm_time(const mclbm_cavity* c) { return c ? c->t : -1; }
 
@@ -2150,6 +2188,7 @@ int mclbm_restore(mclbm_cavity* c, const char* path) {
   for (size_t k = 0; k < secs.size(); ++k)
     if (secs[k].bytes) HIP_TRY(hipMemcpy(c->base + secs[k].off, data[k].data(), secs[k].bytes, hipMemcpyHostToDevice));
   c->t = t;
+  ++c->epoch;
   return MCLBM_OK;
 }
 
@@ -2244,6 +2283,11 @@ struct mclbm_batch {
   int2* d_rtiles() { return reinterpret_cast<int2*>(base + off_rtiles); }
   double* d_rout() { return reinterpret_cast<double*>(base + off_rout); }
   double* h_inactive(int k) { return h_red + 16 * (size_t)n + 16 * (size_t)k; }
+  // the Nusselt numbers of a dropped cavity in h_inactive(k) were computed
+  // at step nu_t[k] of state epoch nu_epoch[k] (-1: none); a dropped cavity
+  // is not stepped, so they stay valid until either changes
+  std::vector<int64_t> nu_t;
+  std::vector<uint64_t> nu_epoch;
 };
 
 namespace {
@@ -2772,7 +2816,8 @@ int mclbm_batch_residual(mclbm_batch* b, double tol, double* out, int32_t* statu
 int mclbm_batch_nusselt(mclbm_batch* b, double* out) {
   if (!b || !out) return fail(MCLBM_EINVAL, "NULL argument");
   // the active cavities in one launch and one copy; the inactive ones
-  // (frozen, each at its own step parity) one by one; one synchronisation
+  // (frozen, each at its own step parity) one by one, and only when their
+  // state changed since their last reduction; one synchronisation
   if (b->nr > 0) {
     const bool odd = (b->t & 1) != 0;
     int rc = dispatch_kinds(b->storage, b->idx32, b->nt, [&](auto k) {
@@ -2790,10 +2835,19 @@ int mclbm_batch_nusselt(mclbm_batch* b, double* out) {
     HIP_TRY(hipMemcpyAsync(b->h_red, b->d_rout(), (size_t)16 * b->nr * sizeof(double), hipMemcpyDeviceToHost,
                            b->stream));
   }
+  if ((int)b->nu_t.size() != b->n) {
+    b->nu_t.assign(b->n, -1);
+    b->nu_epoch.assign(b->n, 0);
+  }
   for (int k = 0; k < b->n; ++k)
-    if (!b->active[k]) {
+    if (!b->active[k] && (b->nu_t[k] != b->cav[k].t || b->nu_epoch[k] != b->cav[k].epoch)) {
       const int rc = enqueue_nusselt(&b->cav[k], b->h_inactive(k));
-      if (rc) return rc;
+      if (rc) {
+        b->nu_t[k] = -1;
+        return rc;
+      }
+      b->nu_t[k] = b->cav[k].t;
+      b->nu_epoch[k] = b->cav[k].epoch;
     }
   HIP_TRY(hipStreamSynchronize(b->stream));
   for (int j = 0; j < b->nr; ++j) {

@@ -669,7 +669,7 @@ def main(argv=None) -> int:
     ws = None
     if a.combine:
         runs = [dict(np.load(f)) for f in a.combine]
-        cold, warm = ({k: (r[k].item() if r[k].ndim == 0 else r[k]) for k in RUN_KEYS} for r in runs)
+        cold, warm = ({k: (r[k].item() if r[k].ndim == 0 else r[k]) for k in RUN_KEYS if k in r} for r in runs)
     else:
         if a.load_model:
             st = dict(np.load(a.load_model))
@@ -717,7 +717,10 @@ def main(argv=None) -> int:
         if a.save_run:
             made = cold if cold is not None else warm
             if made is not None:
-                np.savez(a.save_run, **{k: np.asarray(made[k]) for k in RUN_KEYS})
+                # the final fields only serve an evaluation at the training
+                # resolution; large evaluations leave them out of the file
+                keep = [k for k in RUN_KEYS if k != "fields" or np.asarray(made[k]).nbytes <= (32 << 20)]
+                np.savez(a.save_run, **{k: np.asarray(made[k]) for k in keep})
         if cold is None or warm is None:
             return 0
     done = cold["converged"] & warm["converged"]
@@ -741,7 +744,7 @@ def main(argv=None) -> int:
                  "seconds_to_settle_warm": float(sw.max() * per_step + warm["t_load"]),
                  "seconds_load": warm["t_load"]},
     }
-    if a.eval_side == S and ws is not None:
+    if a.eval_side == S and ws is not None and "fields" in cold:
         pred = ws.predict(test).cpu().numpy() * ws.std + ws.mean
         err = np.sqrt(((pred - cold["fields"]) ** 2).reshape(-1, NCH).mean(0)) / cold["fields"].reshape(-1, NCH).std(0)
         rep["eval"]["rel_rms_error"] = dict(zip(("u", "v", "theta", "phi", "rho_f"), err.tolist()))

@@ -119,3 +119,34 @@ def test_members_cannot_be_stepped_directly():
         b.members[0].step(1)
     L = mc.lib()
     assert L.mclbm_step(b.members[0]._h, 1) == mc.ESTATE
+
+
+def test_batch_nusselt_of_dropped_cavities_follows_their_state():
+    """A dropped cavity's Nusselt numbers are reduced once and reused while
+    its state is unchanged; a change of that state (a copied state, or
+    rejoining and stepping) shows in the next batch call, which always
+    equals the cavity's own call."""
+    xis = _xis(CFGS)
+    b = mc.Batch(CFGS, xis=xis)
+    b.step(100)
+    b.set_active([1, 0, 1, 1, 1])
+    first = b.nusselt()
+    b.step(50)
+    second = b.nusselt()
+    assert np.array_equal(first[1], second[1])
+    assert np.array_equal(second[1], np.array(b.members[1].nusselt()))
+    assert not np.array_equal(first[0], second[0])
+    # a new state for the dropped member
+    other = mc.Cavity(xi=xis[1], **CFGS[1])
+    other.step(40)
+    b.members[1].copy_state_from(other)
+    third = b.nusselt()
+    assert np.array_equal(third[1], np.array(other.nusselt()))
+    assert not np.array_equal(third[1], second[1])
+    # rejoin (even step counts on both sides), step, drop again
+    b.set_active([1, 1, 1, 1, 1])
+    b.step(10)
+    b.set_active([1, 0, 1, 1, 1])
+    fourth = b.nusselt()
+    assert np.array_equal(fourth[1], np.array(b.members[1].nusselt()))
+    assert not np.array_equal(fourth[1], third[1])

@@ -7,6 +7,8 @@ deviation to ~2.4e-4 of itself, BF16 (8-bit mantissa) to ~2e-3.  Measured on
 the 64^2 reference cavity after 1000 steps: FP16 ~1.4e-3 on the moments and
 2e-3 on Nu; BF16 ~3.6e-2 and 1.1e-1.  The bounds below sit at about 3x those.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -76,3 +78,61 @@ def test_reduced_precision_deterministic():
     a.step(101)
     b.step(101)
     assert np.array_equal(a.populations(), b.populations())
+
+
+GOLDEN_256 = os.path.join(os.path.dirname(__file__), "golden", "cavity256_ra1e6_steady.txt")
+MOMENTS = ("rho_f", "ux_f", "uy_f", "phi", "ux_p", "uy_p", "theta", "ux_ns", "uy_ns")
+
+
+def _golden_256():
+    rows, scales, samples = [], {}, {}
+    for line in open(GOLDEN_256):
+        if line.startswith("#") or not line.strip():
+            continue
+        p = line.split()
+        if p[0] == "scale":
+            scales[p[1]] = tuple(float(v) for v in p[2:5])
+        elif p[0] in MOMENTS:
+            samples.setdefault(p[0], []).append((int(p[1]), int(p[2]), float(p[3])))
+        else:
+            rows.append([float(v) for v in p])
+    return np.array(rows), scales, samples
+
+
+# (moments, Nu) bounds of the 256^2 comparison near steady state, about 3x
+# the errors measured (stated in the test output)
+BOUNDS_256 = {mc.FP32S: (1e-5, 1e-4), mc.FP16S: (3e-2, 1e-2), mc.BF16S: (1.0, 0.3)}
+
+
+@pytest.mark.parametrize("storage", [mc.FP32S, mc.FP16S, mc.BF16S])
+def test_storage_types_against_oracle_near_steady_state_256(storage):
+    """The reduced-precision workload (Ra 1e6, 4 % alumina, 30 nm, all
+    forces) at 256^2 after the oracle's long run (``golden/
+    cavity256_ra1e6_steady.txt``, written by ``golden/make_cavity256_steady.py``
+    from the oracle alone): FP32, FP16 and BF16 storage against the FP64
+    state at the same step count, per moment at 100 sampled nodes (relative
+    to the field's scale over the whole cavity, deviation scales for rho_f
+    and phi as in the parity tests) and for the hot-wall Nu."""
+    rows, scales, samples = _golden_256()
+    steps = int(rows[-1, 0])
+    cfg = dict(nx=256, ny=256, Ra=1e6, Pr=6.2, phi0=0.04, dp_nm=30.0, tau_f=-1.0)
+    c = mc.Cavity(xi=inputs.phi_perturbation(4, 256, 256), storage=storage, **cfg)
+    done = 0
+    while done < steps:
+        k = min(200000, steps - done)
+        c.step(k)
+        done += k
+        print("storage", storage, "at", done, flush=True)
+    m = c.moments(MOMENTS)
+    err = {}
+    for name in MOMENTS:
+        mean, dev, mag = scales[name]
+        scale = max(dev, 1e-4 * mag) if name in ("rho_f", "phi") else mag
+        err[name] = max(abs(m[name][y, x] - v) for x, y, v in samples[name]) / scale
+    nu = c.nusselt()[0]
+    nu_err = abs(nu - rows[-1, 1]) / rows[-1, 1]
+    print("storage", storage, "after", steps, "steps:", {k: f"{v:.1e}" for k, v in err.items()},
+          f"Nu {nu:.8f} vs {rows[-1, 1]:.8f} ({nu_err:.1e})", flush=True)
+    mb, nb = BOUNDS_256[storage]
+    assert max(err.values()) <= mb, err
+    assert nu_err <= nb, nu_err
