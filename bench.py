@@ -165,6 +165,38 @@ def batch_measure(torch, mc, inputs, n, steps=64):
     return out
 
 
+def small_batch_measure(torch, mc, inputs, steps=512):
+    """Batches of many small cavities (Ra log-uniform in [1e3, 1e5], phi in
+    [0, 5 %], d_p in [20, 100] nm, automatic tau_f): microseconds per step of
+    the whole batch over the tiles (one launch per step, replayed from a
+    captured graph) and with one workgroup per cavity (up to 256 steps per
+    launch), and the schedule the library picks by default."""
+    import numpy as np
+    out = []
+    for n, side in ((16, 64), (128, 32), (256, 32), (256, 64)):
+        rng = np.random.default_rng(17)
+        cfgs = [dict(nx=side, ny=side, Ra=float(10 ** rng.uniform(3, 5)), phi0=float(rng.uniform(0, 0.05)),
+                     dp_nm=float(rng.uniform(20, 100)), tau_f=-1.0) for _ in range(n)]
+        xis = [inputs.phi_perturbation(40 + k, side, side) for k in range(n)]
+        b = mc.Batch(cfgs, xis=xis)
+        row = {"workload": f"{n} x {side}^2", "default": "per_cavity" if b.per_cavity else "tiles"}
+        for name, on in (("tiles_us_per_step", False), ("per_cavity_us_per_step", True)):
+            b.per_cavity = on
+            b.step(64)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(b.stream)
+            b.step(steps)
+            e1.record(b.stream)
+            torch.cuda.synchronize()
+            row[name] = round(e0.elapsed_time(e1) * 1e3 / steps, 2)
+        out.append(row)
+        b.close()
+        del b
+        torch.cuda.empty_cache()
+    return out
+
+
 def gemm_measure(torch, mc, n=4096, reps=20):
     """The warm-start network's GEMM (mclbm_nn_gemm: FP32 operands rounded to
     BF16, MFMA with FP32 accumulation) on an n^3 product, B as K x N and as
@@ -445,6 +477,7 @@ def main():
     warm = None
     if not a.no_warm_start and not a.no_secondary:
         warm = warm_start_measure()
+    small = None if a.no_secondary else small_batch_measure(torch, mc, inputs)
     gemm = None if a.no_secondary else gemm_measure(torch, mc)
     # a working set inside the 256 MB last-level cache (MALL) is served from
     # it, not from HBM: the fraction is then an effective rate, and the
@@ -475,6 +508,7 @@ def main():
         "larger_than_llc": secondary,
         "hbm_streaming": streaming,
         "batched_sweep": batched,
+        "small_batches": small,
         "time_to_steady": warm,
         "gemm_bf16": gemm,
     }

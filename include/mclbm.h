@@ -377,7 +377,8 @@ const char* mclbm_last_error(void);
  * sweeps over Ra, phi and d_p of Section 3) in one device buffer.  One
  * kernel launch per time step updates every active cavity (one workgroup
  * per tile of every cavity); the step loop is replayed from a captured HIP
- * graph.  Every cavity gives
+ * graph.  Many small cavities step instead one workgroup per cavity for up
+ * to 256 steps per launch (mclbm_batch_set_per_cavity).  Every cavity gives
  * bitwise the same result as the same cavity created alone.  All cavities of
  * a batch share the storage type; each keeps its own workgroup shape.
  * With two steps per launch (steps_per_launch in mclbm_config), each launch
@@ -425,9 +426,26 @@ int mclbm_batch_nusselt(mclbm_batch* b, double* out);
  * equal nx, ny) time `steps` steps, that class alone, with each candidate
  * workgroup shape (256x1, 128x2, 64x4, 32x8), or with two steps per launch
  * each band height of the two-step tiles (3, 4, 6, 8 rows); keep the
- * fastest per class, then restart every cavity from its initial state.
+ * fastest per class.  Where the batch may step one workgroup per cavity
+ * (mclbm_batch_set_per_cavity), time that and the tiles on the whole batch
+ * and keep the faster.  Then restart every cavity from its initial state.
  * Neither changes any result.  Sync. */
 int mclbm_batch_autotune(mclbm_batch* b, int32_t steps);
+
+/* Schedule of many small cavities: with on = 1, every launch runs up to 256
+ * steps (an even number, from an even step) of all active cavities, one
+ * 1024-thread workgroup per cavity with a workgroup barrier between steps;
+ * on = 0 returns to one launch per step over the tiles.  Results are
+ * bitwise those of the tiles.  Needs one step per launch and cavities of at
+ * most 128^2 nodes (MCLBM_EINVAL otherwise).  Default: on for batches of
+ * cavities of at most 64^2 nodes that number at least
+ * max(128, 256 * nodes / 64^2) of the largest; mclbm_batch_autotune times
+ * both on the whole batch and keeps the faster.  Sync. */
+int mclbm_batch_set_per_cavity(mclbm_batch* b, int32_t on);
+
+/* 1 when the batch steps one workgroup per cavity, 0 over tiles, -1 for a
+ * NULL batch. */
+int32_t mclbm_batch_per_cavity(const mclbm_batch* b);
 
 /* Tile of cavity idx: the workgroup shape (bx, by), or with two steps per
  * launch the strip width and band height (62, rows). */

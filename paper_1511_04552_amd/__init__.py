@@ -40,6 +40,7 @@ EXPORTED = ("mclbm_config_defaults", "mclbm_device_bytes", "mclbm_derive_constan
             "mclbm_batch_device_bytes", "mclbm_batch_create", "mclbm_batch_step",
             "mclbm_batch_set_graph_steps", "mclbm_batch_set_active", "mclbm_batch_residual",
             "mclbm_batch_nusselt", "mclbm_batch_autotune", "mclbm_batch_tile_shape",
+            "mclbm_batch_set_per_cavity", "mclbm_batch_per_cavity",
             "mclbm_batch_reset", "mclbm_batch_size", "mclbm_batch_time", "mclbm_batch_cavity",
             "mclbm_batch_destroy",
             "mclbm_nn_gemm", "mclbm_nn_bias_act", "mclbm_nn_act_backward", "mclbm_nn_colsum_scratch",
@@ -135,6 +136,9 @@ def lib(load_torch: bool = True):
     L.mclbm_batch_nusselt.argtypes = [P, D]
     L.mclbm_batch_autotune.argtypes = [P, ctypes.c_int32]
     L.mclbm_batch_tile_shape.argtypes = [P, ctypes.c_int32, I32P, I32P]
+    L.mclbm_batch_set_per_cavity.argtypes = [P, ctypes.c_int32]
+    L.mclbm_batch_per_cavity.argtypes = [P]
+    L.mclbm_batch_per_cavity.restype = ctypes.c_int32
     L.mclbm_batch_reset.argtypes = [P]
     L.mclbm_batch_size.argtypes = [P]
     L.mclbm_batch_size.restype = ctypes.c_int32
@@ -474,6 +478,16 @@ class Batch:
 
     def set_graph_steps(self, steps: int) -> None:
         _check(lib().mclbm_batch_set_graph_steps(self._h, int(steps)))
+
+    @property
+    def per_cavity(self) -> bool:
+        """True when the batch steps one workgroup per cavity, many steps per
+        launch (``mclbm_batch_set_per_cavity``); False over tiles."""
+        return lib().mclbm_batch_per_cavity(self._h) == 1
+
+    @per_cavity.setter
+    def per_cavity(self, on: bool) -> None:
+        _check(lib().mclbm_batch_set_per_cavity(self._h, 1 if on else 0))
 
     def set_active(self, active) -> None:
         a = (ctypes.c_int32 * self.n)(*[1 if v else 0 for v in active])

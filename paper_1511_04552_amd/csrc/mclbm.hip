@@ -12,6 +12,8 @@
 //               one launch, between two population copies (large cavities)
 //   k_step_batch  one launch per step over a batch of uneven cavities
 //   k_step2_batch two steps per launch over such a batch (tiles of k_step2)
+//   k_step_cavity many steps per launch over a batch of small cavities, one
+//               workgroup per cavity
 //   k_nusselt   FP64 wall-Nusselt reduction
 //   k_residual  FP64 relative change of u_ns and theta (steady-state test)
 //   k_*_batch   the same reductions for every active cavity of a batch
@@ -27,6 +29,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "mclbm.h"
@@ -444,6 +447,31 @@ __global__ __launch_bounds__(64) void k_step2_batch(const CavDesc* __restrict__ 
   using T = typename S::T;
   step2_tile<S>(C.P, reinterpret_cast<const T*>(C.pop[flip]), reinterpret_cast<T*>(C.pop[flip ^ 1]),
                 C.d2[1 ^ flip], C.d2[flip], tr.y % C.strips2, tr.y / C.strips2, C.band2);
+}
+
+// Many small cavities: one 1024-thread workgroup owns a whole cavity (at
+// most kPerCavNodes nodes) and runs `steps` steps of it, an even number from
+// an even step, with a workgroup barrier between the steps.  The launch
+// overhead of one launch per step goes, and the cavity's arrays stay in the
+// caches of one XCD; a cavity then has one compute unit, so this pays only
+// with about as many cavities as compute units.  list: the active
+// cavities.  The node updates are those of k_step_batch (bitwise equal).
+constexpr int kPerCavThreads = 1024;
+constexpr int kPerCavNodes = 128 * 128;
+template <class SE, class SO, class I>
+__global__ __launch_bounds__(kPerCavThreads) void k_step_cavity(const CavDesc* __restrict__ cavs,
+                                                                const int* __restrict__ list, int steps) {
+  const CavDesc& C = cavs[list[blockIdx.x]];
+  auto* pop = reinterpret_cast<typename SE::T*>(C.pop[0]);  // one copy: no second role
+  const int nx = C.P.nx, nn = C.P.nx * C.P.ny;
+  for (int s = 0; s < steps; s += 2) {
+    for (int n = (int)threadIdx.x; n < nn; n += kPerCavThreads)
+      step_node<false, SE, I>(C.P, pop, C.d2[1], C.d2[0], C.d5, n % nx, n / nx);
+    __syncthreads();
+    for (int n = (int)threadIdx.x; n < nn; n += kPerCavThreads)
+      step_node<true, SO, I>(C.P, pop, C.d2[0], C.d2[1], C.d5, n % nx, n / nx);
+    __syncthreads();
+  }
 }
 
 // Block-wide FP64 sum; wave64 shuffles then one LDS slot per wave.
@@ -2261,6 +2289,7 @@ struct mclbm_batch {
   std::vector<int2> host_tiles, host_tiles2;
   int ntiles = 0, ntiles2 = 0;
   bool two = false;  // two steps per launch (k_step2_batch) from even steps
+  bool percav = false;  // one workgroup per cavity for many steps (k_step_cavity)
   // pinned host results of the reductions: 16 doubles per listed active
   // cavity, then 16 per cavity for the inactive ones' Nusselt numbers
   double* h_red = nullptr;
@@ -2512,6 +2541,28 @@ int batch_launch2(mclbm_batch* b, hipStream_t s, int flip) {
   }
 }
 
+// One workgroup per active cavity, `steps` (even) steps per launch.
+constexpr int64_t kPerCavChunk = 256;  // steps per launch
+
+bool percav_eligible(const mclbm_batch* b) {
+  if (b->two || !b->idx32 || b->nt) return false;
+  for (int k = 0; k < b->n; ++k)
+    if ((long long)b->cav[k].cfg.nx * b->cav[k].cfg.ny > kPerCavNodes) return false;
+  return true;
+}
+
+// The default schedule: one workgroup per cavity when the cavities are
+// small (at most 64^2) and about as many as compute units or more (measured
+// faster from 128 cavities of 32^2 and 256 of 64^2; slower with 16 of 32^2,
+// 64 of 64^2 or 16 of 128^2).
+bool percav_default(const mclbm_batch* b) {
+  if (!percav_eligible(b)) return false;
+  long long most = 0;
+  for (int k = 0; k < b->n; ++k) most = std::max(most, (long long)b->cav[k].cfg.nx * b->cav[k].cfg.ny);
+  if (most > 64 * 64) return false;
+  return (long long)b->n >= std::max(128LL, 256LL * most / (64 * 64));
+}
+
 void batch_advance(mclbm_batch* b, int64_t k) {
   b->t += k;
   for (int c = 0; c < b->n; ++c)
@@ -2550,6 +2601,26 @@ int batch_direct_step2(mclbm_batch* b) {
   });
   if (rc) return rc;
   batch_advance2(b, 1);
+  return MCLBM_OK;
+}
+
+// `steps` (even) steps of every active cavity from an even step, one
+// workgroup per cavity.
+int batch_cavity_steps(mclbm_batch* b, int64_t steps) {
+  if (b->nr > 0) {
+    int rc = dispatch_kinds(b->storage, b->idx32, b->nt, [&](auto k) {
+      using K = decltype(k);
+      if constexpr (sizeof(typename K::I) == 4 && std::is_same_v<typename K::SE, typename K::S>) {
+        k_step_cavity<typename K::SE, typename K::SO, typename K::I>
+            <<<b->nr, kPerCavThreads, 0, b->stream>>>(b->d_desc(), b->d_rlist(), (int)steps);
+        return launch_check("k_step_cavity");
+      } else {
+        return fail(MCLBM_EUNSUPPORTED, "one workgroup per cavity: small cavities only");
+      }
+    });
+    if (rc) return rc;
+  }
+  batch_advance(b, steps);
   return MCLBM_OK;
 }
 
@@ -2691,6 +2762,7 @@ int mclbm_batch_create(const mclbm_config* cfgs, int32_t n, const double* const*
   (void)ncu;
   b->grid = (unsigned)B.tile_cap;
   b->grid2 = (unsigned)B.tile_cap2;
+  b->percav = percav_default(b);
   hipError_t e = hipHostMalloc((void**)&b->h_red, (size_t)32 * n * sizeof(double), hipHostMallocDefault);
   if (e != hipSuccess) {
     b->h_red = nullptr;
@@ -2721,7 +2793,12 @@ int mclbm_batch_step(mclbm_batch* b, int64_t nsteps) {
   for (int k = 0; k < b->n; ++k) any = any || b->active[k];
   if (!any) return MCLBM_OK;
   while (nsteps > 0) {
-    if (b->graph_steps > 0 && nsteps >= b->graph_steps && (b->t & 1) == 0) {
+    if (b->percav && nsteps >= 2 && (b->t & 1) == 0) {
+      const int64_t k = std::min<int64_t>(nsteps & ~int64_t(1), kPerCavChunk);
+      int rc = batch_cavity_steps(b, k);
+      if (rc) return rc;
+      nsteps -= k;
+    } else if (b->graph_steps > 0 && nsteps >= b->graph_steps && (b->t & 1) == 0) {
       if (b->flip) {
         // the graph was captured for descriptors written with flip 0
         int rc = upload_tables(b);
@@ -2749,6 +2826,18 @@ int mclbm_batch_step(mclbm_batch* b, int64_t nsteps) {
   }
   return MCLBM_OK;
 }
+
+int mclbm_batch_set_per_cavity(mclbm_batch* b, int32_t on) {
+  if (!b) return fail(MCLBM_EINVAL, "batch is NULL");
+  if (on && !percav_eligible(b))
+    return fail(MCLBM_EINVAL, "one workgroup per cavity needs one step per launch and cavities of at most " +
+                                  std::to_string(kPerCavNodes) + " nodes");
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  b->percav = on != 0;
+  return MCLBM_OK;
+}
+
+int32_t mclbm_batch_per_cavity(const mclbm_batch* b) { return b ? (b->percav ? 1 : 0) : -1; }
 
 int mclbm_batch_set_graph_steps(mclbm_batch* b, int32_t steps) {
   if (!b) return fail(MCLBM_EINVAL, "batch is NULL");
@@ -2944,10 +3033,34 @@ int mclbm_batch_autotune(mclbm_batch* b, int32_t steps) {
       if (c->cfg.nx == cl.first && c->cfg.ny == cl.second) apply(c, best_c);
     }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   b->graph_steps = saved_graph;
   drop_graph(b);
+  // then the schedule, every cavity active: the tiles (replayed from the
+  // graph) or one workgroup per cavity
+  if (!rc && percav_eligible(b)) {
+    rc = batch_reset_all(b);
+    const int64_t n2 = std::max<int64_t>(std::max<int64_t>(2, steps & ~1), b->graph_steps);
+    float ms[2] = {0.0f, 0.0f};
+    for (int pc = 0; pc < 2 && !rc; ++pc) {
+      b->percav = pc == 1;
+      rc = mclbm_batch_step(b, n2);  // warm-up (and graph capture)
+      if (rc) break;
+      HIP_TRY(hipEventRecord(e0, b->stream));
+      rc = mclbm_batch_step(b, n2);
+      HIP_TRY(hipEventRecord(e1, b->stream));
+      if (rc) break;
+      hipError_t he = hipEventSynchronize(e1);
+      if (he != hipSuccess) {
+        rc = hip_fail(he, "hipEventSynchronize");
+        break;
+      }
+      HIP_TRY(hipEventElapsedTime(&ms[pc], e0, e1));
+    }
+    if (!rc) b->percav = ms[1] < ms[0];
+    drop_graph(b);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (rc) return rc;
   return batch_reset_all(b);
 }

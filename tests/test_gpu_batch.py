@@ -1,5 +1,5 @@
-"""Batched sweeps of uneven cavities (one persistent launch per step, replayed
-from a captured HIP graph) against single-cavity runs and the oracle."""
+"""Batched sweeps of uneven cavities (one launch per step over the tiles of
+every cavity, replayed from a captured HIP graph) against single-cavity runs and the oracle."""
 import numpy as np
 import pytest
 
