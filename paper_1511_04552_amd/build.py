@@ -15,6 +15,10 @@ FLAGS = [
     "--offload-arch=gfx950",
     # packed FP32 instructions are not emitted (v_pk_* FP32 forms)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # multiply-adds are fused only within one expression, so a kernel's
+    # arithmetic does not depend on the code it is inlined into: every
+    # kernel that runs the node update gives the same bits
+    "-ffp-contract=on",
     "-Wall", "-Wno-unused-function",
 ]
 

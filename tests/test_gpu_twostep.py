@@ -86,18 +86,22 @@ def test_two_steps_per_launch_match_oracle(cfg, band):
         assert abs(a - b) <= 1e-4 * max(abs(b), 1.0)
 
 
-def test_two_steps_per_launch_close_to_single_steps():
-    """Both schedules run the same node arithmetic on the same values (FP32
-    storage is exact), so they agree to the last few bits."""
-    cfg = dict(nx=130, ny=67, Ra=1e5, phi0=0.03, dp_nm=40.0)
-    xi = inputs.phi_perturbation(142, cfg["nx"], cfg["ny"])
+@pytest.mark.parametrize("shape", [(130, 67), (300, 200), (62, 9)])
+def test_two_steps_per_launch_bitwise_equal_to_single_steps(shape):
+    """Both schedules run the same node arithmetic on the same values: FP32
+    storage holds the intermediate state exactly, and multiply-adds are
+    fused per source expression, so the kernels give the same bits after
+    every launch (odd counts end with a one-step launch)."""
+    nx, ny = shape
+    cfg = dict(nx=nx, ny=ny, Ra=1e5, phi0=0.03, dp_nm=40.0)
+    xi = inputs.phi_perturbation(142, nx, ny)
     one = mc.Cavity(xi=xi, steps_per_launch=1, **cfg)
     two = mc.Cavity(xi=xi, steps_per_launch=2, **cfg)
-    one.step(600)
-    two.step(600)
-    w = _worst(two.moments(), one.moments())
-    print(f"two-step vs one-step {w:.2e}")
-    assert w <= 1e-6
+    for n in (2, 3, 40, 600):
+        one.step(n - one.time)
+        two.step(n - two.time)
+        assert np.array_equal(two.populations(), one.populations()), (shape, n)
+    assert one.nusselt() == two.nusselt()
     assert np.isfinite(two.populations()).all()
 
 
@@ -144,8 +148,7 @@ def test_two_step_target_is_fully_written(cfg, band):
 def test_checkpoints_cross_schedules(tmp_path):
     """A checkpoint holds the state, not the schedule: written by a two-step
     cavity (at an odd and at an even step) it resumes bitwise like the run
-    that was not interrupted (same launches) and within rounding in a
-    one-step cavity."""
+    that was not interrupted, in either schedule."""
     cfg = dict(nx=37, ny=29, Ra=5e4, phi0=0.03, dp_nm=40.0)
     xi = inputs.phi_perturbation(145, cfg["nx"], cfg["ny"])
     for at in (333, 334):
@@ -164,7 +167,7 @@ def test_checkpoints_cross_schedules(tmp_path):
         single = mc.Cavity(xi=xi, steps_per_launch=1, **cfg)
         single.restore(path)
         single.step(700 - at)
-        assert _worst(single.moments(), full.moments()) <= 1e-6
+        assert np.array_equal(single.populations(), full.populations())
 
 
 def test_two_steps_per_launch_rejected_where_unsupported():
@@ -233,5 +236,5 @@ def test_reset_set_properties_and_load_fields_with_two_steps():
         d.step(7)
         d.load_fields(F, affine=aff)
         d.step(300)
-        runs.append(d.moments())
-    assert _worst(runs[1], runs[0]) <= 1e-6
+        runs.append(d.populations())
+    assert np.array_equal(runs[1], runs[0])
