@@ -51,6 +51,9 @@ def parse():
                          "launch (k_step2); 0: the library's choice for the workload")
     ap.add_argument("--gemm-only", action="store_true",
                     help="time only the warm-start network's BF16 GEMM at 4096^3 and print its line")
+    ap.add_argument("--small-batches-only", action="store_true",
+                    help="time only the batches of many small cavities (tiles against one workgroup per "
+                         "cavity) and print their line")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="summarise two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this "
                          "bench into the traffic file and exit")
@@ -377,6 +380,10 @@ def main():
         sys.exit(1)
     if a.gemm_only:
         print(json.dumps({"gemm_bf16": gemm_measure(torch, mc)}), flush=True)
+        return
+    if a.small_batches_only:
+        from paper_1511_04552_amd import inputs
+        print(json.dumps({"small_batches": small_batch_measure(torch, mc, inputs)}), flush=True)
         return
     w = inputs.WORKLOADS[a.workload]
     cfg = {k: v for k, v in w.items() if k != "seed"}

@@ -115,3 +115,17 @@ def test_autotune_chooses_a_schedule_and_keeps_results():
     ref.step(70)
     _equal(b, ref, range(0, 128, 9))
     print("autotuned schedule for 128 x 32^2: one workgroup per cavity" if chosen else "tiles", flush=True)
+
+
+@pytest.mark.parametrize("storage", [mc.FP16S, mc.BF16S])
+def test_per_cavity_16bit_storage_equals_tiles(storage):
+    cfgs, xis = _small(9, seed=13)
+    cfgs = [dict(c, storage=storage) for c in cfgs]
+    a = mc.Batch(cfgs, xis=xis)
+    b = mc.Batch(cfgs, xis=xis)
+    a.per_cavity = True
+    b.per_cavity = False
+    for n in (260, 5):
+        a.step(n)
+        b.step(n)
+        _equal(a, b, range(len(cfgs)))
