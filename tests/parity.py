@@ -70,6 +70,38 @@ def assert_nusselt(a, b, tol=NU_TOL, label=""):
         assert abs(x - y) <= tol * abs(y), (label, a, b)
 
 
+def load_sampled(path):
+    """An oracle reference written by the golden scripts: the step count,
+    the Nusselt numbers, each field's (mean, largest deviation from the mean,
+    largest magnitude) over the whole cavity, and the field values at
+    sampled nodes as {field: [(x, y, value), ...]}."""
+    g = {"scales": {}, "samples": {}}
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        p = line.split()
+        if p[0] == "steps":
+            g["steps"] = int(p[1])
+        elif p[0] == "nusselt":
+            g["nu"] = tuple(float(v) for v in p[1:4])
+        elif p[0] == "scale":
+            g["scales"][p[1]] = tuple(float(v) for v in p[2:5])
+        else:
+            g["samples"].setdefault(p[0], []).append((int(p[1]), int(p[2]), float(p[3])))
+    return g
+
+
+def sampled_errors(m, g):
+    """Per field: max |gpu - oracle| over the sampled nodes, relative to the
+    oracle field's scale over the whole cavity (as field_scale)."""
+    err = {}
+    for f, samples in g["samples"].items():
+        mean, dev, mag = g["scales"][f]
+        scale = max(dev, DEVIATION_FLOOR * mag) if f in DEVIATION_FIELDS else mag
+        err[f] = max(abs(m[f][y, x] - v) for x, y, v in samples) / scale
+    return err
+
+
 # ---------------------------------------------------------------- ablations --
 # The paper's ablation study (Section 3, Figs 5 and 7) switches the slip
 # forces of Table 1 off one at a time.  Drag stays on in every case: without

@@ -21,9 +21,9 @@ if not torch.cuda.is_available():
 import oracle  # noqa: E402
 import paper_1511_04552_amd as mc  # noqa: E402
 from paper_1511_04552_amd import inputs  # noqa: E402
-from parity import (ABLATION_MASKS, ABLATION_SEED, ABLATION_STEPS, DEVIATION_FIELDS,  # noqa: E402
-                    DEVIATION_FLOOR, MOMENT_TOL, NU_TOL, ablation_config, assert_fields, assert_nusselt,
-                    field_errors)
+from parity import (ABLATION_MASKS, ABLATION_SEED, ABLATION_STEPS, MOMENT_TOL, NU_TOL,  # noqa: E402
+                    ablation_config, assert_fields, assert_nusselt, field_errors, load_sampled,
+                    sampled_errors)
 
 MOMENTS = oracle.FIELDS[:9]
 
@@ -187,23 +187,6 @@ def test_bench_workload_long_horizon_nusselt():
 GOLDEN_2048 = os.path.join(os.path.dirname(__file__), "golden", "cavity2048_ra1e6_sampled.txt")
 
 
-def _golden_2048():
-    g = {"scales": {}, "samples": {}}
-    for line in open(GOLDEN_2048):
-        if line.startswith("#") or not line.strip():
-            continue
-        p = line.split()
-        if p[0] == "steps":
-            g["steps"] = int(p[1])
-        elif p[0] == "nusselt":
-            g["nu"] = tuple(float(v) for v in p[1:4])
-        elif p[0] == "scale":
-            g["scales"][p[1]] = tuple(float(v) for v in p[2:5])
-        else:
-            g["samples"].setdefault(p[0], []).append((int(p[1]), int(p[2]), float(p[3])))
-    return g
-
-
 @pytest.mark.timeout(300)
 def test_full_size_2048_both_schedules_all_fields():
     """2048^2, Ra 1e6, phi 4 %, 30 nm (the reduced-precision workload's
@@ -219,7 +202,7 @@ def test_full_size_2048_both_schedules_all_fields():
     1000 more steps.  (At 1000 steps the vertical particle velocity, still
     confined to thin wall layers, is resolved to ~1e-5 of its maximum; at
     2000 every field to a few 1e-6.)"""
-    g = _golden_2048()
+    g = load_sampled(GOLDEN_2048)
     n = g["steps"]
     w = inputs.WORKLOADS["cavity2048_ra1e6"]
     cfg = {k: v for k, v in w.items() if k != "seed"}
@@ -232,11 +215,7 @@ def test_full_size_2048_both_schedules_all_fields():
     for name, c in (("k_step", one), ("k_step2", two)):
         c.step(n)
         m = c.moments(MOMENTS)
-        err = {}
-        for f in MOMENTS:
-            mean, dev, mag = g["scales"][f]
-            scale = max(dev, DEVIATION_FLOOR * mag) if f in DEVIATION_FIELDS else mag
-            err[f] = max(abs(m[f][y, x] - v) for x, y, v in g["samples"][f]) / scale
+        err = sampled_errors(m, g)
         print(name, f"t={n} sampled", {k: f"{v:.2e}" for k, v in err.items()}, flush=True)
         for f, v in err.items():
             assert v <= MOMENT_TOL, (name, f, v)
