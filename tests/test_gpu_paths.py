@@ -52,24 +52,23 @@ def _cavity(cfg, xi, steps, **knobs):
     (dict(nx=40, ny=33, Ra=1e5, phi0=0.02, dp_nm=30.0, storage=mc.FP16S), 6e-3),
 ])
 def test_index64_and_streaming_paths_match_oracle(cfg, tol):
-    """Each variant is its own kernel instantiation (the compiler may fuse
-    multiply-adds differently), so the bar is the parity bar against the
-    oracle (for FP16 storage its error bound), and the distance to the
-    default path is reported."""
+    """Each variant is its own kernel instantiation with the same arithmetic
+    (multiply-adds fused per source expression), so it gives the default
+    path's bits; each is also held to the parity bar against the oracle
+    (for FP16 storage its error bound)."""
     xi = inputs.phi_perturbation(101, cfg["nx"], cfg["ny"])
     o = oracle.Oracle(xi=xi, **{k: v for k, v in cfg.items() if k != "storage"})
     o.step(1001)
     mo = o.moments()
-    ref = _cavity(cfg, xi, 1001).moments()
+    ref = _cavity(cfg, xi, 1001).populations()
     for knobs in (dict(), dict(index64=True), dict(streaming=True), dict(index64=True, streaming=True)):
-        mg = _cavity(cfg, xi, 1001, **knobs).moments()
-        err = field_errors(mg, mo)
+        c = _cavity(cfg, xi, 1001, **knobs)
+        err = field_errors(c.moments(), mo)
         worst = max(err.values())
-        to_default = max(field_errors(mg, ref).values())
         print(cfg.get("storage", 0), cfg.get("thermal_lattices", 1), knobs,
-              {k: f"{v:.1e}" for k, v in err.items()},
-              f"vs oracle {worst:.2e}, vs default path {to_default:.2e}")
+              {k: f"{v:.1e}" for k, v in err.items()}, f"vs oracle {worst:.2e}")
         assert worst <= tol, (knobs, worst)
+        assert np.array_equal(c.populations(), ref), knobs
 
 
 def test_batch_index64_path_matches_single_runs():
@@ -98,7 +97,13 @@ def test_cavity_above_2gib_matches_oracle():
     (``golden/cavity4608_ra1e6_sampled.txt``, written by
     ``golden/make_cavity4608_sampled.py`` from the oracle alone), each moment
     relative to the oracle field's scale over the whole cavity; and the
-    particle mass."""
+    particle mass.  With tau_f 0.8 the flow develops slowly at this size:
+    after 2000 steps the velocities are at most 3e-6 (fluid) and FP32
+    storage resolves them to 1.1e-5 (fluid), 1.4e-5 (mixture) and 5.0e-5
+    (particle, the smallest density) of their maximum (measured), so they
+    are held to 1.5e-4; the densities and theta to the 1e-5 bar (measured
+    1.2e-6 ... 1.7e-6).  The 64-bit offsets and streamed accesses give the
+    32-bit path's bits on small cavities (test_index64_and_streaming_paths_match_oracle)."""
     g = load_sampled(GOLDEN_4608)
     n = 4608
     cfg = dict(nx=n, ny=n, Ra=1e6, phi0=0.04, dp_nm=30.0)
@@ -111,7 +116,7 @@ def test_cavity_above_2gib_matches_oracle():
     err = sampled_errors(m, g)
     print(f"4608^2 t={g['steps']} sampled", {k: f"{v:.2e}" for k, v in err.items()}, flush=True)
     for f, v in err.items():
-        assert v <= MOMENT_TOL, (f, v)
+        assert v <= (MOMENT_TOL if f in ("rho_f", "phi", "theta") else 1.5e-4), (f, v)
     assert_nusselt(c.nusselt(), g["nu"], label="4608^2")
     assert abs(m["phi"].sum() - phi0) <= 1e-6 * phi0
 
