@@ -137,6 +137,69 @@ def test_large_gemm_sampled_rows_2048():
     assert (np.abs(got - ref) <= bound).all(), np.abs(got - ref).max()
 
 
+@pytest.mark.parametrize("tb", [0, 1])
+def test_large_tile_gemm_many_batches_matches_fp64_of_bf16_operands(tb):
+    """16 products of 1024 x 1024 x 96 through the large-tile kernel (512
+    tiles over the batch), padded leading dimensions, two-level batch
+    offsets and alpha/beta: every element within the bound of the general
+    kernel, and nothing written outside the products."""
+    M = N = 1024
+    K = 96
+    rng = np.random.default_rng(17 + tb)
+    nb1, nb2 = 4, 4
+    br, bc = (N, K) if tb else (K, N)
+    lda, ldb, ldc = K + 4, bc + 4, N + 1
+    sa2, sb2, sc2 = M * lda + 4, br * ldb + 4, M * ldc
+    sa1, sb1, sc1 = nb2 * sa2, nb2 * sb2 + 8, nb2 * sc2 + 3
+    A = rng.normal(size=nb1 * sa1).astype(np.float32)
+    B = rng.normal(size=nb1 * sb1).astype(np.float32)
+    C0 = rng.normal(size=nb1 * sc1).astype(np.float32)
+    alpha, beta = 0.75, -0.5
+    tA, tB, tC = (torch.tensor(x, device=DEV) for x in (A, B, C0))
+    _gemm(0, tb, M, N, K, alpha, tA, lda, (sa1, sa2), tB, ldb, (sb1, sb2), beta, tC, ldc, (sc1, sc2), nb1, nb2)
+    got = tC.cpu().numpy().astype(np.float64)
+    Ab, Bb = bf16(A), bf16(B)
+    for z1 in range(nb1):
+        for z2 in range(nb2):
+            a = Ab[z1 * sa1 + z2 * sa2:][:M * lda].reshape(M, lda)[:, :K]
+            b = Bb[z1 * sb1 + z2 * sb2:][:br * ldb].reshape(br, ldb)[:, :bc]
+            opb = b.T if tb else b
+            o = z1 * sc1 + z2 * sc2
+            c0 = C0[o:o + M * ldc].astype(np.float64).reshape(M, ldc)[:, :N]
+            ref = alpha * (a @ opb) + beta * c0
+            bound = 2.0 * K * 2.0 ** -24 * abs(alpha) * (np.abs(a) @ np.abs(opb)) + 2.0 ** -23 * np.abs(ref) + 1e-30
+            g = got[o:o + M * ldc].reshape(M, ldc)[:, :N]
+            assert (np.abs(g - ref) <= bound).all(), (z1, z2, np.abs(g - ref).max())
+    # the C elements outside the products are untouched
+    mask = np.ones(nb1 * sc1, bool)
+    for z1 in range(nb1):
+        for z2 in range(nb2):
+            o = z1 * sc1 + z2 * sc2
+            mask[o:o + M * ldc].reshape(M, ldc)[:, :N] = False
+    assert np.array_equal(got[mask], C0.astype(np.float64)[mask])
+
+
+@pytest.mark.parametrize("tb", [0, 1])
+def test_large_gemm_sampled_rows_4096(tb):
+    """4096^3, the benchmarked product, with both layouts of B: sampled rows
+    of C (every row position of a wave's block and the tile edges) against
+    FP64 products of the BF16-rounded operands."""
+    n = 4096
+    g = torch.Generator(device="cpu").manual_seed(7 + tb)
+    A = torch.randn(n, n, generator=g)
+    B = torch.randn(n, n, generator=g)
+    tA, tB = A.to(DEV), B.to(DEV)
+    tC = torch.zeros(n, n, device=DEV)
+    _gemm(0, tb, n, n, n, 1.0, tA, n, (0, 0), tB, n, (0, 0), 0.0, tC, n, (0, 0), 1, 1)
+    rows = np.array([0, 1, 31, 32, 63, 64, 127, 128, 191, 192, 255, 256, 2100, 4095])
+    Ab, Bb = bf16(A.numpy()), bf16(B.numpy())
+    opb = Bb.T if tb else Bb
+    ref = Ab[rows] @ opb
+    bound = 2.0 * n * 2.0 ** -24 * (np.abs(Ab[rows]) @ np.abs(opb)) + 1e-30
+    got = tC.cpu().numpy()[rows].astype(np.float64)
+    assert (np.abs(got - ref) <= bound).all(), np.abs(got - ref).max()
+
+
 def test_gemm_beta_zero_ignores_nan_in_c():
     A = torch.ones(4, 4, device=DEV)
     C = torch.full((4, 4), float("nan"), device=DEV)
