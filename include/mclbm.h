@@ -155,17 +155,17 @@ typedef struct {
                               cavities of 2^20 nodes in total that fill at
                               least 60 % of their 62-column strips; else 1.  A step
                               count or start that is odd takes single steps
-                              where needed.  Results are those of single
-                              steps up to rounding (16-bit storage: the
-                              intermediate odd-step state is kept in FP32,
-                              not rounded to storage) */
+                              where needed.  With FP32 storage the results
+                              are bitwise those of single steps (16-bit
+                              storage: the intermediate odd-step state is
+                              kept in FP32, not rounded to storage) */
 } mclbm_config;
 
 typedef struct mclbm_cavity mclbm_cavity; /* opaque host-side handle */
 
 /* Environment variables read when a cavity is created (none changes the
- * results beyond rounding; the tests use them to reach size-chosen paths on
- * small cavities):
+ * results; the tests use them to reach size-chosen paths on small
+ * cavities):
  *   MCLBM_LOG=debug      one line on stderr per configuration with the
  *                        lattice constants and stability numbers
  *   MCLBM_INDEX64=1      64-bit element offsets (otherwise above 2 GiB of
@@ -346,8 +346,8 @@ int mclbm_derived(const mclbm_cavity* c, double* out, int n);
  * configuration apart from its launch shape (block_x, block_y and
  * steps_per_launch may differ; MCLBM_EINVAL otherwise, or for a damaged or
  * foreign file; the cavity is then unchanged); stepping then continues
- * bitwise as the checkpointed run would have (after a change of
- * steps_per_launch: up to rounding).  Not for batch members
+ * bitwise as the checkpointed run would have (also after a change of
+ * steps_per_launch with FP32 storage).  Not for batch members
  * (MCLBM_ESTATE).
  * Both return MCLBM_EHIP-free host errors as MCLBM_EINVAL with a message. */
 int mclbm_checkpoint(mclbm_cavity* c, const char* path);
