@@ -3038,6 +3038,7 @@ int mclbm_batch_autotune(mclbm_batch* b, int32_t steps) {
   // then the schedule, every cavity active: the tiles (replayed from the
   // graph) or one workgroup per cavity
   if (!rc && percav_eligible(b)) {
+    const bool prior = b->percav;
     rc = batch_reset_all(b);
     const int64_t n2 = std::max<int64_t>(std::max<int64_t>(2, steps & ~1), b->graph_steps);
     float ms[2] = {0.0f, 0.0f};
@@ -3056,7 +3057,7 @@ int mclbm_batch_autotune(mclbm_batch* b, int32_t steps) {
       }
       HIP_TRY(hipEventElapsedTime(&ms[pc], e0, e1));
     }
-    if (!rc) b->percav = ms[1] < ms[0];
+    b->percav = rc ? prior : ms[1] < ms[0];
     drop_graph(b);
   }
   (void)hipEventDestroy(e0);
