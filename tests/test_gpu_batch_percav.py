@@ -129,3 +129,17 @@ def test_per_cavity_16bit_storage_equals_tiles(storage):
         a.step(n)
         b.step(n)
         _equal(a, b, range(len(cfgs)))
+
+
+def test_per_cavity_largest_cavities_equal_tiles():
+    """Cavities up to the 128^2-node limit (16 nodes per thread, ragged
+    last pass) give the tile schedule's bits."""
+    cfgs, xis = _small(4, seed=23, sides=((128, 128), (100, 72), (127, 129), (33, 31)))
+    a = mc.Batch(cfgs, xis=xis)
+    b = mc.Batch(cfgs, xis=xis)
+    a.per_cavity = True
+    b.per_cavity = False
+    for n in (130, 33):
+        a.step(n)
+        b.step(n)
+        _equal(a, b, range(len(cfgs)))
