@@ -102,6 +102,25 @@ def sampled_errors(m, g):
     return err
 
 
+def load_records(path, fields):
+    """An oracle reference of the long-horizon golden scripts: the records
+    (step, nu_hot, nu_cold, nu_hot_k, res_u, res_theta) as an array, each
+    field's (mean, largest deviation, largest magnitude) of the last record,
+    and the fields at sampled nodes as {field: [(x, y, value), ...]}."""
+    rows, scales, samples = [], {}, {}
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        p = line.split()
+        if p[0] == "scale":
+            scales[p[1]] = tuple(float(v) for v in p[2:5])
+        elif p[0] in fields:
+            samples.setdefault(p[0], []).append((int(p[1]), int(p[2]), float(p[3])))
+        else:
+            rows.append([float(v) for v in p])
+    return np.array(rows), {"scales": scales, "samples": samples}
+
+
 # ---------------------------------------------------------------- ablations --
 # The paper's ablation study (Section 3, Figs 5 and 7) switches the slip
 # forces of Table 1 off one at a time.  Drag stays on in every case: without

@@ -22,8 +22,8 @@ import oracle  # noqa: E402
 import paper_1511_04552_amd as mc  # noqa: E402
 from paper_1511_04552_amd import inputs  # noqa: E402
 from parity import (ABLATION_MASKS, ABLATION_SEED, ABLATION_STEPS, MOMENT_TOL, NU_TOL,  # noqa: E402
-                    ablation_config, assert_fields, assert_nusselt, field_errors, load_sampled,
-                    sampled_errors)
+                    ablation_config, assert_fields, assert_nusselt, field_errors, load_records,
+                    load_sampled, sampled_errors)
 
 MOMENTS = oracle.FIELDS[:9]
 
@@ -229,6 +229,35 @@ def test_full_size_2048_both_schedules_all_fields():
         rel = abs(m1[k].sum() - m0[k].sum()) / m0[k].sum()
         print(k, "mass drift", rel)
         assert rel < 1e-9, (k, rel)
+
+
+GOLDEN_160 = os.path.join(os.path.dirname(__file__), "golden", "cavity160_paper_steady.txt")
+
+
+@pytest.mark.skipif(not os.path.exists(GOLDEN_160), reason="oracle reference not written yet")
+def test_paper_lattice_long_horizon_nusselt_and_moments():
+    """The paper's lattice and case (160^2, Ra 1e6, Pr 8.923, 4 % alumina,
+    33 nm, every force, tau_f automatic) towards steady state: the hot,
+    cold and conductivity-weighted Nu at every record of the oracle's run
+    (``golden/cavity160_paper_steady.txt``, written by
+    ``golden/make_cavity160_steady.py`` from the oracle alone), and the nine
+    moments at 100 sampled nodes after the last record."""
+    rows, g = load_records(GOLDEN_160, MOMENTS)
+    w = inputs.WORKLOADS["cavity160_paper"]
+    cfg = dict({k: v for k, v in w.items() if k != "seed"}, tau_f=-1.0)
+    c = mc.Cavity(xi=inputs.phi_perturbation(w["seed"], 160, 160), **cfg)
+    worst = 0.0
+    for row in rows:
+        c.step(int(row[0]) - c.time)
+        nu = c.nusselt()
+        err = max(abs(a - b) / abs(b) for a, b in zip(nu, row[1:4]))
+        worst = max(worst, err)
+        print(f"t={int(row[0])} Nu {nu[0]:.8f} oracle {row[1]:.8f} ({err:.1e})", flush=True)
+    err = sampled_errors(c.moments(MOMENTS), g)
+    print("paper lattice, last record, sampled", {k: f"{v:.2e}" for k, v in err.items()}, flush=True)
+    assert worst <= NU_TOL, worst
+    for f, v in err.items():
+        assert v <= MOMENT_TOL, (f, v)
 
 
 def test_block_shapes_bitwise_identical_and_deterministic():
