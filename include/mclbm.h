@@ -174,7 +174,11 @@ typedef struct mclbm_cavity mclbm_cavity; /* opaque host-side handle */
  *                        (otherwise above 160 MiB)
  *   MCLBM_POISON=1       race check: NaN-fill, before each launch, what it
  *                        writes and must not read first
- *   MCLBM_BAND2=<rows>   band height of two steps per launch (tuning) */
+ *   MCLBM_BAND2=<rows>   band height of two steps per launch (tuning)
+ *   MCLBM_PLANE_PAD=<n>  elements of padding between population planes, a
+ *                        multiple of 64 in [0, 2^20] (otherwise 4160 from
+ *                        2^20 nodes on, 0 below); checkpoints and
+ *                        mclbm_copy_state need the same pad on both sides */
 
 /* Fill *cfg with the defaults: 64x64, Ra 1e3, Pr 6.2, phi0 0.01, dp 100 nm,
  * tau_f 0.8, dT 10 K, T0 300 K, all forces at scale 1, amplitude 1e-6,
@@ -182,7 +186,9 @@ typedef struct mclbm_cavity mclbm_cavity; /* opaque host-side handle */
 void mclbm_config_defaults(mclbm_config* cfg);
 
 /* Bytes of device memory a cavity with this configuration needs; 0 if the
- * configuration is invalid (see mclbm_last_error). */
+ * configuration is invalid (see mclbm_last_error).  From 2^20 nodes on the
+ * population planes are padded (MCLBM_PLANE_PAD), which adds a few hundred
+ * KB. */
 size_t mclbm_device_bytes(const mclbm_config* cfg);
 
 /* Derived lattice constants of a configuration (host only, no device work):

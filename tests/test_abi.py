@@ -75,6 +75,28 @@ def test_invalid_configs_rejected(bad):
     assert mc.lib().mclbm_last_error()
 
 
+def test_plane_pad_sizes():
+    """Population planes of cavities from 2^20 nodes on are padded by 4160
+    elements (the second copy of two steps per launch shows it exactly);
+    MCLBM_PLANE_PAD overrides the pad, and invalid values are ignored."""
+    def second_copy(nx, ny):
+        return mc.device_bytes(nx=nx, ny=ny, steps_per_launch=2) - mc.device_bytes(nx=nx, ny=ny, steps_per_launch=1)
+    assert second_copy(1024, 1024) == 27 * 4 * (1024 * 1024 + 4160)
+    assert second_copy(1024, 1023) == 27 * 4 * 1024 * 1023
+    old = os.environ.get("MCLBM_PLANE_PAD")
+    try:
+        for env, pad in (("0", 0), ("128", 128), ("100", 4160), ("-64", 4160), (str(1 << 21), 4160)):
+            os.environ["MCLBM_PLANE_PAD"] = env
+            assert second_copy(1024, 1024) == 27 * 4 * (1024 * 1024 + pad), env
+        os.environ["MCLBM_PLANE_PAD"] = "256"
+        assert second_copy(64, 64) == 27 * 4 * (64 * 64 + 256)
+    finally:
+        if old is None:
+            os.environ.pop("MCLBM_PLANE_PAD", None)
+        else:
+            os.environ["MCLBM_PLANE_PAD"] = old
+
+
 def test_two_steps_per_launch_sizes_and_limits():
     """Two steps per launch keep a second population copy: on request, and
     by default for FP32 storage from 2^20 nodes and 256 columns on (below
@@ -82,7 +104,8 @@ def test_two_steps_per_launch_sizes_and_limits():
     pop64 = 27 * 4 * 64 * 64
     assert mc.device_bytes(nx=64, ny=64, steps_per_launch=2) == mc.device_bytes(nx=64, ny=64) + pop64
     assert mc.device_bytes(nx=64, ny=64, steps_per_launch=1) == mc.device_bytes(nx=64, ny=64)
-    pop2k = 27 * 4 * 2048 * 2048
+    # from 2^20 nodes on each population plane is padded by 4160 elements
+    pop2k = 27 * 4 * (2048 * 2048 + 4160)
     one = mc.device_bytes(nx=2048, ny=2048, steps_per_launch=1)
     assert mc.device_bytes(nx=2048, ny=2048) == mc.device_bytes(nx=2048, ny=2048, steps_per_launch=2) == one + pop2k
     assert mc.device_bytes(nx=1024, ny=1024) > mc.device_bytes(nx=1024, ny=1024, steps_per_launch=1)

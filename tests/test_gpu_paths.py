@@ -23,9 +23,11 @@ MOMENTS = oracle.FIELDS[:9]
 
 
 class _knobs:
-    def __init__(self, index64=False, streaming=False, poison=False):
+    def __init__(self, index64=False, streaming=False, poison=False, plane_pad=None):
         self.env = {"MCLBM_INDEX64": "1" if index64 else "0", "MCLBM_STREAMING": "1" if streaming else "0",
                     "MCLBM_POISON": "1" if poison else "0"}
+        if plane_pad is not None:
+            self.env["MCLBM_PLANE_PAD"] = str(plane_pad)
 
     def __enter__(self):
         self.old = {k: os.environ.get(k) for k in self.env}
@@ -69,6 +71,27 @@ def test_index64_and_streaming_paths_match_oracle(cfg, tol):
               {k: f"{v:.1e}" for k, v in err.items()}, f"vs oracle {worst:.2e}")
         assert worst <= tol, (knobs, worst)
         assert np.array_equal(c.populations(), ref), knobs
+
+
+@pytest.mark.parametrize("cfg", [
+    dict(nx=67, ny=53, Ra=1e5, phi0=0.03, dp_nm=40.0, steps_per_launch=1),
+    dict(nx=300, ny=45, Ra=1e5, phi0=0.03, dp_nm=40.0, steps_per_launch=2),
+    dict(nx=67, ny=53, Ra=1e5, phi0=0.03, dp_nm=40.0, storage=mc.FP16S),
+])
+def test_plane_pad_is_bitwise_neutral(cfg):
+    """Padding between population planes (the default from 2^20 nodes on)
+    moves the planes in memory and changes no bit of the results; a state
+    hand-over between cavities of different pads is refused."""
+    xi = inputs.phi_perturbation(11, cfg["nx"], cfg["ny"])
+    ref = _cavity(cfg, xi, 301)
+    for pad in (64, 4160):
+        c = _cavity(cfg, xi, 301, plane_pad=pad)
+        assert np.array_equal(c.populations(), ref.populations()), pad
+        mg, mr = c.moments(), ref.moments()
+        assert all(np.array_equal(mg[k], mr[k]) for k in mr), pad
+        assert c.nusselt() == ref.nusselt()
+    with pytest.raises(mc.MclbmError):
+        c.copy_state_from(ref)
 
 
 def test_batch_index64_path_matches_single_runs():
