@@ -1041,12 +1041,13 @@ bool two_step(const mclbm_config& c, bool batch_member) {
   return c.storage == MCLBM_FP32S && (long long)c.nx * c.ny >= (1LL << 20) && c.nx >= 256;
 }
 
-// Band height of the two-step kernel: 6 rows below 2^21 nodes and 4 from
-// there on (of 3 to 32 rows, the fastest or within 1 % of it at 1024^2,
-// 1536^2, 2048^2, 3072^2 and 4096^2: more waves in flight outweigh the halo
-// rows recomputed, whose loads hit in L2); MCLBM_BAND2 sets it (tuning knob).
+// Band height of the two-step kernel: 6 rows below 2^21 nodes and 3 from
+// there on (of 2 to 32 rows, the fastest at 1024^2, 1536^2, 2048^2, 3072^2
+// and 4096^2 with padded planes, by 1-2 % over 4 rows: more waves in flight
+// outweigh the halo rows recomputed, whose loads hit in L2); MCLBM_BAND2
+// sets it (tuning knob).
 int band2_of(const mclbm_config& c) {
-  int band = (long long)c.nx * c.ny >= (1LL << 21) ? 4 : 6;
+  int band = (long long)c.nx * c.ny >= (1LL << 21) ? 3 : 6;
   if (const char* e = std::getenv("MCLBM_BAND2")) {
     const int v = std::atoi(e);
     if (v >= 1 && v <= 65536) band = v;
