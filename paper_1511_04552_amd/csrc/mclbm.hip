@@ -1435,7 +1435,12 @@ int setup_cavity(mclbm_cavity* c) {
   c->L = make_layout(c->cfg, c->in_batch);
   c->P = make_params(c->cfg, c->D, c->L);
   int bx = c->cfg.block_x, by = c->cfg.block_y;
-  if (bx == 0) bx = c->cfg.nx >= 256 ? 256 : 64;
+  // Default workgroup: 256 x 1 from 256 columns on; with 16-bit storage
+  // 64 x 1 from 2^21 nodes on (2048^2 and 4096^2: +3-4 % over 256 x 1 for
+  // FP16 and BF16; equal at 1024^2, 3.5 % slower at 512^2; FP32 is fastest
+  // with 256 x 1 at every size).
+  const bool narrow16 = c->cfg.storage != MCLBM_FP32S && (long long)c->cfg.nx * c->cfg.ny >= (1LL << 21);
+  if (bx == 0) bx = c->cfg.nx >= 256 && !narrow16 ? 256 : 64;
   if (by == 0) by = 1;
   c->block = dim3(bx, by, 1);
   c->tiles_x = (c->cfg.nx + bx - 1) / bx;
