@@ -94,6 +94,23 @@ def test_plane_pad_is_bitwise_neutral(cfg):
         c.copy_state_from(ref)
 
 
+def test_16bit_default_launch_shape_at_large_size_is_bitwise():
+    """From 2^21 nodes on, 16-bit storage defaults to 64 x 1 workgroups;
+    the results equal those of 256 x 1 bit for bit (same node update, other
+    launch shape)."""
+    cfg = dict(nx=1536, ny=1400, Ra=1e6, phi0=0.04, dp_nm=30.0, storage=mc.FP16S)
+    assert cfg["nx"] * cfg["ny"] >= 1 << 21
+    xi = inputs.phi_perturbation(5, cfg["nx"], cfg["ny"])
+    a = mc.Cavity(xi=xi, **cfg)
+    b = mc.Cavity(xi=xi, block_x=256, block_y=1, **cfg)
+    a.step(21)
+    b.step(21)
+    names = ("rho_f", "ux_f", "phi", "theta")
+    ma, mb = a.moments(names), b.moments(names)
+    assert all(np.array_equal(ma[k], mb[k]) for k in names)
+    assert a.nusselt() == b.nusselt()
+
+
 def test_batch_index64_path_matches_single_runs():
     cfgs = [dict(nx=37, ny=29, Ra=5e4, phi0=0.03, dp_nm=40.0), dict(nx=64, ny=48, Ra=2e5, phi0=0.01, dp_nm=80.0)]
     xis = [inputs.phi_perturbation(110 + k, c["nx"], c["ny"]) for k, c in enumerate(cfgs)]
