@@ -54,6 +54,10 @@ def parse():
     ap.add_argument("--small-batches-only", action="store_true",
                     help="time only the batches of many small cavities (tiles against one workgroup per "
                          "cavity) and print their line")
+    ap.add_argument("--copy-only", action="store_true",
+                    help="time plain device copies (this library's streaming copy kernel and torch's "
+                         "copy_) of 16, 30.4 (the bytes each way of one 512^2 step), 61 and 1024 MB "
+                         "and print their line")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="summarise two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this "
                          "bench into the traffic file and exit")
@@ -126,6 +130,38 @@ def pmc_summary(fetch_dir, write_dir, workload, out_path, storage="fp32"):
            "fetch_scale": res["FETCH_SIZE"]["scale"], "write_scale": res["WRITE_SIZE"]["scale"]}
     json.dump(out, open(out_path, "w"), indent=1)
     print(json.dumps(out, indent=1))
+
+
+def copy_measure(torch, mc):
+    """Microseconds and GB/s (bytes read plus written) of plain device copies
+    of several sizes: the library's streaming copy kernel and torch's copy_.
+    30.4 MB each way is what one 512^2 FP32 step reads and writes, so these
+    copies are the rate a step of that size could reach if it did nothing
+    but move its bytes."""
+    s = torch.cuda.current_stream()
+    out = []
+    for mb in (16.0, 30.4, 61.0, 1024.0):
+        n = int(mb * (1 << 20)) // 16 * 4
+        src = torch.empty(n, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        reps = 2000 if mb < 100 else 100
+        row = {"mb_each_way": mb}
+        for name, fn in (("copy_kernel", lambda: mc.copy_kernel(dst, src, s)), ("torch_copy", lambda: dst.copy_(src))):
+            for _ in range(20):
+                fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            for _ in range(reps):
+                fn()
+            e1.record(s)
+            torch.cuda.synchronize()
+            us = e0.elapsed_time(e1) * 1e3 / reps
+            row[name] = {"us": round(us, 2), "GBps": round(2 * n * 4 / us / 1e3, 1)}
+        out.append(row)
+        del src, dst
+        torch.cuda.empty_cache()
+    return out
 
 
 def batch_measure(torch, mc, inputs, n, steps=64):
@@ -380,6 +416,9 @@ def main():
         sys.exit(1)
     if a.gemm_only:
         print(json.dumps({"gemm_bf16": gemm_measure(torch, mc)}), flush=True)
+        return
+    if a.copy_only:
+        print(json.dumps({"copies": copy_measure(torch, mc)}), flush=True)
         return
     if a.small_batches_only:
         from paper_1511_04552_amd import inputs
