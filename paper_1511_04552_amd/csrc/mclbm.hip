@@ -1009,8 +1009,10 @@ constexpr size_t kStreamingBytes = 160u << 20;
 // 0, 4160, 16512, 65600 and 131136 elements were timed at 1024^2, 1536^2,
 // 2048^2, 3072^2 and 4096^2: 4160 was never slower than no pad (two steps
 // per launch +1 % to +11 %, one step +2 %), the larger pads were faster at
-// some sizes and up to 20 % slower at others.  MCLBM_PLANE_PAD (elements, a
-// multiple of 64, 0 to 2^20) overrides it (tuning knob).
+// some sizes and up to 20 % slower at others.  Below 2^20 nodes, inside the
+// last-level cache, the pad does not pay (512^2: 2.6 % slower).
+// MCLBM_PLANE_PAD (elements, a multiple of 64, 0 to 2^20) overrides it
+// (tuning knob).
 constexpr long long kPlanePad = 4160;
 long long plane_of(const mclbm_config& c) {
   const long long px = (c.nx + 63) / 64 * 64;
