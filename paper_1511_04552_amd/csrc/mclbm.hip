@@ -1024,9 +1024,10 @@ long long plane_of(const mclbm_config& c) {
   return px * c.ny + pad;
 }
 
-size_t pop_bytes(const mclbm_config& c) {
-  return (size_t)9 * lattices(c) * (size_t)plane_of(c) * storage_bytes(c.storage);
+size_t pop_bytes(const mclbm_config& c, long long plane) {
+  return (size_t)9 * lattices(c) * (size_t)plane * storage_bytes(c.storage);
 }
+size_t pop_bytes(const mclbm_config& c) { return pop_bytes(c, plane_of(c)); }
 
 // Two time steps per launch (k_step2): one thermal lattice and a population
 // array below 2 GiB (32-bit buffer offsets) only.  By default for FP32
@@ -1065,9 +1066,9 @@ Layout make_layout(const mclbm_config& c, bool batch_member = false) {
   const long long nn = (long long)c.nx * c.ny;
   size_t off = 0;
   L.off_pop = off;
-  off = align_up(off + pop_bytes(c));
+  off = align_up(off + pop_bytes(c, L.plane));
   L.off_pop2 = off;  // second copy (two steps per launch), else empty
-  if (two_step(c, batch_member)) off = align_up(off + pop_bytes(c));
+  if (two_step(c, batch_member)) off = align_up(off + pop_bytes(c, L.plane));
   L.off_d2 = off;
   off = align_up(off + (size_t)2 * L.plane * sizeof(float2));
   L.off_d5 = off;
@@ -1510,7 +1511,7 @@ int launch_step2(mclbm_cavity* c) {
       // race check: every slot of the target copy and every lag-field entry
       // the launch writes start as NaN, so a slot left unwritten (or read
       // before it is written) shows up in the results
-      const long long np = (long long)pop_bytes(c->cfg) / (long long)sizeof(float);
+      const long long np = (long long)pop_bytes(c->cfg, c->L.plane) / (long long)sizeof(float);
       k_poison<<<(unsigned)std::min<long long>((np + 255) / 256, 1 << 20), 256, 0, c->stream>>>(
           reinterpret_cast<float*>(c->pop_other()), np);
       const long long n2 = 2 * c->L.plane;
@@ -1714,7 +1715,7 @@ struct CkptSection {
 std::vector<CkptSection> ckpt_sections(const mclbm_cavity* c) {
   const long long nn = (long long)c->cfg.nx * c->cfg.ny;
   return {
-      {"populations", c->pop_off(c->popsel), pop_bytes(c->cfg)},
+      {"populations", c->pop_off(c->popsel), pop_bytes(c->cfg, c->L.plane)},
       {"lag_field_0", c->d2_off(0), (size_t)c->L.plane * sizeof(float2)},
       {"lag_field_1", c->d2_off(1), (size_t)c->L.plane * sizeof(float2)},
       {"side_buffer", c->L.off_d5, (size_t)6 * (c->P.nl - 2) * c->L.px * sizeof(float)},
