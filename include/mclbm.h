@@ -175,6 +175,9 @@ typedef struct mclbm_cavity mclbm_cavity; /* opaque host-side handle */
  *   MCLBM_POISON=1       race check: NaN-fill, before each launch, what it
  *                        writes and must not read first
  *   MCLBM_BAND2=<rows>   band height of two steps per launch (tuning)
+ *   MCLBM_BANDMIX=<n>    dispatch interleave of those bands, 1 to 64 (1:
+ *                        in order; otherwise about 150 / strips of 62
+ *                        columns from 2^21 nodes on) (tuning)
  *   MCLBM_PLANE_PAD=<n>  elements of padding between population planes, a
  *                        multiple of 64 in [0, 2^20] (otherwise 4160 from
  *                        2^20 nodes on, 0 below); checkpoints and

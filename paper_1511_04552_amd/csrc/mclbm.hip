@@ -186,6 +186,24 @@ __global__ __launch_bounds__(256) void k_step(StepParams P,
 // above), never stored.
 constexpr int kStrip2 = 62;
 
+// Dispatch order of the bands of a two-step launch.  Each XCD takes the
+// band rows of its range in order, so band b + 1 of a strip would start
+// about one row iteration after band b: the halo rows the two share are
+// then read an iteration or two apart, by which time the XCD's L2 has
+// streamed past them.  Within windows of mix x kBandWindow band rows, band
+// i of the window is dispatched at slot (i % kBandWindow) * mix + i /
+// kBandWindow, so neighbouring bands start mix slots apart and read their
+// shared rows at about the same time.  A bijection of the band indices
+// (the tail beyond the last whole window keeps its order); the tiles of a
+// launch are independent, so the results do not depend on it.
+constexpr int kBandWindow = 16;
+__device__ __forceinline__ int band_of_tile(int slot, int segs, int mix) {
+  const int w = mix * kBandWindow;
+  if (mix <= 1 || slot >= segs / w * w) return slot;
+  const int i = slot % w;
+  return slot - i + (i % mix) * kBandWindow + i / mix;
+}
+
 // the 3 directions of each pull group, per lattice: up (e_y = +1), along
 // (e_y = 0), down (e_y = -1)
 __device__ __forceinline__ float pull_x(float v, int i) {
@@ -389,9 +407,10 @@ template <class S>
 __global__ __launch_bounds__(64) void k_step2(StepParams P, const typename S::T* __restrict__ popA,
                                               typename S::T* __restrict__ popB,
                                               const float2* __restrict__ d2p, float2* __restrict__ d2o,
-                                              int strips, int band) {
+                                              int strips, int band, int mix) {
   const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);
-  step2_tile<S>(P, popA, popB, d2p, d2o, (int)(tile % (unsigned)strips), (int)(tile / (unsigned)strips), band);
+  step2_tile<S>(P, popA, popB, d2p, d2o, (int)(tile % (unsigned)strips),
+                band_of_tile((int)(tile / (unsigned)strips), (P.ny + band - 1) / band, mix), band);
 }
 
 // Batched sweep: one launch per time step updates every active cavity of a
@@ -1059,6 +1078,25 @@ int band2_of(const mclbm_config& c) {
 }
 int strips2_of(const mclbm_config& c) { return (c.nx + kStrip2 - 1) / kStrip2; }
 
+// Band interleave of the two-step launch (band_of_tile): from 2^21 nodes
+// on, about 150 / strips band rows (1 to 8).  Of 1 to 10 at 1536^2, 2048^2,
+// 2560^2, 3072^2 and 4096^2 (25 to 67 strips) this is the fastest or
+// within 1.2 % of it, +3 % to +4.5 % over dispatching the bands in order;
+// below 2^21 nodes (bands of 6 rows) the bands keep their order.
+// MCLBM_BANDMIX sets it (tuning knob).
+int mix2_of(const mclbm_config& c) {
+  int mix = 1;
+  if ((long long)c.nx * c.ny >= (1LL << 21)) {
+    const int strips = strips2_of(c);
+    mix = std::min(8, std::max(1, (150 + strips / 2) / strips));
+  }
+  if (const char* e = std::getenv("MCLBM_BANDMIX")) {
+    const int v = std::atoi(e);
+    if (v >= 1 && v <= 64) mix = v;
+  }
+  return mix;
+}
+
 Layout make_layout(const mclbm_config& c, bool batch_member = false) {
   Layout L{};
   L.px = (c.nx + 63) / 64 * 64;
@@ -1301,6 +1339,7 @@ struct mclbm_cavity {
   bool two;            // two steps per launch (k_step2) from even steps
   int popsel, d2sel;   // which population copy is current; lag-field swap
   unsigned nblocks2;   // k_step2 grid: strips x bands
+  int mix2;            // k_step2 band interleave (band_of_tile)
   int strips2, band2;
   const int64_t* batch_clock;  // the owning batch's step count (members only)
   std::vector<double> host_dev_p;  // initial phi deviations (source of an async copy)
@@ -1461,6 +1500,7 @@ int setup_cavity(mclbm_cavity* c) {
   c->two = two_step(c->cfg, c->in_batch) && c->idx32;
   c->strips2 = strips2_of(c->cfg);
   c->band2 = band2_of(c->cfg);
+  c->mix2 = mix2_of(c->cfg);
   c->nblocks2 = (unsigned)c->strips2 * (unsigned)((c->cfg.ny + c->band2 - 1) / c->band2);
   return MCLBM_OK;
 }
@@ -1520,7 +1560,8 @@ int launch_step2(mclbm_cavity* c) {
       int r = launch_check("k_poison");
       if (r) return r;
     }
-    k_step2<S><<<c->nblocks2, 64, 0, c->stream>>>(c->P, src, dst, c->d2(1), c->d2(0), c->strips2, c->band2);
+    k_step2<S><<<c->nblocks2, 64, 0, c->stream>>>(c->P, src, dst, c->d2(1), c->d2(0), c->strips2, c->band2,
+                                                  c->mix2);
     int r = launch_check("k_step2");
     if (r) return r;
     c->popsel ^= 1;

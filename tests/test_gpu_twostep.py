@@ -105,6 +105,32 @@ def test_two_steps_per_launch_bitwise_equal_to_single_steps(shape):
     assert np.isfinite(two.populations()).all()
 
 
+@pytest.mark.parametrize("nx,ny,knobs,steps", [
+    (300, 200, dict(MCLBM_BAND2=3, MCLBM_BANDMIX=3), 40),   # one whole window of 48 bands and a tail
+    (300, 200, dict(MCLBM_BAND2=1, MCLBM_BANDMIX=5), 41),   # two windows of 80 bands and a tail, odd end
+    (1536, 1400, dict(), 20),                               # the default interleave (6) at 2^21 nodes
+])
+def test_band_interleave_is_bitwise_neutral(nx, ny, knobs, steps):
+    """The order in which the bands of a two-step launch are dispatched
+    (MCLBM_BANDMIX, by default about 150 / strips from 2^21 nodes on) is a
+    permutation of independent tiles: the results equal those of bands in
+    order bit for bit."""
+    cfg = dict(nx=nx, ny=ny, Ra=1e5, phi0=0.03, dp_nm=40.0, steps_per_launch=2)
+    xi = inputs.phi_perturbation(143, nx, ny)
+    with _env(**{**knobs, "MCLBM_BANDMIX": 1}):
+        ref = mc.Cavity(xi=xi, **cfg)
+    with _env(**knobs):
+        mix = mc.Cavity(xi=xi, **cfg)
+    ref.step(steps)
+    mix.step(steps)
+    names = ("rho_f", "ux_f", "uy_f", "phi", "ux_p", "theta")
+    mr, mm = ref.moments(names), mix.moments(names)
+    assert all(np.array_equal(mm[k], mr[k]) for k in names)
+    assert mix.nusselt() == ref.nusselt()
+    if nx * ny < 1 << 20:
+        assert np.array_equal(mix.populations(), ref.populations())
+
+
 @pytest.mark.parametrize("storage,tol", [(mc.FP16S, 6e-3), (mc.BF16S, 1.2e-1)])
 def test_two_steps_per_launch_16bit_storage(storage, tol):
     """16-bit storage: the odd step starts from the even step's FP32 result
