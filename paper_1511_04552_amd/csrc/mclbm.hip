@@ -197,7 +197,7 @@ constexpr int kStrip2 = 62;
 // (the tail beyond the last whole window keeps its order); the tiles of a
 // launch are independent, so the results do not depend on it.
 constexpr int kBandWindow = 16;
-__host__ __device__ __forceinline__ int band_of_tile(int slot, int segs, int mix) {
+__device__ __forceinline__ int band_of_tile(int slot, int segs, int mix) {
   const int w = mix * kBandWindow;
   if (mix <= 1 || slot >= segs / w * w) return slot;
   const int i = slot % w;
@@ -2521,9 +2521,17 @@ void deal_to_xcds(const std::vector<int2>& list, std::vector<int2>& table) {
     }
 }
 
+// The dispatch order of band_of_tile, for the batch's tile table.
+int band_slot(int slot, int segs, int mix) {
+  const int w = mix * kBandWindow;
+  if (mix <= 1 || slot >= segs / w * w) return slot;
+  const int i = slot % w;
+  return slot - i + (i % mix) * kBandWindow + i / mix;
+}
+
 // With two steps per launch, the (strip, band) tiles of each active cavity
 // (band-row-major, the band rows in the cavity's interleaved dispatch order,
-// band_of_tile) form the second table, dealt to the XCDs the same way.
+// band_slot) form the second table, dealt to the XCDs the same way.
 // The descriptors take the current roles of the copies: flip restarts at 0.
 int upload_tables(mclbm_batch* b) {
   std::vector<int2> list, list2;
@@ -2537,7 +2545,7 @@ int upload_tables(mclbm_batch* b) {
       const mclbm_cavity& c = b->cav[k];
       const int segs = (c.cfg.ny + c.band2 - 1) / c.band2;
       for (int slot = 0; slot < segs; ++slot) {
-        const int seg = band_of_tile(slot, segs, c.mix2);
+        const int seg = band_slot(slot, segs, c.mix2);
         for (int st = 0; st < c.strips2; ++st) list2.push_back(make_int2(k, seg * c.strips2 + st));
       }
     }

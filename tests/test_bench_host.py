@@ -77,3 +77,13 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "exactly one GPU" in r.stderr
+
+
+def test_stored_headline_traffic_belongs_to_the_current_kernels():
+    """The bench reports the HBM bytes of its headline launch from the
+    stored counter summary only while the step kernels' source is the one
+    the counters were taken with; a kernel change needs new counter runs."""
+    import json
+    t = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
+    assert t["workload"] == "cavity512_ra1e5" and t["storage"] == "fp32"
+    assert t["kernel_hash"] == bench.kernel_hash()
