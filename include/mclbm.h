@@ -180,8 +180,10 @@ typedef struct mclbm_cavity mclbm_cavity; /* opaque host-side handle */
  *                        columns from 2^21 nodes on) (tuning)
  *   MCLBM_PLANE_PAD=<n>  elements of padding between population planes, a
  *                        multiple of 64 in [0, 2^20] (otherwise 4160 from
- *                        2^20 nodes on, 0 below); checkpoints and
- *                        mclbm_copy_state need the same pad on both sides */
+ *                        2^20 nodes on and for every member of a batch
+ *                        whose FP32 working set exceeds 160 MiB, 0 below);
+ *                        mclbm_copy_state needs the same pad on both
+ *                        sides, checkpoints hold the planes without it */
 
 /* Fill *cfg with the defaults: 64x64, Ra 1e3, Pr 6.2, phi0 0.01, dp 100 nm,
  * tau_f 0.8, dT 10 K, T0 300 K, all forces at scale 1, amplitude 1e-6,
@@ -349,7 +351,8 @@ int mclbm_derived(const mclbm_cavity* c, double* out, int n);
  * configuration in readable form and as raw bytes, the derived constants,
  * the step count, parity, storage type and the byte size of each section),
  * then the raw sections: populations (storage format, both A-A parities
- * as stored), the two lag-field buffers, the adiabatic side buffer and the
+ * as stored, the planes without the padding between them), the two
+ * lag-field buffers (likewise), the adiabatic side buffer and the
  * residual snapshot.  Sync.  A member of a batch may be checkpointed.
  * mclbm_restore reads such a file into a cavity created with the same
  * configuration apart from its launch shape (block_x, block_y and

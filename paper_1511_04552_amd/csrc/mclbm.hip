@@ -1033,9 +1033,9 @@ constexpr size_t kStreamingBytes = 160u << 20;
 // MCLBM_PLANE_PAD (elements, a multiple of 64, 0 to 2^20) overrides it
 // (tuning knob).
 constexpr long long kPlanePad = 4160;
-long long plane_of(const mclbm_config& c) {
+long long plane_of(const mclbm_config& c, bool pad_planes = false) {
   const long long px = (c.nx + 63) / 64 * 64;
-  long long pad = (long long)c.nx * c.ny >= (1LL << 20) ? kPlanePad : 0;
+  long long pad = pad_planes || (long long)c.nx * c.ny >= (1LL << 20) ? kPlanePad : 0;
   if (const char* e = std::getenv("MCLBM_PLANE_PAD")) {
     const long long v = std::atoll(e);
     if (v >= 0 && v % 64 == 0 && v <= (1 << 20)) pad = v;
@@ -1097,10 +1097,12 @@ int mix2_of(const mclbm_config& c) {
   return mix;
 }
 
-Layout make_layout(const mclbm_config& c, bool batch_member = false) {
+// pad_planes: pad the planes whatever the size (members of a batch whose
+// working set streams from HBM)
+Layout make_layout(const mclbm_config& c, bool batch_member = false, bool pad_planes = false) {
   Layout L{};
   L.px = (c.nx + 63) / 64 * 64;
-  L.plane = plane_of(c);
+  L.plane = plane_of(c, pad_planes);
   const long long nn = (long long)c.nx * c.ny;
   size_t off = 0;
   L.off_pop = off;
@@ -1335,6 +1337,7 @@ struct mclbm_cavity {
   bool nt;             // non-temporal population traffic
   bool idx32;          // 32-bit element offsets
   bool in_batch;       // owned by a batch: stepped only through it
+  bool pad_planes;     // planes padded at any size (members of a streaming batch)
   bool poison;         // race check: NaN-fill what a step writes before it runs
   bool two;            // two steps per launch (k_step2) from even steps
   int popsel, d2sel;   // which population copy is current; lag-field swap
@@ -1474,7 +1477,7 @@ bool env_flag(const char* name) {
 
 int setup_cavity(mclbm_cavity* c) {
   derive(c->cfg, c->D);
-  c->L = make_layout(c->cfg, c->in_batch);
+  c->L = make_layout(c->cfg, c->in_batch, c->pad_planes);
   c->P = make_params(c->cfg, c->D, c->L);
   int bx = c->cfg.block_x, by = c->cfg.block_y;
   // Default workgroup: 256 x 1 from 256 columns on; with 16-bit storage
@@ -1748,20 +1751,40 @@ namespace {
 
 constexpr int kCkptVersion = 2;
 
+// A section of the file: `bytes` in `rows` equal rows, which lie `pitch`
+// bytes apart in device memory.  The file holds the planes without the pad
+// between them (px * ny elements each), so a checkpoint does not depend on
+// the plane pad of the cavity that wrote it.
 struct CkptSection {
   const char* name;
   size_t off, bytes;
+  size_t rows, pitch;
 };
 
 std::vector<CkptSection> ckpt_sections(const mclbm_cavity* c) {
   const long long nn = (long long)c->cfg.nx * c->cfg.ny;
+  const size_t lp = (size_t)c->L.px * c->cfg.ny;  // elements of a plane without its pad
+  const size_t sb = storage_bytes(c->cfg.storage);
+  const size_t np = (size_t)9 * c->P.nl;
   return {
-      {"populations", c->pop_off(c->popsel), pop_bytes(c->cfg, c->L.plane)},
-      {"lag_field_0", c->d2_off(0), (size_t)c->L.plane * sizeof(float2)},
-      {"lag_field_1", c->d2_off(1), (size_t)c->L.plane * sizeof(float2)},
-      {"side_buffer", c->L.off_d5, (size_t)6 * (c->P.nl - 2) * c->L.px * sizeof(float)},
-      {"residual_snapshot", c->L.off_snap, (size_t)3 * nn * sizeof(double)},
+      {"populations", c->pop_off(c->popsel), np * lp * sb, np, (size_t)c->L.plane * sb},
+      {"lag_field_0", c->d2_off(0), lp * sizeof(float2), 1, 0},
+      {"lag_field_1", c->d2_off(1), lp * sizeof(float2), 1, 0},
+      {"side_buffer", c->L.off_d5, (size_t)6 * (c->P.nl - 2) * c->L.px * sizeof(float), 1, 0},
+      {"residual_snapshot", c->L.off_snap, (size_t)3 * nn * sizeof(double), 1, 0},
   };
+}
+
+// Copies of one section between the device and the host (sync).
+hipError_t ckpt_to_host(const mclbm_cavity* c, const CkptSection& sc, void* host) {
+  if (sc.rows <= 1) return hipMemcpy(host, c->base + sc.off, sc.bytes, hipMemcpyDeviceToHost);
+  const size_t w = sc.bytes / sc.rows;
+  return hipMemcpy2D(host, w, c->base + sc.off, sc.pitch, w, sc.rows, hipMemcpyDeviceToHost);
+}
+hipError_t ckpt_to_device(mclbm_cavity* c, const CkptSection& sc, const void* host) {
+  if (sc.rows <= 1) return hipMemcpy(c->base + sc.off, host, sc.bytes, hipMemcpyHostToDevice);
+  const size_t w = sc.bytes / sc.rows;
+  return hipMemcpy2D(c->base + sc.off, sc.pitch, host, w, w, sc.rows, hipMemcpyHostToDevice);
 }
 
 std::string hex_of(const void* p, size_t n) {
@@ -2240,7 +2263,7 @@ int mclbm_checkpoint(mclbm_cavity* c, const char* path) {
     if (!ok) break;
     host.resize(sc.bytes);
     if (sc.bytes) {
-      hipError_t e = hipMemcpy(host.data(), c->base + sc.off, sc.bytes, hipMemcpyDeviceToHost);
+      hipError_t e = ckpt_to_host(c, sc, host.data());
       if (e != hipSuccess) {
         std::fclose(fp);
         return hip_fail(e, "checkpoint: hipMemcpy");
@@ -2286,7 +2309,7 @@ int mclbm_restore(mclbm_cavity* c, const char* path) {
   std::fclose(fp);
   HIP_TRY(hipStreamSynchronize(c->stream));
   for (size_t k = 0; k < secs.size(); ++k)
-    if (secs[k].bytes) HIP_TRY(hipMemcpy(c->base + secs[k].off, data[k].data(), secs[k].bytes, hipMemcpyHostToDevice));
+    if (secs[k].bytes) HIP_TRY(ckpt_to_device(c, secs[k], data[k].data()));
   c->t = t;
   ++c->epoch;
   return MCLBM_OK;
@@ -2402,6 +2425,7 @@ struct BatchLayout {
   size_t off_red, off_rlist, off_rtiles, off_rout;
   int tile_cap, tile_cap2, rtile_cap;
   bool two;
+  bool pad;  // members' planes padded: the batch's working set streams from HBM
   std::vector<size_t> off_cav;
 };
 
@@ -2428,6 +2452,7 @@ int batch_layout(const mclbm_config* cfgs, int n, BatchLayout& B) {
   int n1 = 0, n2 = 0;    // cavities asking for one or for two steps per launch
   bool possible = true;  // every cavity can take two steps per launch
   double used = 0.0;     // nodes weighted by the share of strip lanes they fill
+  double streaming = 0.0;  // FP32 population and lag-field bytes of all members
   for (int k = 0; k < n; ++k) {
     int rc = validate(&cfgs[k]);
     if (rc) return fail(rc, "cavity " + std::to_string(k) + ": " + g_err);
@@ -2440,6 +2465,7 @@ int batch_layout(const mclbm_config* cfgs, int n, BatchLayout& B) {
     const long long nn = (long long)cfgs[k].nx * cfgs[k].ny;
     nodes += nn;
     used += (double)nn * cfgs[k].nx / (double)(kStrip2 * strips2_of(cfgs[k]));
+    streaming += (double)((cfgs[k].nx + 63) / 64 * 64) * cfgs[k].ny * (27 * 4 + 2 * 8);
     int m = 0;
     for (const auto& sh : kShapes) m = std::max(m, tiles_of(cfgs[k].nx, cfgs[k].ny, sh[0], sh[1]));
     cap += m;
@@ -2450,6 +2476,12 @@ int batch_layout(const mclbm_config* cfgs, int n, BatchLayout& B) {
                 "a batch runs every cavity one step per launch, or every cavity two (steps_per_launch 2 for all)");
   if (cap > (1LL << 30) || rcap > (1LL << 30)) return fail(MCLBM_EINVAL, "batch too large");
   B.rtile_cap = (int)rcap;
+  // Members of a batch whose working set streams from HBM (counted in FP32,
+  // so that batches of one set of cavities in different storage types lay
+  // them out alike) pad their planes like single cavities from 2^20 nodes:
+  // the 256-cavity sweep (64^2 to 512^2 members, 6 GB) +3 % with two steps
+  // per launch.
+  B.pad = streaming > (double)kStreamingBytes;
   // Automatic (every cavity 0): two steps per launch for FP32 batches from
   // 2^20 nodes whose cavities fill at least 60 % of their strips' lanes
   // (measured: 1.06-1.51x from 1 M to 17 M nodes of 128- to 512-column
@@ -2483,7 +2515,7 @@ int batch_layout(const mclbm_config* cfgs, int n, BatchLayout& B) {
   B.off_cav.resize(n);
   for (int k = 0; k < n; ++k) {
     B.off_cav[k] = off;
-    off = align_up(off + make_layout(member_config(cfgs[k], B.two), true).total);
+    off = align_up(off + make_layout(member_config(cfgs[k], B.two), true, B.pad).total);
   }
   B.total = off;
   return MCLBM_OK;
@@ -2813,7 +2845,8 @@ int mclbm_batch_create(const mclbm_config* cfgs, int32_t n, const double* const*
     if (xis && xis[k]) c->xi.assign(xis[k], xis[k] + (size_t)cfgs[k].nx * cfgs[k].ny);
     c->stream = b->stream;
     c->base = b->base + B.off_cav[k];
-    c->bytes = make_layout(c->cfg, true).total;
+    c->pad_planes = B.pad;
+    c->bytes = make_layout(c->cfg, true, B.pad).total;
     c->in_batch = true;
     c->batch_clock = &b->t;
     setup_cavity(c);

@@ -97,6 +97,20 @@ def test_plane_pad_sizes():
             os.environ["MCLBM_PLANE_PAD"] = old
 
 
+def test_streaming_batch_pads_its_members():
+    """A batch pads its members' planes (4160 elements, both population
+    copies and the lag fields) once the FP32 populations and lag fields of
+    all its members exceed 160 MiB: five 512^2 cavities (156 MiB) stay
+    unpadded, six (186 MiB) are padded."""
+    def extra(n):
+        cfgs = [dict(nx=512, ny=512, Ra=1e5 * (1 + k), phi0=0.03, dp_nm=50.0, steps_per_launch=2) for k in range(n)]
+        arr = (mc.Config * n)(*[mc.make_config(**c) for c in cfgs])
+        return mc.lib().mclbm_batch_device_bytes(arr, n) - sum(mc.device_bytes(**c) for c in cfgs)
+    tables5, padded6 = extra(5), extra(6)
+    assert tables5 < 1 << 20
+    assert padded6 >= 6 * (2 * 27 * 4 + 2 * 8) * 4160
+
+
 def test_two_steps_per_launch_sizes_and_limits():
     """Two steps per launch keep a second population copy: on request, and
     by default for FP32 storage from 2^20 nodes and 256 columns on (below

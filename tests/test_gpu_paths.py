@@ -94,6 +94,58 @@ def test_plane_pad_is_bitwise_neutral(cfg):
         c.copy_state_from(ref)
 
 
+@pytest.mark.parametrize("pads", [(4160, 0), (0, 4160), (64, 4160)])
+def test_checkpoint_restores_across_plane_pads(tmp_path, pads):
+    """A checkpoint holds the population planes and lag fields without the
+    pad between them: one written by a cavity with one pad restores into a
+    cavity with another, and both runs continue bitwise alike (one and two
+    steps per launch)."""
+    for spl in (1, 2):
+        cfg = dict(nx=67, ny=53, Ra=1e5, phi0=0.03, dp_nm=40.0, steps_per_launch=spl)
+        xi = inputs.phi_perturbation(12, cfg["nx"], cfg["ny"])
+        with _knobs(plane_pad=pads[0]):
+            a = mc.Cavity(xi=xi, **cfg)
+        with _knobs(plane_pad=pads[1]):
+            b = mc.Cavity(xi=xi, **cfg)
+        a.step(102)
+        path = tmp_path / f"pad{spl}.ckpt"
+        a.checkpoint(path)
+        b.restore(path)
+        a.step(60)
+        b.step(60)
+        assert np.array_equal(a.populations(), b.populations()), (pads, spl)
+        assert a.nusselt() == b.nusselt()
+
+
+def test_streaming_batch_pads_its_members_bitwise():
+    """A batch whose FP32 working set exceeds 160 MiB (here six 512^2
+    cavities, 195 MB of populations and lag fields) pads its members' planes,
+    also below 2^20 nodes; the members still step bitwise like single
+    cavities, and a member's checkpoint restores into an unpadded single
+    cavity."""
+    cfgs = [dict(nx=512, ny=512, Ra=1e5 * (1 + k), phi0=0.03, dp_nm=50.0, steps_per_launch=2) for k in range(6)]
+    xis = [inputs.phi_perturbation(60 + k, 512, 512) for k in range(6)]
+    plain = sum(mc.device_bytes(**c) for c in cfgs)
+    arr = (mc.Config * len(cfgs))(*[mc.make_config(**c) for c in cfgs])
+    assert mc.lib().mclbm_batch_device_bytes(arr, len(cfgs)) >= plain + 6 * 27 * 4 * 4160  # members padded
+    b = mc.Batch(cfgs, xis=xis)
+    b.step(20)
+    single = mc.Cavity(xi=xis[2], **cfgs[2])
+    single.step(20)
+    assert np.array_equal(b.members[2].populations(), single.populations())
+    path = os.path.join(os.environ.get("TMPDIR", "/tmp"), f"stream_member_{os.getpid()}.ckpt")
+    try:
+        b.members[2].checkpoint(path)
+        c = mc.Cavity(xi=xis[2], **cfgs[2])
+        c.restore(path)
+    finally:
+        if os.path.exists(path):
+            os.remove(path)
+    b.step(10)
+    c.step(10)
+    assert np.array_equal(c.populations(), b.members[2].populations())
+
+
 def test_16bit_default_launch_shape_at_large_size_is_bitwise():
     """From 2^21 nodes on, 16-bit storage defaults to 64 x 1 workgroups;
     the results equal those of 256 x 1 bit for bit (same node update, other
