@@ -484,6 +484,7 @@ def main():
     copy_gbps = copy_bandwidth(torch, mc)
     secondary = None
     streaming = None
+    above_2gib = None
     if not a.no_secondary:
         del cav
         torch.cuda.empty_cache()
@@ -517,6 +518,9 @@ def main():
         secondary["one_step_per_launch"] = measure("cavity2048_ra1e6", 200, steps_per_launch=1)
         streaming = measure("cavity4096_ra1e6", 50)    # 1.8 GB: streams from HBM
         streaming["one_step_per_launch"] = measure("cavity4096_ra1e6", 50, steps_per_launch=1)
+        # 2.29 GB of populations: 64-bit element offsets in both schedules
+        above_2gib = measure("cavity4608_ra1e6", 40)
+        above_2gib["one_step_per_launch"] = measure("cavity4608_ra1e6", 40, steps_per_launch=1)
     batched = None
     if a.batch > 0 and not a.no_secondary:
         batched = batch_measure(torch, mc, inputs, a.batch)
@@ -553,6 +557,7 @@ def main():
         "reductions": red,
         "larger_than_llc": secondary,
         "hbm_streaming": streaming,
+        "above_2gib": above_2gib,
         "batched_sweep": batched,
         "small_batches": small,
         "time_to_steady": warm,

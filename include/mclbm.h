@@ -144,10 +144,14 @@ typedef struct {
                               population copy into a second one (device
                               bytes grow by one population array; 1.25x
                               instead of 2x the bytes of one step, the same
-                              arithmetic); one thermal lattice and
-                              populations below 2 GiB only
+                              arithmetic); one thermal lattice only, and
+                              in a batch populations below 2 GiB per cavity
                               (MCLBM_EUNSUPPORTED on request otherwise; the
-                              automatic choice falls back to 1).  A batch
+                              automatic choice falls back to 1).  Above
+                              2 GiB of populations the single cavity's
+                              launches take 64-bit element offsets; the
+                              two copies then need twice those bytes of
+                              device memory (set 1 where they do not fit).  A batch
                               takes one schedule for all its cavities: 2
                               if every cavity asks for 2 (a batch mixing
                               2 with 0 or 1 is rejected), or if every
@@ -169,7 +173,8 @@ typedef struct mclbm_cavity mclbm_cavity; /* opaque host-side handle */
  *   MCLBM_LOG=debug      one line on stderr per configuration with the
  *                        lattice constants and stability numbers
  *   MCLBM_INDEX64=1      64-bit element offsets (otherwise above 2 GiB of
- *                        populations; then one step per launch)
+ *                        populations), in both schedules of a single
+ *                        cavity; a batch then steps one step per launch
  *   MCLBM_STREAMING=1    non-temporal population access of single steps
  *                        (otherwise above 160 MiB)
  *   MCLBM_POISON=1       race check: NaN-fill, before each launch, what it

@@ -214,12 +214,11 @@ __device__ __forceinline__ float pull_x(float v, int i) {
 }
 
 // One tile (strip, band segment seg) of one cavity, by one 64-lane wave.
-template <class S>
+template <class S, class I>
 __device__ __forceinline__ void step2_tile(const StepParams& P, const typename S::T* __restrict__ popA,
                                            typename S::T* __restrict__ popB,
                                            const float2* __restrict__ d2p, float2* __restrict__ d2o,
                                            int strip, int seg, int band) {
-  using I = uint32_t;
   constexpr int UP[3] = {2, 5, 6}, AL[3] = {0, 1, 3}, DN[3] = {4, 7, 8};
   // What a row sends up waits two iterations: a ring of three rows in LDS,
   // one column per lane (each lane reads back only what it wrote).  The
@@ -403,13 +402,13 @@ __device__ __forceinline__ void step2_tile(const StepParams& P, const typename S
   }
 }
 
-template <class S>
+template <class S, class I>
 __global__ __launch_bounds__(64) void k_step2(StepParams P, const typename S::T* __restrict__ popA,
                                               typename S::T* __restrict__ popB,
                                               const float2* __restrict__ d2p, float2* __restrict__ d2o,
                                               int strips, int band, int mix) {
   const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);
-  step2_tile<S>(P, popA, popB, d2p, d2o, (int)(tile % (unsigned)strips),
+  step2_tile<S, I>(P, popA, popB, d2p, d2o, (int)(tile % (unsigned)strips),
                 band_of_tile((int)(tile / (unsigned)strips), (P.ny + band - 1) / band, mix), band);
 }
 
@@ -464,7 +463,7 @@ __global__ __launch_bounds__(64) void k_step2_batch(const CavDesc* __restrict__ 
   if (tr.x < 0) return;  // padding entry
   const CavDesc& C = cavs[tr.x];
   using T = typename S::T;
-  step2_tile<S>(C.P, reinterpret_cast<const T*>(C.pop[flip]), reinterpret_cast<T*>(C.pop[flip ^ 1]),
+  step2_tile<S, uint32_t>(C.P, reinterpret_cast<const T*>(C.pop[flip]), reinterpret_cast<T*>(C.pop[flip ^ 1]),
                 C.d2[1 ^ flip], C.d2[flip], tr.y % C.strips2, tr.y / C.strips2, C.band2);
 }
 
@@ -1048,16 +1047,20 @@ size_t pop_bytes(const mclbm_config& c, long long plane) {
 }
 size_t pop_bytes(const mclbm_config& c) { return pop_bytes(c, plane_of(c)); }
 
-// Two time steps per launch (k_step2): one thermal lattice and a population
-// array below 2 GiB (32-bit buffer offsets) only.  By default for FP32
-// storage from 2^20 nodes and 256 columns on, where it was measured faster
-// than one step per launch (1024^2 +8 %, 2048^2 +18 %, 4096^2 +44 %; slower
-// at 512^2, and with 16-bit storage at every size).
-bool two_step_possible(const mclbm_config& c) {
-  return lattices(c) == 3 && pop_bytes(c) < ((size_t)1 << 31);
+// Two time steps per launch (k_step2): one thermal lattice; population
+// arrays of 2 GiB and more take 64-bit element offsets (4608^2: 32.4 GLUPS
+// against 20.8 with one step per launch; at 4096^2 the 64-bit offsets cost
+// 7 %).  By default for FP32 storage from 2^20 nodes and 256 columns on,
+// where it was measured faster than one step per launch (1024^2 +8 %,
+// 2048^2 +18 %, 4096^2 +44 % before the plane pad; slower at 512^2, and
+// with 16-bit storage at every size).  The batch kernel takes 32-bit
+// offsets only: batches need every member below 2 GiB of populations.
+bool two_step_possible(const mclbm_config& c) { return lattices(c) == 3; }
+bool two_step_batchable(const mclbm_config& c) {
+  return two_step_possible(c) && pop_bytes(c) < ((size_t)1 << 31);
 }
 bool two_step(const mclbm_config& c, bool batch_member) {
-  if (!two_step_possible(c)) return false;
+  if (!(batch_member ? two_step_batchable(c) : two_step_possible(c))) return false;
   if (c.steps_per_launch != 0) return c.steps_per_launch == 2;
   if (batch_member) return false;  // a batch writes its own choice (member_config)
   return c.storage == MCLBM_FP32S && (long long)c.nx * c.ny >= (1LL << 20) && c.nx >= 256;
@@ -1167,7 +1170,7 @@ int validate(const mclbm_config* c) {
   if (c->steps_per_launch < 0 || c->steps_per_launch > 2)
     return fail(MCLBM_EINVAL, "steps_per_launch must be 0, 1 or 2");
   if (c->steps_per_launch == 2 && !two_step_possible(*c))
-    return fail(MCLBM_EUNSUPPORTED, "two steps per launch need one thermal lattice and populations below 2 GiB");
+    return fail(MCLBM_EUNSUPPORTED, "two steps per launch need one thermal lattice");
   const int bx = c->block_x == 0 ? 64 : c->block_x;
   const int by = c->block_y == 0 ? 1 : c->block_y;
   if (!(bx == 32 || bx == 64 || bx == 128 || bx == 256) || by < 1 ||
@@ -1500,7 +1503,7 @@ int setup_cavity(mclbm_cavity* c) {
   if (env_flag("MCLBM_STREAMING")) c->nt = true;
   c->poison = env_flag("MCLBM_POISON");
   // two steps per launch: strips of kStrip2 columns, bands of band2 rows
-  c->two = two_step(c->cfg, c->in_batch) && c->idx32;
+  c->two = two_step(c->cfg, c->in_batch) && (c->idx32 || !c->in_batch);
   c->strips2 = strips2_of(c->cfg);
   c->band2 = band2_of(c->cfg);
   c->mix2 = mix2_of(c->cfg);
@@ -1541,7 +1544,7 @@ int launch_step(mclbm_cavity* c) {
 // one of t - 1's partner, and both selections flip.
 template <class K>
 int launch_step2(mclbm_cavity* c) {
-  if constexpr (K::NL == 3 && sizeof(typename K::I) == 4) {
+  if constexpr (K::NL == 3) {
     // cached loads and stores at every size: a wave's 64 lanes start one
     // column before its strip, so its row loads straddle the cache lines it
     // shares with the neighbouring strips (and bands), which then hit in L2;
@@ -1563,15 +1566,15 @@ int launch_step2(mclbm_cavity* c) {
       int r = launch_check("k_poison");
       if (r) return r;
     }
-    k_step2<S><<<c->nblocks2, 64, 0, c->stream>>>(c->P, src, dst, c->d2(1), c->d2(0), c->strips2, c->band2,
-                                                  c->mix2);
+    k_step2<S, typename K::I><<<c->nblocks2, 64, 0, c->stream>>>(c->P, src, dst, c->d2(1), c->d2(0), c->strips2,
+                                                                 c->band2, c->mix2);
     int r = launch_check("k_step2");
     if (r) return r;
     c->popsel ^= 1;
     c->d2sel ^= 1;
     return MCLBM_OK;
   } else {
-    return fail(MCLBM_EUNSUPPORTED, "two steps per launch: one thermal lattice and 32-bit offsets only");
+    return fail(MCLBM_EUNSUPPORTED, "two steps per launch: one thermal lattice only");
   }
 }
 
@@ -2461,7 +2464,10 @@ int batch_layout(const mclbm_config* cfgs, int n, BatchLayout& B) {
       return fail(MCLBM_EUNSUPPORTED, "cavity " + std::to_string(k) + ": batches take one thermal lattice");
     n1 += cfgs[k].steps_per_launch == 1;
     n2 += cfgs[k].steps_per_launch == 2;
-    possible = possible && two_step_possible(cfgs[k]) && cfgs[k].storage == MCLBM_FP32S;
+    possible = possible && two_step_batchable(cfgs[k]) && cfgs[k].storage == MCLBM_FP32S;
+    if (cfgs[k].steps_per_launch == 2 && !two_step_batchable(cfgs[k]))
+      return fail(MCLBM_EUNSUPPORTED,
+                  "cavity " + std::to_string(k) + ": two steps per launch in a batch need populations below 2 GiB");
     const long long nn = (long long)cfgs[k].nx * cfgs[k].ny;
     nodes += nn;
     used += (double)nn * cfgs[k].nx / (double)(kStrip2 * strips2_of(cfgs[k]));

@@ -57,6 +57,10 @@ WORKLOADS = {
     # every step streams from HBM (2048^2, 450 MB, is still partly cached)
     "cavity4096_ra1e6": dict(nx=4096, ny=4096, Ra=1e6, Pr=6.2, phi0=0.04, dp_nm=30.0,
                              tau_f=0.8, seed=7),
+    # 2.29 GB of populations (above 2 GiB: 64-bit element offsets); the
+    # stored 2000-step oracle samples of this cavity use seed 4
+    "cavity4608_ra1e6": dict(nx=4608, ny=4608, Ra=1e6, Pr=6.2, phi0=0.04, dp_nm=30.0,
+                             tau_f=0.8, seed=4),
 }
 
 

@@ -113,8 +113,9 @@ def test_streaming_batch_pads_its_members():
 
 def test_two_steps_per_launch_sizes_and_limits():
     """Two steps per launch keep a second population copy: on request, and
-    by default for FP32 storage from 2^20 nodes and 256 columns on (below
-    2 GiB of populations); one thermal lattice only."""
+    by default for FP32 storage from 2^20 nodes and 256 columns on (above
+    2 GiB of populations with 64-bit offsets); one thermal lattice only;
+    in a batch every cavity below 2 GiB of populations."""
     pop64 = 27 * 4 * 64 * 64
     assert mc.device_bytes(nx=64, ny=64, steps_per_launch=2) == mc.device_bytes(nx=64, ny=64) + pop64
     assert mc.device_bytes(nx=64, ny=64, steps_per_launch=1) == mc.device_bytes(nx=64, ny=64)
@@ -124,14 +125,22 @@ def test_two_steps_per_launch_sizes_and_limits():
     assert mc.device_bytes(nx=2048, ny=2048) == mc.device_bytes(nx=2048, ny=2048, steps_per_launch=2) == one + pop2k
     assert mc.device_bytes(nx=1024, ny=1024) > mc.device_bytes(nx=1024, ny=1024, steps_per_launch=1)
     # automatic: one step below 2^20 nodes, for 16-bit storage, narrow
-    # cavities and populations of 2 GiB and more
+    # cavities and two thermal lattices
     for kw in (dict(nx=512, ny=512), dict(nx=2048, ny=2048, storage=mc.FP16S), dict(nx=128, ny=16384),
-               dict(nx=4608, ny=4608), dict(nx=2048, ny=2048, thermal_lattices=2)):
+               dict(nx=2048, ny=2048, thermal_lattices=2)):
         assert mc.device_bytes(**kw) == mc.device_bytes(steps_per_launch=1, **kw), kw
-    for bad in (dict(thermal_lattices=2), dict(nx=4608, ny=4608)):
-        with pytest.raises(mc.MclbmError) as e:
-            mc.derive_constants(steps_per_launch=2, **bad)
-        assert e.value.code == mc.EUNSUPPORTED
+    # populations above 2 GiB: two steps per launch by default as well
+    pop46 = 27 * 4 * (4608 * 4608 + 4160)
+    assert pop46 > 1 << 31
+    assert mc.device_bytes(nx=4608, ny=4608) == mc.device_bytes(nx=4608, ny=4608, steps_per_launch=1) + pop46
+    with pytest.raises(mc.MclbmError) as e:
+        mc.derive_constants(steps_per_launch=2, thermal_lattices=2)
+    assert e.value.code == mc.EUNSUPPORTED
+    # a batch member of 2 GiB or more cannot take two steps per launch
+    big = dict(nx=4608, ny=4608, steps_per_launch=2)
+    assert _batch_bytes([big, dict(nx=64, ny=64, steps_per_launch=2)]) == 0
+    assert "below 2 GiB" in mc.lib().mclbm_last_error().decode()
+    assert _batch_bytes([dict(nx=4608, ny=4608), dict(nx=64, ny=64)]) > 0  # automatic: one step
 
 
 def _batch_bytes(cfgs):

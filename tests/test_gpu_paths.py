@@ -52,6 +52,7 @@ def _cavity(cfg, xi, steps, **knobs):
     (dict(nx=37, ny=29, Ra=5e4, phi0=0.03, dp_nm=40.0), 1e-5),
     (dict(nx=37, ny=29, Ra=5e4, phi0=0.03, dp_nm=40.0, thermal_lattices=2), 1e-5),
     (dict(nx=40, ny=33, Ra=1e5, phi0=0.02, dp_nm=30.0, storage=mc.FP16S), 6e-3),
+    (dict(nx=300, ny=45, Ra=5e4, phi0=0.03, dp_nm=40.0, steps_per_launch=2), 1e-5),
 ])
 def test_index64_and_streaming_paths_match_oracle(cfg, tol):
     """Each variant is its own kernel instantiation with the same arithmetic
@@ -59,7 +60,7 @@ def test_index64_and_streaming_paths_match_oracle(cfg, tol):
     path's bits; each is also held to the parity bar against the oracle
     (for FP16 storage its error bound)."""
     xi = inputs.phi_perturbation(101, cfg["nx"], cfg["ny"])
-    o = oracle.Oracle(xi=xi, **{k: v for k, v in cfg.items() if k != "storage"})
+    o = oracle.Oracle(xi=xi, **{k: v for k, v in cfg.items() if k not in ("storage", "steps_per_launch")})
     o.step(1001)
     mo = o.moments()
     ref = _cavity(cfg, xi, 1001).populations()
@@ -181,9 +182,11 @@ GOLDEN_4608 = os.path.join(os.path.dirname(__file__), "golden", "cavity4608_ra1e
 
 
 @pytest.mark.skipif(not os.path.exists(GOLDEN_4608), reason="oracle reference not written yet")
-def test_cavity_above_2gib_matches_oracle():
+@pytest.mark.parametrize("spl", [0, 1])
+def test_cavity_above_2gib_matches_oracle(spl):
     """4608^2 FP32: 2.29 GB of populations, so element offsets need 64 bits
-    and the accesses stream past the caches.  After 2000 steps, all nine
+    and single steps stream past the caches; by default two steps per
+    launch (64-bit k_step2), and one step per launch.  After 2000 steps, all nine
     moments at 256 sampled nodes (walls, their neighbours, interior) and the
     Nusselt numbers against the oracle's values
     (``golden/cavity4608_ra1e6_sampled.txt``, written by
@@ -201,12 +204,14 @@ def test_cavity_above_2gib_matches_oracle():
     cfg = dict(nx=n, ny=n, Ra=1e6, phi0=0.04, dp_nm=30.0)
     assert 27 * 4 * n * n > (1 << 31)
     xi = inputs.phi_perturbation(4, n, n)
-    c = mc.Cavity(xi=xi, **cfg)
+    c = mc.Cavity(xi=xi, steps_per_launch=spl, **cfg)
+    if spl == 0:  # the default at this size: two steps per launch
+        assert mc.device_bytes(**cfg) > mc.device_bytes(steps_per_launch=1, **cfg) + (1 << 31)
     phi0 = c.moments("phi")["phi"].sum()
     c.step(g["steps"])
     m = c.moments(MOMENTS)
     err = sampled_errors(m, g)
-    print(f"4608^2 t={g['steps']} sampled", {k: f"{v:.2e}" for k, v in err.items()}, flush=True)
+    print(f"4608^2 spl {spl} t={g['steps']} sampled", {k: f"{v:.2e}" for k, v in err.items()}, flush=True)
     for f, v in err.items():
         assert v <= (MOMENT_TOL if f in ("rho_f", "phi", "theta") else 1.5e-4), (f, v)
     assert_nusselt(c.nusselt(), g["nu"], label="4608^2")
